@@ -1,0 +1,496 @@
+/*
+ * Plain CPU oracle for point-cloud tomography (Yang et al., "Efficient Global
+ * Navigational Planning in 3D Structures based on Point Cloud Tomography").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library; neither includes
+ * or links the other.
+ *
+ * Everything is written as plain loops in the order the paper states it:
+ *   - tomogram construction: Algorithm 1, construction part, literally
+ *     (every point against every plane, O(points x slices)), in FP32, which
+ *     is exact because only max/min and comparisons are involved;
+ *   - traversability: Eqs. (1)-(5) per cell in FP64, then the inflation
+ *     of Eq. (6) as a direct 2-D sliding-window weighted max in FP64;
+ *   - simplification: the sequential slice test of Sec. III-C with the
+ *     unique-grid conditions of Eqs. (8)-(9);
+ *   - trajectory cost sampling and every adjoint, in FP64.
+ *
+ * Readings of points where the paper is silent or ambiguous are stated at
+ * each function.  Build: gcc -O2 -fno-fast-math -ffp-contract=off [-fopenmp].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    float x0, y0, res;
+    int32_t nx, ny;
+    float slice_dz;
+} o_grid;
+
+typedef struct {
+    float d_min, d_ref, theta_b, theta_s, theta_p, c_barrier, alpha_d, alpha_b, alpha_s, d_inf, d_sm;
+    int32_t patch_radius;
+} o_robot;
+
+int o_omp_threads(void) {
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III-A: rasterize.  The paper names the step but not the rule.
+ * Reading: cell (i, j) of a grid with origin (x0, y0) and resolution r holds
+ * the points with floor((x - x0) / r) = i and floor((y - y0) / r) = j, where
+ * the subtraction and the division are single correctly rounded FP32
+ * operations.  Points outside [0, nx) x [0, ny) are not part of the map. */
+static int o_rasterize(float x, float y, const o_grid* g, int* ix, int* iy) {
+    float qx = (x - g->x0) / g->res;
+    float qy = (y - g->y0) / g->res;
+    if (!(qx >= 0.0f && qx < (float)g->nx)) return 0;
+    if (!(qy >= 0.0f && qy < (float)g->ny)) return 0;
+    *ix = (int)floorf(qx);
+    *iy = (int)floorf(qy);
+    return 1;
+}
+
+static int o_point_ok(const float* p) {
+    return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
+}
+
+/* Algorithm 1, first line: the lowest point height.  Reading: taken over the
+ * points that belong to the map (finite and inside the grid); the highest
+ * height is taken over the same set because the plane count depends on it.
+ * Returns the number of such points. */
+int64_t o_extent(const float* xyz, int64_t n, const o_grid* g, float* zmin, float* zmax) {
+    float lo = INFINITY, hi = -INFINITY;
+    int64_t used = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        const float* p = xyz + 3 * u;
+        int ix, iy;
+        if (!o_point_ok(p) || !o_rasterize(p[0], p[1], g, &ix, &iy)) continue;
+        float z = p[2] + 0.0f; /* -0 becomes +0 */
+        if (z < lo) lo = z;
+        if (z > hi) hi = z;
+        ++used;
+    }
+    *zmin = lo;
+    *zmax = hi;
+    return used;
+}
+
+/* Sec. III-A: planes spaced d_s apart, the first one d_s above the lowest
+ * point, as many as needed for the last one to lie above the highest point.
+ * Plane k (k = 0 .. N-1) sits at z_min + (k + 1) d_s, evaluated as one FP32
+ * multiply followed by one FP32 add.  Returns N, -1 if two consecutive
+ * planes coincide in FP32, -2 if more than `cap` planes would be needed. */
+int o_planes(float zmin, float zmax, float ds, int cap, float* h) {
+    for (int k = 0; k < cap; ++k) {
+        float step = (float)(k + 1) * ds;
+        float hk = zmin + step;
+        h[k] = hk;
+        if (k > 0 && !(hk > h[k - 1])) return -1;
+        if (hk > zmax) return k + 1;
+    }
+    return -2;
+}
+
+/* Algorithm 1, construction loop, literally: every point is compared with
+ * every plane.  The lower group of plane k (z at or below the plane) sets the
+ * ground elevation by max, the upper group (z above the plane) sets the
+ * ceiling by min.  The printed algorithm swaps the two inequalities; the text
+ * of Sec. III-A (lower group projected up to the ground layer, upper group
+ * down to the ceiling) decides, and the equality case stays with the ground.
+ * Empty cells are invalid: ground -inf, ceiling +inf, ids -1.  The ids record
+ * which point gives each value; on equal heights the lowest index wins.
+ * Layout of every [N][ny][nx] array: x fastest. */
+void o_build(const float* xyz, int64_t n, const o_grid* g, const float* h, int N,
+             float* eG, float* eC, int32_t* aG, int32_t* aC) {
+    const int64_t plane = (int64_t)g->nx * g->ny;
+    for (int64_t i = 0; i < plane * N; ++i) {
+        eG[i] = -INFINITY;
+        eC[i] = INFINITY;
+        if (aG) aG[i] = -1;
+        if (aC) aC[i] = -1;
+    }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < N; ++k) {
+        for (int64_t u = 0; u < n; ++u) {
+            const float* p = xyz + 3 * u;
+            int ix, iy;
+            if (!o_point_ok(p) || !o_rasterize(p[0], p[1], g, &ix, &iy)) continue;
+            float z = p[2] + 0.0f;
+            int64_t c = (int64_t)k * plane + (int64_t)iy * g->nx + ix;
+            if (z <= h[k]) {
+                if (z > eG[c]) { eG[c] = z; if (aG) aG[c] = (int32_t)u; }
+            } else {
+                if (z < eC[c]) { eC[c] = z; if (aC) aC[c] = (int32_t)u; }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III-B, traversability of one slice, in FP64. */
+
+static double o_g(const float* eG, int nx, int ny, int x, int y) {
+    if (x < 0 || y < 0 || x >= nx || y >= ny) return -INFINITY;
+    return (double)eG[(int64_t)y * nx + x];
+}
+
+/* Eq. (2): central finite differences g^x = (e(x+1) - e(x-1)) / 2r and
+ * likewise g^y; m^xy = max(|g^x|, |g^y|), m^grad = |g|.  Reading: a stencil
+ * that needs a neighbour outside the grid or without ground has no slope
+ * estimate and counts as infinitely steep (both magnitudes +inf). */
+static void o_slope(const float* eG, int nx, int ny, double res, int x, int y,
+                    double* gx, double* gy, double* mxy, double* mgrad) {
+    double l = o_g(eG, nx, ny, x - 1, y), r = o_g(eG, nx, ny, x + 1, y);
+    double d = o_g(eG, nx, ny, x, y - 1), u = o_g(eG, nx, ny, x, y + 1);
+    if (!isfinite(l) || !isfinite(r) || !isfinite(d) || !isfinite(u)) {
+        *gx = *gy = 0.0;
+        *mxy = *mgrad = INFINITY;
+        return;
+    }
+    *gx = (r - l) / (2.0 * res);
+    *gy = (u - d) / (2.0 * res);
+    *mxy = fmax(fabs(*gx), fabs(*gy));
+    *mgrad = sqrt((*gx) * (*gx) + (*gy) * (*gy));
+}
+
+/* Eq. (4): the step test compares the share p_s of gentle neighbours with
+ * theta_p.  Reading: the patch is the (2 r_p + 1)^2 square minus its centre
+ * (r_p = 1 unless the robot says otherwise); neighbours outside the grid or
+ * without ground are not gentle; the denominator is fixed.  p_s > theta_p is
+ * decided in integers as count > floor(theta_p * patch) (FP64 product). */
+static int o_patch_threshold(const o_robot* rb) {
+    int np = (2 * rb->patch_radius + 1) * (2 * rb->patch_radius + 1) - 1;
+    return (int)floor((double)rb->theta_p * (double)np);
+}
+
+typedef struct {
+    double cI, cG, cinit, mxy, mgrad, gx, gy, dI;
+    int gentle, count, branch; /* branch: 0 no ground, 1 barrier, 2 gentle, 3 step, 4 step-barrier */
+} o_cell;
+
+static int o_is_gentle(const float* eG, int nx, int ny, double res, const o_robot* rb, int x, int y) {
+    if (!isfinite(o_g(eG, nx, ny, x, y))) return 0;
+    double gx, gy, mxy, mg;
+    o_slope(eG, nx, ny, res, x, y, &gx, &gy, &mxy, &mg);
+    return mg < (double)rb->theta_s;
+}
+
+/* One cell of Eqs. (1)-(5).  Reading for invalid layers: no ground gives the
+ * barrier cost c^B (nothing to stand on); no ceiling gives an infinite
+ * interval and hence c^I = 0.  Case order of Eq. (3)/(4): barrier test first,
+ * then the gentle test, then the step test. */
+static o_cell o_eval_cell(const float* eG, const float* eC, int nx, int ny, double res,
+                          const o_robot* rb, int x, int y) {
+    o_cell o;
+    memset(&o, 0, sizeof o);
+    const double cB = rb->c_barrier;
+    double G = o_g(eG, nx, ny, x, y);
+    double C = (double)eC[(int64_t)y * nx + x];
+    o_slope(eG, nx, ny, res, x, y, &o.gx, &o.gy, &o.mxy, &o.mgrad);
+    o.gentle = isfinite(G) && o.mgrad < (double)rb->theta_s;
+    if (!isfinite(G)) {
+        o.cinit = cB;
+        o.cI = cB;
+        o.cG = cB;
+        o.dI = NAN;
+        o.branch = 0;
+        return o;
+    }
+    /* Eq. (1) */
+    o.dI = C - G;
+    if (o.dI < (double)rb->d_min) o.cI = cB;
+    else o.cI = fmax(0.0, (double)rb->alpha_d * ((double)rb->d_ref - o.dI));
+    /* Eqs. (3)-(4) */
+    int rp = rb->patch_radius;
+    o.count = 0;
+    for (int dy = -rp; dy <= rp; ++dy)
+        for (int dx = -rp; dx <= rp; ++dx)
+            if (dx || dy) o.count += o_is_gentle(eG, nx, ny, res, rb, x + dx, y + dy);
+    if (o.mxy > (double)rb->theta_b) {
+        o.cG = cB;
+        o.branch = 1;
+    } else if (o.mgrad < (double)rb->theta_s) {
+        double t = o.mgrad / (double)rb->theta_s;
+        o.cG = (double)rb->alpha_s * t * t;
+        o.branch = 2;
+    } else if (o.count > o_patch_threshold(rb)) {
+        double t = o.mxy / (double)rb->theta_b;
+        o.cG = (double)rb->alpha_b * t * t;
+        o.branch = 3;
+    } else {
+        o.cG = cB;
+        o.branch = 4;
+    }
+    /* Eq. (5) */
+    o.cinit = fmin(cB, o.cI + o.cG);
+    return o;
+}
+
+/* Per-cell layers of one slice; every output pointer may be NULL. */
+void o_layers(const float* eG, const float* eC, int nx, int ny, double res, const o_robot* rb,
+              double* cI, double* cG, double* cinit, double* mxy, double* mgrad,
+              uint8_t* gentle, int32_t* branch) {
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            o_cell o = o_eval_cell(eG, eC, nx, ny, res, rb, x, y);
+            int64_t i = (int64_t)y * nx + x;
+            if (cI) cI[i] = o.cI;
+            if (cG) cG[i] = o.cG;
+            if (cinit) cinit[i] = o.cinit;
+            if (mxy) mxy[i] = o.mxy;
+            if (mgrad) mgrad[i] = o.mgrad;
+            if (gentle) gentle[i] = (uint8_t)o.gentle;
+            if (branch) branch[i] = o.branch;
+        }
+}
+
+/* Eq. (6): K(m,n) = max(0, min(1 - (d_mn - d_inf) / (d_sm - r_g), 1)) with
+ * d_mn = r_g sqrt(m^2 + n^2), in FP64 from the float parameters.
+ * Reading: the parameters are decimal values stored as floats, so lattice
+ * distances that equal d_inf or the outer edge in decimal land a few 1e-8
+ * off; weights within 1e-6 of 1 are taken as 1 and within 1e-6 of 0 as 0.
+ * K is written as a (2 rmax + 1)^2 array, row n + rmax, column m + rmax.
+ * Returns the support radius R, -1 if d_sm <= r_g, -2 if the support does
+ * not fit in rmax. */
+int o_kernel(double res, double d_inf, double d_sm, int rmax, double* K) {
+    if (!(d_sm > res)) return -1;
+    int w = 2 * rmax + 1, R = 0;
+    for (int n = -rmax; n <= rmax; ++n)
+        for (int m = -rmax; m <= rmax; ++m) {
+            double d = res * sqrt((double)(m * m + n * n));
+            double k = 1.0 - (d - d_inf) / (d_sm - res);
+            k = fmax(0.0, fmin(k, 1.0));
+            if (k >= 1.0 - 1e-6) k = 1.0;
+            if (k <= 1e-6) k = 0.0;
+            K[(n + rmax) * w + (m + rmax)] = k;
+            if (k > 0.0) {
+                int a = abs(m) > abs(n) ? abs(m) : abs(n);
+                if (a > R) R = a;
+            }
+        }
+    if (R >= rmax) return -2;
+    return R;
+}
+
+/* Sec. III-B, last paragraph: sliding window; each output cell takes the
+ * maximum over the window of kernel weight times initial cost.  Window cells
+ * outside the grid are skipped. */
+void o_inflate(const double* cinit, int nx, int ny, const double* K, int rmax, int R, double* cT) {
+    int w = 2 * rmax + 1;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double best = -INFINITY;
+            for (int n = -R; n <= R; ++n)
+                for (int m = -R; m <= R; ++m) {
+                    double k = K[(n + rmax) * w + (m + rmax)];
+                    int qx = x + m, qy = y + n;
+                    if (k <= 0.0 || qx < 0 || qy < 0 || qx >= nx || qy >= ny) continue;
+                    double v = k * cinit[(int64_t)qy * nx + qx];
+                    if (v > best) best = v;
+                }
+            cT[(int64_t)y * nx + x] = best;
+        }
+}
+
+#define O_RMAX 24
+
+/* Algorithm 1, evaluation lines: c^init per slice, then inflation, for all
+ * N slices.  Returns R, or a negative kernel error. */
+int o_eval(const float* eG, const float* eC, int N, int nx, int ny, double res,
+           const o_robot* rb, double* cT) {
+    double K[(2 * O_RMAX + 1) * (2 * O_RMAX + 1)];
+    int R = o_kernel(res, rb->d_inf, rb->d_sm, O_RMAX, K);
+    if (R < 0) return R;
+    const int64_t plane = (int64_t)nx * ny;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < N; ++k) {
+        double* ci = (double*)malloc(sizeof(double) * plane);
+        o_layers(eG + k * plane, eC + k * plane, nx, ny, res, rb, NULL, NULL, ci, NULL, NULL, NULL, NULL);
+        o_inflate(ci, nx, ny, K, O_RMAX, R, cT + k * plane);
+        free(ci);
+    }
+    return R;
+}
+
+/* Sec. III-C and Eqs. (7)-(9).  A traversable cell (c^T < c^B) of slice k is
+ * unique when it differs from the slice below (higher ground or lower cost)
+ * and from the slice above (the slice above has higher ground, or this cell
+ * has the lower cost).  Slices with no unique cell are removed.
+ * Reading: the text runs the test sequentially - once a slice is removed the
+ * next one is compared with the last slice that was kept - while the slice
+ * above is always the next raw slice; a missing neighbour (before the first
+ * kept slice, after the last slice) counts as different. */
+void o_simplify(const float* eG, const double* cT, int N, int nx, int ny, double cB, uint8_t* keep) {
+    const int64_t plane = (int64_t)nx * ny;
+    int p = -1;
+    for (int k = 0; k < N; ++k) {
+        int found = 0;
+        for (int64_t c = 0; c < plane && !found; ++c) {
+            double ck = cT[k * plane + c];
+            if (!(ck < cB)) continue;
+            double ek = eG[k * plane + c];
+            int lower = p < 0 || ek > (double)eG[p * plane + c] || ck < cT[p * plane + c];
+            int upper = k == N - 1 || (double)eG[(k + 1) * plane + c] > ek || ck < cT[(k + 1) * plane + c];
+            found = lower && upper;
+        }
+        keep[k] = (uint8_t)found;
+        if (found) p = k;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Envelope for comparing an FP32 evaluation with this FP64 one.
+ *
+ * Eqs. (1)-(4) switch between branches at thresholds; an FP32 evaluation
+ * can take the other branch when an operand lies within rounding distance of
+ * its threshold.  A predicate is ambiguous here when its operand is within
+ * tau * max(1, |threshold|) of the threshold.  For each cell the initial cost
+ * is computed under every combination of outcomes of its ambiguous
+ * predicates (the neighbour count of Eq. (4) ranges over the gentle flags of
+ * its ambiguous neighbours) and lo/hi are the extremes; inflation is
+ * monotone in c^init, so inflating lo and hi brackets every admissible
+ * result.  Returns the number of ambiguous cell-slices. */
+
+static int o_near(double v, double th, double tau) {
+    return isfinite(v) && fabs(v - th) <= tau * fmax(1.0, fabs(th));
+}
+
+static double o_cinit_forced(const o_cell* o, const o_robot* rb, int pI, int pB, int pS, int pP) {
+    const double cB = rb->c_barrier;
+    double cI = pI ? cB : fmax(0.0, (double)rb->alpha_d * ((double)rb->d_ref - o->dI));
+    double cG;
+    if (pB) cG = cB;
+    else if (pS) { double t = o->mgrad / (double)rb->theta_s; cG = (double)rb->alpha_s * t * t; }
+    else if (pP) { double t = o->mxy / (double)rb->theta_b; cG = (double)rb->alpha_b * t * t; }
+    else cG = cB;
+    return fmin(cB, cI + cG);
+}
+
+int64_t o_eval_envelope(const float* eG, const float* eC, int N, int nx, int ny, double res,
+                        const o_robot* rb, double tau, double* lo, double* hi) {
+    double K[(2 * O_RMAX + 1) * (2 * O_RMAX + 1)];
+    int R = o_kernel(res, rb->d_inf, rb->d_sm, O_RMAX, K);
+    if (R < 0) return R;
+    const int64_t plane = (int64_t)nx * ny;
+    const int kp = o_patch_threshold(rb);
+    int64_t amb_total = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : amb_total)
+    for (int k = 0; k < N; ++k) {
+        const float* g = eG + k * plane;
+        const float* c = eC + k * plane;
+        double* l = (double*)malloc(sizeof(double) * plane);
+        double* u = (double*)malloc(sizeof(double) * plane);
+        uint8_t* gamb = (uint8_t*)malloc(plane);
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double gx, gy, mxy, mg;
+                o_slope(g, nx, ny, res, x, y, &gx, &gy, &mxy, &mg);
+                gamb[(int64_t)y * nx + x] = isfinite(o_g(g, nx, ny, x, y)) && o_near(mg, rb->theta_s, tau);
+            }
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t i = (int64_t)y * nx + x;
+                o_cell o = o_eval_cell(g, c, nx, ny, res, rb, x, y);
+                l[i] = u[i] = o.cinit;
+                if (o.branch == 0) continue;
+                int aI = o_near(o.dI, rb->d_min, tau);
+                int aB = o_near(o.mxy, rb->theta_b, tau);
+                int aS = o_near(o.mgrad, rb->theta_s, tau);
+                int namb = 0, rp = rb->patch_radius;
+                for (int dy = -rp; dy <= rp; ++dy)
+                    for (int dx = -rp; dx <= rp; ++dx) {
+                        int qx = x + dx, qy = y + dy;
+                        if ((dx || dy) && qx >= 0 && qy >= 0 && qx < nx && qy < ny)
+                            namb += gamb[(int64_t)qy * nx + qx];
+                    }
+                /* count of definitely-gentle neighbours and the ambiguous range */
+                int cnt_def = o.count;
+                for (int dy = -rp; dy <= rp; ++dy)
+                    for (int dx = -rp; dx <= rp; ++dx) {
+                        int qx = x + dx, qy = y + dy;
+                        if ((dx || dy) && qx >= 0 && qy >= 0 && qx < nx && qy < ny &&
+                            gamb[(int64_t)qy * nx + qx] && o_is_gentle(g, nx, ny, res, rb, qx, qy))
+                            --cnt_def;
+                    }
+                int aP = cnt_def <= kp && kp < cnt_def + namb;
+                if (!(aI || aB || aS || aP)) continue;
+                ++amb_total;
+                int vI = o.dI < (double)rb->d_min, vB = o.mxy > (double)rb->theta_b;
+                int vS = o.mgrad < (double)rb->theta_s, vP = o.count > kp;
+                double mn = INFINITY, mx = -INFINITY;
+                for (int bI = 0; bI <= aI; ++bI)
+                    for (int bB = 0; bB <= aB; ++bB)
+                        for (int bS = 0; bS <= aS; ++bS)
+                            for (int bP = 0; bP <= aP; ++bP) {
+                                double v = o_cinit_forced(&o, rb, aI ? bI : vI, aB ? bB : vB,
+                                                          aS ? bS : vS, aP ? bP : vP);
+                                mn = fmin(mn, v);
+                                mx = fmax(mx, v);
+                            }
+                l[i] = mn;
+                u[i] = mx;
+            }
+        o_inflate(l, nx, ny, K, O_RMAX, R, lo + k * plane);
+        o_inflate(u, nx, ny, K, O_RMAX, R, hi + k * plane);
+        free(l);
+        free(u);
+        free(gamb);
+    }
+    return amb_total;
+}
+
+/* Three-valued check of a keep list produced elsewhere against the
+ * simplification rule, with costs known only to within [lo - tol, hi + tol].
+ * Walks the given keep list; at each slice the rule is evaluated with Kleene
+ * logic (0 false, 1 true, 2 unknown).  Equal definite costs compare as equal.
+ * Returns -1 when every decision is admissible, else the first slice whose
+ * decision contradicts a definite outcome. */
+static int t_and(int a, int b) { return (a == 0 || b == 0) ? 0 : (a == 1 && b == 1) ? 1 : 2; }
+static int t_or(int a, int b) { return (a == 1 || b == 1) ? 1 : (a == 0 && b == 0) ? 0 : 2; }
+
+static int o_less3(double lk, double hk, double lp, double hp, double tol) {
+    if (hk < lp - 2 * tol) return 1;
+    if (lk > hp + 2 * tol) return 0;
+    if (lk == hk && lp == hp && lk == lp) return 0;
+    return 2;
+}
+
+int o_simplify_check(const float* eG, const double* lo, const double* hi, int N, int nx, int ny,
+                     double cB, double tol, const uint8_t* keep) {
+    const int64_t plane = (int64_t)nx * ny;
+    int p = -1;
+    for (int k = 0; k < N; ++k) {
+        int U = 0;
+        for (int64_t c = 0; c < plane && U != 1; ++c) {
+            int64_t ik = k * plane + c;
+            int trav = hi[ik] < cB - tol ? 1 : (lo[ik] >= cB ? 0 : 2);
+            if (trav == 0) continue;
+            double ek = eG[ik];
+            int lower = 1;
+            if (p >= 0) {
+                int64_t ip = p * plane + c;
+                lower = t_or(ek > (double)eG[ip], o_less3(lo[ik], hi[ik], lo[ip], hi[ip], tol));
+            }
+            int upper = 1;
+            if (k < N - 1) {
+                int64_t iu = (k + 1) * plane + c;
+                upper = t_or((double)eG[iu] > ek, o_less3(lo[ik], hi[ik], lo[iu], hi[iu], tol));
+            }
+            U = t_or(U, t_and(trav, t_and(lower, upper)));
+        }
+        if ((U == 1 && !keep[k]) || (U == 0 && keep[k])) return k;
+        if (keep[k]) p = k;
+    }
+    return -1;
+}
