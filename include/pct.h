@@ -1,0 +1,183 @@
+/*
+ * pct.h - C ABI of the MI355X (gfx950) point-cloud-tomography library.
+ *
+ * Method: Yang et al., "Efficient Global Navigational Planning in 3D
+ * Structures based on Point Cloud Tomography" (arXiv 2403.07631).
+ *   - tomogram construction: Sec. III-A and Algorithm 1 (construction lines);
+ *   - traversability: Sec. III-B, Eqs. (1)-(6);
+ *   - simplification: Sec. III-C, Eqs. (7)-(9);
+ *   - trajectory cost sampling and adjoints: the cost and height terms of the
+ *     trajectory optimisation of Sec. III-E, Eq. (11).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* are device (HBM) pointers owned by the caller; the
+ *     library never allocates or frees device memory.  Pointers named h_* or
+ *     passed as structs are host pointers, read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is enqueued on it; only pct_tomogram_extent waits for it.
+ *   - Grids are stored [slice][iy][ix], ix fastest (row-major, x = column).
+ *   - Every entry point validates its arguments before enqueueing anything
+ *     and returns a pct_status.  On error nothing is launched and
+ *     pct_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).  A HIP error is reported as PCT_ERR_DEVICE.
+ *   - Workspaces are caller-provided device buffers of at least the size the
+ *     matching *_workspace_bytes function returns, 256-byte aligned.
+ *   - Arithmetic is FP32.  Tomograms are exact: every stored height is the
+ *     height of an input point.
+ */
+#ifndef PCT_H
+#define PCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pct_status;
+#define PCT_OK 0
+#define PCT_ERR_ARG (-1)       /* invalid argument (null pointer, bad size, bad parameter) */
+#define PCT_ERR_WORKSPACE (-2) /* workspace smaller than required */
+#define PCT_ERR_CAPACITY (-3)  /* a size limit below is exceeded */
+#define PCT_ERR_DEVICE (-4)    /* a HIP runtime call failed */
+
+#define PCT_ABI_VERSION 1
+#define PCT_MAX_SLICES 1024      /* N, the number of slice planes */
+#define PCT_MAX_KERNEL_RADIUS 16 /* support radius of the inflation kernel, in cells */
+#define PCT_MAX_PATCH_RADIUS 4   /* r_p of the step test's neighbour patch */
+#define PCT_MAX_GRID_SIDE 65535  /* nx, ny */
+
+/* Grid of Sec. III-A: resolution r_g = res, slice interval d_s = slice_dz.
+ * Cell (ix, iy) holds the points with floor((x - x0) / res) = ix and
+ * floor((y - y0) / res) = iy, the subtraction and the division each being one
+ * correctly rounded FP32 operation.  Points outside [0,nx) x [0,ny) are not
+ * part of the map. */
+typedef struct {
+    float x0, y0, res;
+    int32_t nx, ny;
+    float slice_dz;
+} pct_grid;
+
+/* Vertical extent of the map (Algorithm 1, first line) and the slice count.
+ * Plane k (k = 0 .. n_slices-1) is at h_k = z_min + (k+1) * slice_dz, one
+ * FP32 multiply then one FP32 add; n_slices is the least N with
+ * h_{N-1} > z_max (Sec. III-A).  n_used counts the points that belong to the
+ * map (finite and inside the grid), n_dropped the others.  An empty map has
+ * n_slices = 0. */
+typedef struct {
+    float z_min, z_max;
+    int32_t n_slices;
+    int32_t reserved;
+    int64_t n_used, n_dropped;
+} pct_extent;
+
+/* Robot parameters of Eqs. (1)-(6) and Table I.  theta_b, theta_s bound the
+ * gradient magnitudes m^xy and m^grad of Eq. (2); theta_p bounds the share
+ * p_s of gentle neighbours in the (2 patch_radius + 1)^2 patch of Eq. (4);
+ * d_inf and d_sm shape the inflation kernel of Eq. (6). */
+typedef struct {
+    float d_min, d_ref, theta_b, theta_s, theta_p, c_barrier, alpha_d, alpha_b, alpha_s, d_inf, d_sm;
+    int32_t patch_radius;
+} pct_robot;
+
+/* ABI version of the loaded library (PCT_ABI_VERSION). */
+int32_t pct_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* pct_last_error(void);
+
+/* Host only.  Robot parameters from a physical description at grid
+ * resolution res: theta_s = tan(max_slope), theta_b = max_step / (2 res)
+ * (a central difference across a step of height s is s / 2r, Eq. (2)),
+ * d_min = min_interval, d_ref = nominal_height, d_inf = inflation_radius,
+ * d_sm = safe_margin; theta_p = 0.2, c^B = 50, alpha_d = 20, alpha_b = 20,
+ * alpha_s = 15 from Table I; patch_radius = 1.  PCT_ERR_ARG on a
+ * non-positive size or a slope outside (0, 90) degrees. */
+pct_status pct_robot_from_physical(float min_interval, float nominal_height, float max_slope_deg,
+                                   float max_step, float inflation_radius, float safe_margin, float res,
+                                   pct_robot* out);
+
+/* Host only.  Checks a grid (res > 0, slice_dz > 0, 1 <= nx, ny <= 65535,
+ * finite origin). */
+pct_status pct_validate_grid(const pct_grid* grid);
+
+/* Host only.  Checks a robot at resolution res: finite parameters,
+ * c_barrier > 0, d_sm > res (the margin of Eq. (6) must be wider than a
+ * cell), 1 <= patch_radius <= 4, kernel radius <= 16. */
+pct_status pct_validate_robot(const pct_robot* robot, float res);
+
+/* Host only.  Support radius R (cells) of the Eq. (6) kernel of a robot at
+ * resolution res: the largest max(|m|,|n|) with K(m,n) > 0. */
+pct_status pct_kernel_radius(const pct_robot* robot, float res, int32_t* radius_out);
+
+/* Host only.  Plane heights h_0 .. h_{N-1} of an extent (see pct_extent),
+ * written to h_out[0 .. cap).  PCT_ERR_CAPACITY if N > cap. */
+pct_status pct_plane_heights(const pct_extent* extent, float slice_dz, float* h_out, int32_t cap);
+
+/* ---------------------------------------------------------------------- */
+/* Tomogram construction (Sec. III-A, Algorithm 1)                        */
+
+/* Workspace bytes for pct_tomogram_extent over n points. */
+size_t pct_extent_workspace_bytes(int64_t n);
+
+/* Algorithm 1, first line, and the plane count of Sec. III-A.
+ * d_xyz: n points, float32 [n][3] (x, y, z).  Non-finite points and points
+ * outside the grid are dropped; -0 heights count as +0.  Writes *h_out and
+ * returns after synchronising `stream` (the slice count sizes the outputs
+ * of pct_build_tomogram).  PCT_ERR_CAPACITY if more than PCT_MAX_SLICES
+ * planes are needed, PCT_ERR_ARG if two planes coincide in FP32. */
+pct_status pct_tomogram_extent(const float* d_xyz, int64_t n, const pct_grid* grid, pct_extent* h_out,
+                               void* d_ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for pct_build_tomogram. */
+size_t pct_build_workspace_bytes(int64_t n, const pct_grid* grid, const pct_extent* extent);
+
+/* Algorithm 1, construction loop: for every slice k and cell, the ground
+ * e^G_k = highest height of the cell's points at or below plane h_k and the
+ * ceiling e^C_k = lowest height above it (Sec. III-A: the lower group is
+ * projected up to the ground layer, the upper group down to the ceiling).
+ * Empty sets give e^G = -inf, e^C = +inf.
+ * Outputs d_ground, d_ceil: float32 [N][ny][nx], fully overwritten.
+ * d_arg_ground, d_arg_ceil (nullable, both or neither): int32 [N][ny][nx],
+ * the index in d_xyz of the point that gives the value (lowest index among
+ * equal heights), -1 where invalid.  `extent` must come from
+ * pct_tomogram_extent on the same points and grid. */
+pct_status pct_build_tomogram(const float* d_xyz, int64_t n, const pct_grid* grid, const pct_extent* extent,
+                              float* d_ground, float* d_ceil, int32_t* d_arg_ground, int32_t* d_arg_ceil,
+                              void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Traversability (Sec. III-B) and simplification (Sec. III-C)            */
+
+/* Workspace bytes for pct_eval_traversability with n_robots robots. */
+size_t pct_eval_workspace_bytes(const pct_grid* grid, const pct_extent* extent, int32_t n_robots);
+
+/* Eqs. (1)-(6) for every slice, then the slice test of Eqs. (7)-(9), for
+ * each of n_robots robots (h_robots: host array).
+ *   c^I:   d^I = e^C - e^G; c^B if d^I < d_min else max(0, alpha_d (d_ref - d^I)).
+ *   c^G:   central differences of e^G over 2 res; c^B if m^xy > theta_b;
+ *          alpha_s (m^grad / theta_s)^2 if m^grad < theta_s; otherwise
+ *          alpha_b (m^xy / theta_b)^2 if more than floor(theta_p * P) of the
+ *          P = (2 r_p + 1)^2 - 1 patch neighbours are gentle, else c^B.
+ *   c^init = min(c^B, c^I + c^G); c^B where there is no ground.  A stencil
+ *          reaching off the grid or into a cell without ground gives an
+ *          infinite slope.  No ceiling gives c^I = 0.
+ *   c^T:   max over the Eq. (6) window of K(m,n) * c^init (off-grid taps
+ *          skipped).
+ *   keep:  slice k is kept if some cell with c^T < c^B differs from the last
+ *          kept slice (higher ground or lower cost; true when none is kept
+ *          yet) and from slice k+1 (higher ground there or lower cost here;
+ *          true for the last slice).
+ * d_ground, d_ceil: float32 [N][ny][nx] from pct_build_tomogram.
+ * d_cost: float32 [n_robots][N][ny][nx], fully overwritten with c^T.
+ * d_keep: uint8 [n_robots][N], 1 = kept (nullable: skip the slice test). */
+pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                   const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
+                                   float* d_cost, uint8_t* d_keep, void* d_ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCT_H */

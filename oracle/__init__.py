@@ -61,6 +61,8 @@ def lib():
         L.o_planes.argtypes = [C.c_float, C.c_float, C.c_float, C.c_int, f32p]
         L.o_planes.restype = C.c_int
         L.o_build.argtypes = [f32p, C.c_int64, C.POINTER(Grid), f32p, C.c_int, f32p, f32p, i32p, i32p]
+        L.o_build_window.argtypes = [f32p, C.c_int64, C.POINTER(Grid), f32p, C.c_int, C.c_int, C.c_int,
+                                     C.c_int, C.c_int, f32p, f32p, i32p, i32p]
         L.o_layers.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_double, C.POINTER(Robot),
                                f64p, f64p, f64p, f64p, f64p, u8p, i32p]
         L.o_kernel.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, f64p]
@@ -165,6 +167,22 @@ def build(points, grid, h, ids=True):
     lib().o_build(_p(pts, C.c_float), pts.shape[0], C.byref(g), _p(h, C.c_float), N,
                   _p(eG, C.c_float), _p(eC, C.c_float),
                   _p(aG, C.c_int32) if ids else None, _p(aC, C.c_int32) if ids else None)
+    return eG, eC, aG, aC
+
+
+def build_window(points, grid, h, wx0, wy0, wnx, wny, ids=True):
+    """Algorithm 1 for the cells of one window of the grid; [N, wny, wnx]."""
+    pts = _f32(points).reshape(-1, 3)
+    h = _f32(h)
+    N = len(h)
+    eG = np.empty((N, wny, wnx), np.float32)
+    eC = np.empty((N, wny, wnx), np.float32)
+    aG = np.empty((N, wny, wnx), np.int32) if ids else None
+    aC = np.empty((N, wny, wnx), np.int32) if ids else None
+    g = grid_struct(grid)
+    lib().o_build_window(_p(pts, C.c_float), pts.shape[0], C.byref(g), _p(h, C.c_float), N,
+                         wx0, wy0, wnx, wny, _p(eG, C.c_float), _p(eC, C.c_float),
+                         _p(aG, C.c_int32) if ids else None, _p(aC, C.c_int32) if ids else None)
     return eG, eC, aG, aC
 
 

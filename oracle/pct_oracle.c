@@ -137,6 +137,38 @@ void o_build(const float* xyz, int64_t n, const o_grid* g, const float* h, int N
     }
 }
 
+/* The same loop restricted to the cells of a window [wx0, wx0+wnx) x
+ * [wy0, wy0+wny) of the grid (cells are still assigned with the full grid's
+ * rasterisation).  Outputs are [N][wny][wnx].  Lets a map too large for the
+ * full O(points x slices) loop be checked window by window. */
+void o_build_window(const float* xyz, int64_t n, const o_grid* g, const float* h, int N,
+                    int wx0, int wy0, int wnx, int wny,
+                    float* eG, float* eC, int32_t* aG, int32_t* aC) {
+    const int64_t plane = (int64_t)wnx * wny;
+    for (int64_t i = 0; i < plane * N; ++i) {
+        eG[i] = -INFINITY;
+        eC[i] = INFINITY;
+        if (aG) aG[i] = -1;
+        if (aC) aC[i] = -1;
+    }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < N; ++k) {
+        for (int64_t u = 0; u < n; ++u) {
+            const float* p = xyz + 3 * u;
+            int ix, iy;
+            if (!o_point_ok(p) || !o_rasterize(p[0], p[1], g, &ix, &iy)) continue;
+            if (ix < wx0 || iy < wy0 || ix >= wx0 + wnx || iy >= wy0 + wny) continue;
+            float z = p[2] + 0.0f;
+            int64_t c = (int64_t)k * plane + (int64_t)(iy - wy0) * wnx + (ix - wx0);
+            if (z <= h[k]) {
+                if (z > eG[c]) { eG[c] = z; if (aG) aG[c] = (int32_t)u; }
+            } else {
+                if (z < eC[c]) { eC[c] = z; if (aC) aC[c] = (int32_t)u; }
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. III-B, traversability of one slice, in FP64. */
 

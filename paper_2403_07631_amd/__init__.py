@@ -1,0 +1,229 @@
+"""Python binding of libpct, the MI355X (gfx950) point-cloud-tomography library.
+
+The functions carry the C ABI's names (see ``include/pct.h``) and only
+marshal arguments: torch CUDA tensors are passed by ``data_ptr()`` with the
+current stream, outputs and workspaces are allocated as torch tensors.  Every
+step of the computation runs in the library's HIP kernels; if the library is
+missing, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpct.so")
+
+PCT_OK, PCT_ERR_ARG, PCT_ERR_WORKSPACE, PCT_ERR_CAPACITY, PCT_ERR_DEVICE = 0, -1, -2, -3, -4
+PCT_MAX_SLICES = 1024
+
+
+class PctError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed (status {status}): {msg}")
+        self.status = status
+
+
+class pct_grid(C.Structure):
+    _fields_ = [("x0", C.c_float), ("y0", C.c_float), ("res", C.c_float),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("slice_dz", C.c_float)]
+
+
+class pct_extent(C.Structure):
+    _fields_ = [("z_min", C.c_float), ("z_max", C.c_float), ("n_slices", C.c_int32),
+                ("reserved", C.c_int32), ("n_used", C.c_int64), ("n_dropped", C.c_int64)]
+
+
+_ROBOT_FIELDS = ("d_min", "d_ref", "theta_b", "theta_s", "theta_p", "c_barrier", "alpha_d",
+                 "alpha_b", "alpha_s", "d_inf", "d_sm")
+
+
+class pct_robot(C.Structure):
+    _fields_ = [(n, C.c_float) for n in _ROBOT_FIELDS] + [("patch_radius", C.c_int32)]
+
+    def as_dict(self):
+        d = {n: float(getattr(self, n)) for n in _ROBOT_FIELDS}
+        d["patch_radius"] = int(self.patch_radius)
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libpct.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpct.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_2403_07631_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, sz, i64, i32, f32 = C.c_void_p, C.c_size_t, C.c_int64, C.c_int32, C.c_float
+    G, E, Rb = C.POINTER(pct_grid), C.POINTER(pct_extent), C.POINTER(pct_robot)
+    sig = {
+        "pct_abi_version": ([], i32),
+        "pct_last_error": ([], C.c_char_p),
+        "pct_robot_from_physical": ([f32, f32, f32, f32, f32, f32, f32, Rb], i32),
+        "pct_validate_grid": ([G], i32),
+        "pct_validate_robot": ([Rb, f32], i32),
+        "pct_kernel_radius": ([Rb, f32, C.POINTER(i32)], i32),
+        "pct_plane_heights": ([E, f32, vp, i32], i32),
+        "pct_extent_workspace_bytes": ([i64], sz),
+        "pct_tomogram_extent": ([vp, i64, G, E, vp, sz, vp], i32),
+        "pct_build_workspace_bytes": ([i64, G, E], sz),
+        "pct_build_tomogram": ([vp, i64, G, E, vp, vp, vp, vp, vp, sz, vp], i32),
+        "pct_eval_workspace_bytes": ([G, E, i32], sz),
+        "pct_eval_traversability": ([vp, vp, G, E, Rb, i32, vp, vp, vp, sz, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def declared_symbols():
+    """Names of the entry points the binding declares (for export checks)."""
+    lib()
+    return sorted(n for n in dir(_lib) if n.startswith("pct_"))
+
+
+def _check(fn, status):
+    if status != PCT_OK:
+        raise PctError(fn, status, lib().pct_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def grid_struct(grid) -> pct_grid:
+    if isinstance(grid, pct_grid):
+        return grid
+    return pct_grid(float(grid["x0"]), float(grid["y0"]), float(grid["res"]), int(grid["nx"]),
+                    int(grid["ny"]), float(grid["slice_dz"]))
+
+
+def robot_struct(r) -> pct_robot:
+    if isinstance(r, pct_robot):
+        return r
+    return pct_robot(*[float(r[n]) for n in _ROBOT_FIELDS], int(r.get("patch_radius", 1)))
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------- host
+
+def pct_abi_version() -> int:
+    return int(lib().pct_abi_version())
+
+
+def pct_robot_from_physical(min_interval, nominal_height, max_slope_deg, max_step,
+                            inflation_radius, safe_margin, res) -> pct_robot:
+    out = pct_robot()
+    _check("pct_robot_from_physical",
+           lib().pct_robot_from_physical(min_interval, nominal_height, max_slope_deg, max_step,
+                                         inflation_radius, safe_margin, res, C.byref(out)))
+    return out
+
+
+def robot_from_physical(phys: dict, res: float) -> pct_robot:
+    return pct_robot_from_physical(phys["min_interval"], phys["nominal_height"], phys["max_slope_deg"],
+                                   phys["max_step"], phys["inflation_radius"], phys["safe_margin"], res)
+
+
+def pct_validate_grid(grid) -> None:
+    g = grid_struct(grid)
+    _check("pct_validate_grid", lib().pct_validate_grid(C.byref(g)))
+
+
+def pct_validate_robot(robot, res) -> None:
+    r = robot_struct(robot)
+    _check("pct_validate_robot", lib().pct_validate_robot(C.byref(r), res))
+
+
+def pct_kernel_radius(robot, res) -> int:
+    r = robot_struct(robot)
+    out = C.c_int32()
+    _check("pct_kernel_radius", lib().pct_kernel_radius(C.byref(r), res, C.byref(out)))
+    return int(out.value)
+
+
+def pct_plane_heights(extent: pct_extent, slice_dz: float):
+    import numpy as np
+    h = np.zeros(max(1, extent.n_slices), np.float32)
+    _check("pct_plane_heights", lib().pct_plane_heights(C.byref(extent), slice_dz,
+                                                        h.ctypes.data_as(C.c_void_p), len(h)))
+    return h[:extent.n_slices]
+
+
+# --------------------------------------------------------------------- device
+
+def _points(xyz):
+    if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.dim() == 2 and xyz.shape[1] == 3):
+        raise ValueError("points must be a CUDA float32 tensor of shape [n, 3]")
+    return xyz.contiguous()
+
+
+def pct_tomogram_extent(xyz, grid) -> pct_extent:
+    xyz = _points(xyz)
+    g = grid_struct(grid)
+    n = xyz.shape[0]
+    ws = _workspace(lib().pct_extent_workspace_bytes(n), xyz.device)
+    out = pct_extent()
+    _check("pct_tomogram_extent",
+           lib().pct_tomogram_extent(_ptr(xyz), n, C.byref(g), C.byref(out), _ptr(ws), ws.numel(),
+                                     _stream(xyz.device)))
+    return out
+
+
+def pct_build_tomogram(xyz, grid, extent: pct_extent, with_ids: bool = False, workspace=None):
+    """Returns (ground, ceil, arg_ground, arg_ceil); the ids are None unless
+    ``with_ids``.  Shapes [N, ny, nx]."""
+    xyz = _points(xyz)
+    g = grid_struct(grid)
+    n, N = xyz.shape[0], extent.n_slices
+    dev = xyz.device
+    ground = torch.empty((N, g.ny, g.nx), dtype=torch.float32, device=dev)
+    ceil = torch.empty_like(ground)
+    ag = torch.empty((N, g.ny, g.nx), dtype=torch.int32, device=dev) if with_ids else None
+    ac = torch.empty_like(ag) if with_ids else None
+    need = lib().pct_build_workspace_bytes(n, C.byref(g), C.byref(extent))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    _check("pct_build_tomogram",
+           lib().pct_build_tomogram(_ptr(xyz), n, C.byref(g), C.byref(extent), _ptr(ground), _ptr(ceil),
+                                    _ptr(ag), _ptr(ac), _ptr(ws), ws.numel(), _stream(dev)))
+    return ground, ceil, ag, ac
+
+
+def pct_eval_traversability(ground, ceil, grid, extent: pct_extent, robots, keep: bool = True,
+                            workspace=None):
+    """Returns (cost [R, N, ny, nx] float32, keep [R, N] uint8 or None)."""
+    if isinstance(robots, (pct_robot, dict)):
+        robots = [robots]
+    rs = (pct_robot * len(robots))(*[robot_struct(r) for r in robots])
+    g = grid_struct(grid)
+    N = extent.n_slices
+    dev = ground.device
+    for t in (ground, ceil):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (N, g.ny, g.nx)):
+            raise ValueError("ground/ceil must be contiguous CUDA float32 [N, ny, nx]")
+    cost = torch.empty((len(robots), N, g.ny, g.nx), dtype=torch.float32, device=dev)
+    kp = torch.empty((len(robots), N), dtype=torch.uint8, device=dev) if keep else None
+    need = lib().pct_eval_workspace_bytes(C.byref(g), C.byref(extent), len(robots))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    _check("pct_eval_traversability",
+           lib().pct_eval_traversability(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), rs,
+                                         len(robots), _ptr(cost), _ptr(kp), _ptr(ws), ws.numel(),
+                                         _stream(dev)))
+    return cost, kp

@@ -1,0 +1,311 @@
+// Host side of libpct: argument validation, parameter tables, workspace
+// sizing and launch orchestration.  Nothing here allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "pct_internal.h"
+
+namespace pct {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+pct_status fail(pct_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+namespace {
+
+bool finite_f(float v) { return isfinite(v) != 0; }
+
+pct_status check_grid(const pct_grid* g) {
+    if (!g) return fail(PCT_ERR_ARG, "grid is null");
+    if (!finite_f(g->x0) || !finite_f(g->y0)) return fail(PCT_ERR_ARG, "grid origin must be finite");
+    if (!(g->res > 0.0f) || !finite_f(g->res)) return fail(PCT_ERR_ARG, "grid res must be > 0");
+    if (!(g->slice_dz > 0.0f) || !finite_f(g->slice_dz)) return fail(PCT_ERR_ARG, "slice_dz must be > 0");
+    if (g->nx < 1 || g->ny < 1 || g->nx > PCT_MAX_GRID_SIDE || g->ny > PCT_MAX_GRID_SIDE)
+        return fail(PCT_ERR_ARG, "grid size %d x %d outside [1, %d]", g->nx, g->ny, PCT_MAX_GRID_SIDE);
+    return PCT_OK;
+}
+
+// Eq. (6) weight in FP64 from the float parameters; weights within 1e-6
+// of 1 or 0 are taken as exactly 1 or 0 (lattice distances that equal d_inf
+// or the outer edge in decimal land a few 1e-8 off after the parameters
+// are stored as floats).
+double kernel_weight(const pct_robot& r, float res, int a, int j) {
+    const double rr = (double)res;
+    const double dist = rr * sqrt((double)(a * a + j * j));
+    double k = 1.0 - (dist - (double)r.d_inf) / ((double)r.d_sm - rr);
+    k = std::max(0.0, std::min(k, 1.0));
+    if (k >= 1.0 - 1e-6) k = 1.0;
+    if (k <= 1e-6) k = 0.0;
+    return k;
+}
+
+int kernel_radius(const pct_robot& r, float res) {
+    int R = 0;
+    for (int a = 0; a <= PCT_MAX_KERNEL_RADIUS + 1; ++a)
+        for (int j = 0; j <= a; ++j)
+            if (kernel_weight(r, res, a, j) > 0.0) R = a;
+    return R;
+}
+
+pct_status check_robot(const pct_robot* r, float res) {
+    if (!r) return fail(PCT_ERR_ARG, "robot is null");
+    const float v[] = {r->d_min, r->d_ref, r->theta_b, r->theta_s, r->theta_p, r->c_barrier,
+                       r->alpha_d, r->alpha_b, r->alpha_s, r->d_inf, r->d_sm};
+    for (float x : v)
+        if (!finite_f(x)) return fail(PCT_ERR_ARG, "robot parameters must be finite");
+    if (!(r->c_barrier > 0.0f)) return fail(PCT_ERR_ARG, "c_barrier must be > 0");
+    if (!(r->theta_b > 0.0f) || !(r->theta_s > 0.0f)) return fail(PCT_ERR_ARG, "theta_b and theta_s must be > 0");
+    if (r->theta_p < 0.0f) return fail(PCT_ERR_ARG, "theta_p must be >= 0");
+    if (r->alpha_d < 0.0f || r->alpha_b < 0.0f || r->alpha_s < 0.0f) return fail(PCT_ERR_ARG, "scaling factors must be >= 0");
+    if (r->d_inf < 0.0f) return fail(PCT_ERR_ARG, "d_inf must be >= 0");
+    if (!(r->d_sm > res)) return fail(PCT_ERR_ARG, "d_sm (%g) must exceed the grid resolution (%g)", r->d_sm, res);
+    if (r->patch_radius < 1 || r->patch_radius > PCT_MAX_PATCH_RADIUS)
+        return fail(PCT_ERR_ARG, "patch_radius must be in [1, %d]", PCT_MAX_PATCH_RADIUS);
+    if (kernel_radius(*r, res) > PCT_MAX_KERNEL_RADIUS)
+        return fail(PCT_ERR_CAPACITY, "inflation kernel radius exceeds %d cells", PCT_MAX_KERNEL_RADIUS);
+    return PCT_OK;
+}
+
+pct_status check_extent(const pct_extent* e) {
+    if (!e) return fail(PCT_ERR_ARG, "extent is null");
+    if (e->n_slices < 0 || e->n_slices > PCT_MAX_SLICES)
+        return fail(PCT_ERR_CAPACITY, "n_slices %d outside [0, %d]", e->n_slices, PCT_MAX_SLICES);
+    if (e->n_slices > 0 && (!finite_f(e->z_min) || !finite_f(e->z_max)))
+        return fail(PCT_ERR_ARG, "extent heights must be finite");
+    return PCT_OK;
+}
+
+// Number of planes for an extent (Sec. III-A): the least N with
+// h_{N-1} > z_max; -1 if consecutive planes coincide, -2 if N > cap.
+int plane_count(float zmin, float zmax, float ds, int cap) {
+    float prev = -INFINITY;
+    for (int k = 0; k < cap; ++k) {
+        const float h = plane_height(zmin, ds, k);
+        if (!(h > prev)) return -1;
+        if (h > zmax) return k + 1;
+        prev = h;
+    }
+    return -2;
+}
+
+}  // namespace
+
+pct_status make_eval_params(const pct_robot& r, const pct_grid& g, int N, EvalParams* out) {
+    EvalParams p{};
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.N = N;
+    p.plane = (long long)g.nx * g.ny;
+    p.R = kernel_radius(r, g.res);
+    if (p.R > PCT_MAX_KERNEL_RADIUS) return fail(PCT_ERR_CAPACITY, "inflation kernel radius exceeds %d", PCT_MAX_KERNEL_RADIUS);
+    p.d_min = r.d_min;
+    p.d_ref = r.d_ref;
+    p.cB = r.c_barrier;
+    p.alpha_d = r.alpha_d;
+    const double two_r = 2.0 * (double)g.res;
+    const double tb = (double)r.theta_b * two_r, ts = (double)r.theta_s * two_r;
+    p.Tb = (float)tb;
+    p.Ts2 = (float)(ts * ts);
+    p.As = (float)((double)r.alpha_s / (ts * ts));
+    p.Ab = (float)((double)r.alpha_b / (tb * tb));
+    p.rp = r.patch_radius;
+    const int np = (2 * r.patch_radius + 1) * (2 * r.patch_radius + 1) - 1;
+    p.kp = (int)floor((double)r.theta_p * (double)np);
+    for (int a = 0; a < kKmax; ++a)
+        for (int j = 0; j < kKmax; ++j) p.K[a][j] = (float)kernel_weight(r, g.res, a, j);
+    *out = p;
+    return PCT_OK;
+}
+
+}  // namespace pct
+
+using namespace pct;
+
+extern "C" {
+
+int32_t pct_abi_version(void) { return PCT_ABI_VERSION; }
+
+const char* pct_last_error(void) { return g_err; }
+
+pct_status pct_validate_grid(const pct_grid* grid) {
+    clear_error();
+    return check_grid(grid);
+}
+
+pct_status pct_validate_robot(const pct_robot* robot, float res) {
+    clear_error();
+    if (!(res > 0.0f)) return fail(PCT_ERR_ARG, "res must be > 0");
+    return check_robot(robot, res);
+}
+
+pct_status pct_kernel_radius(const pct_robot* robot, float res, int32_t* radius_out) {
+    clear_error();
+    if (!radius_out) return fail(PCT_ERR_ARG, "radius_out is null");
+    pct_status st = pct_validate_robot(robot, res);
+    if (st != PCT_OK) return st;
+    *radius_out = kernel_radius(*robot, res);
+    return PCT_OK;
+}
+
+pct_status pct_robot_from_physical(float min_interval, float nominal_height, float max_slope_deg, float max_step,
+                                   float inflation_radius, float safe_margin, float res, pct_robot* out) {
+    clear_error();
+    if (!out) return fail(PCT_ERR_ARG, "out is null");
+    if (!(res > 0.0f) || !(min_interval > 0.0f) || !(nominal_height > 0.0f) || !(max_step > 0.0f) ||
+        !(inflation_radius >= 0.0f) || !(safe_margin > 0.0f))
+        return fail(PCT_ERR_ARG, "sizes must be positive");
+    if (!(max_slope_deg > 0.0f && max_slope_deg < 90.0f)) return fail(PCT_ERR_ARG, "max slope must be in (0, 90) degrees");
+    pct_robot r{};
+    r.d_min = min_interval;
+    r.d_ref = nominal_height;
+    r.theta_s = (float)tan((double)max_slope_deg * M_PI / 180.0);
+    r.theta_b = (float)((double)max_step / (2.0 * (double)res));
+    r.theta_p = 0.20f;
+    r.c_barrier = 50.0f;
+    r.alpha_d = 20.0f;
+    r.alpha_b = 20.0f;
+    r.alpha_s = 15.0f;
+    r.d_inf = inflation_radius;
+    r.d_sm = safe_margin;
+    r.patch_radius = 1;
+    *out = r;
+    return PCT_OK;
+}
+
+pct_status pct_plane_heights(const pct_extent* extent, float slice_dz, float* h_out, int32_t cap) {
+    clear_error();
+    pct_status st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (!(slice_dz > 0.0f)) return fail(PCT_ERR_ARG, "slice_dz must be > 0");
+    if (extent->n_slices > cap) return fail(PCT_ERR_CAPACITY, "h_out holds %d planes, %d needed", cap, extent->n_slices);
+    if (extent->n_slices > 0 && !h_out) return fail(PCT_ERR_ARG, "h_out is null");
+    for (int k = 0; k < extent->n_slices; ++k) h_out[k] = plane_height(extent->z_min, slice_dz, k);
+    return PCT_OK;
+}
+
+size_t pct_extent_workspace_bytes(int64_t n) { return extent_ws_bytes(n); }
+
+pct_status pct_tomogram_extent(const float* d_xyz, int64_t n, const pct_grid* grid, pct_extent* h_out, void* d_ws,
+                               size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    if (!h_out) return fail(PCT_ERR_ARG, "h_out is null");
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count %lld outside [0, 2^31)", (long long)n);
+    pct_extent e{};
+    e.z_min = INFINITY;
+    e.z_max = -INFINITY;
+    if (n == 0) {
+        *h_out = e;
+        return PCT_OK;
+    }
+    if (!d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    if (!d_ws || ws_bytes < extent_ws_bytes(n))
+        return fail(PCT_ERR_WORKSPACE, "extent workspace too small: %zu < %zu", ws_bytes, extent_ws_bytes(n));
+    hipStream_t s = (hipStream_t)stream;
+    GridDev g = make_grid_dev(*grid);
+    ExtentDev* d_out = (ExtentDev*)((char*)d_ws + extent_ws_bytes(n) - align_up(sizeof(ExtentDev)));
+    st = launch_extent(d_xyz, n, g, d_ws, d_out, s);
+    if (st != PCT_OK) return st;
+    ExtentDev hx{};
+    PCT_HIP(hipMemcpyAsync(&hx, d_out, sizeof hx, hipMemcpyDeviceToHost, s));
+    PCT_HIP(hipStreamSynchronize(s));
+    e.n_used = (int64_t)hx.used;
+    e.n_dropped = n - e.n_used;
+    if (e.n_used > 0) {
+        e.z_min = hx.zmin;
+        e.z_max = hx.zmax;
+        int N = plane_count(hx.zmin, hx.zmax, grid->slice_dz, PCT_MAX_SLICES);
+        if (N == -1) return fail(PCT_ERR_ARG, "slice planes coincide in FP32 (slice_dz too small for z range)");
+        if (N == -2) return fail(PCT_ERR_CAPACITY, "more than %d slices needed", PCT_MAX_SLICES);
+        e.n_slices = N;
+    }
+    *h_out = e;
+    return PCT_OK;
+}
+
+size_t pct_build_workspace_bytes(int64_t n, const pct_grid* grid, const pct_extent* extent) {
+    (void)extent;
+    if (!grid || check_grid(grid) != PCT_OK || n < 0) return 0;
+    return build_ws_bytes(n, make_grid_dev(*grid), true);
+}
+
+pct_status pct_build_tomogram(const float* d_xyz, int64_t n, const pct_grid* grid, const pct_extent* extent,
+                              float* d_ground, float* d_ceil, int32_t* d_arg_ground, int32_t* d_arg_ceil, void* d_ws,
+                              size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count %lld outside [0, 2^31)", (long long)n);
+    if ((d_arg_ground == nullptr) != (d_arg_ceil == nullptr))
+        return fail(PCT_ERR_ARG, "d_arg_ground and d_arg_ceil must both be given or both be null");
+    if (extent->n_slices == 0) return PCT_OK;
+    if (!d_ground || !d_ceil) return fail(PCT_ERR_ARG, "output pointers are null");
+    if (n > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    if (plane_count(extent->z_min, extent->z_max, grid->slice_dz, PCT_MAX_SLICES) != extent->n_slices)
+        return fail(PCT_ERR_ARG, "extent does not match the plane rule for this slice_dz");
+    GridDev g = make_grid_dev(*grid);
+    const bool ids = d_arg_ground != nullptr;
+    if (!d_ws || ws_bytes < build_ws_bytes(n, g, ids))
+        return fail(PCT_ERR_WORKSPACE, "build workspace too small: %zu < %zu", ws_bytes, build_ws_bytes(n, g, ids));
+    return launch_build(d_xyz, n, g, extent->z_min, grid->slice_dz, extent->n_slices, d_ground, d_ceil, d_arg_ground,
+                        d_arg_ceil, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t pct_eval_workspace_bytes(const pct_grid* grid, const pct_extent* extent, int32_t n_robots) {
+    if (!grid || !extent || extent->n_slices < 0) return 0;
+    return eval_ws_bytes(std::max(1, (int)extent->n_slices), n_robots);
+}
+
+pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                   const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
+                                   float* d_cost, uint8_t* d_keep, void* d_ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (n_robots < 1 || !h_robots) return fail(PCT_ERR_ARG, "at least one robot is required");
+    for (int i = 0; i < n_robots; ++i) {
+        st = check_robot(&h_robots[i], grid->res);
+        if (st != PCT_OK) return st;
+    }
+    const int N = extent->n_slices;
+    if (N == 0) return PCT_OK;
+    if (!d_ground || !d_ceil || !d_cost) return fail(PCT_ERR_ARG, "device pointers are null");
+    if (d_keep && (!d_ws || ws_bytes < eval_ws_bytes(N, n_robots)))
+        return fail(PCT_ERR_WORKSPACE, "eval workspace too small: %zu < %zu", ws_bytes, eval_ws_bytes(N, n_robots));
+    hipStream_t s = (hipStream_t)stream;
+    const long long per_robot = (long long)N * grid->nx * grid->ny;
+    for (int i = 0; i < n_robots; ++i) {
+        EvalParams p;
+        st = make_eval_params(h_robots[i], *grid, N, &p);
+        if (st != PCT_OK) return st;
+        float* cost = d_cost + per_robot * i;
+        st = launch_eval(d_ground, d_ceil, p, cost, s);
+        if (st != PCT_OK) return st;
+        if (d_keep) {
+            st = launch_simplify(d_ground, cost, p, d_keep + (size_t)N * i, d_ws, s);
+            if (st != PCT_OK) return st;
+        }
+    }
+    return PCT_OK;
+}
+
+}  // extern "C"

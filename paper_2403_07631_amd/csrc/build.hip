@@ -1,0 +1,532 @@
+// Tomogram construction on gfx950 (Sec. III-A, Algorithm 1).
+//
+// Algorithm 1 compares every point with every plane.  Here the points are
+// first binned by a counting sort into construction tiles (64 x th cells),
+// with LDS-privatised integer counters; then one workgroup per tile sorts
+// each cell's heights in LDS and sweeps the planes once:
+//   ground e^G_k = the largest height <= h_k, ceiling e^C_k = the next one.
+// This equals Algorithm 1's per-plane max/min exactly (only comparisons are
+// involved) and writes each output element once, coalesced along x.
+#include "pct_internal.h"
+
+namespace pct {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kBinPPT = 16;           // points per thread in the binning kernels
+constexpr int kReduceCapIds = 6144;   // LDS record capacity of the tile reduce (with ids)
+constexpr int kReduceCap = 8192;      // ... without ids
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ extent
+__global__ __launch_bounds__(kBlock) void k_extent(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                   float* __restrict__ pmin, float* __restrict__ pmax,
+                                                   unsigned long long* __restrict__ pused) {
+    float lo = INFINITY, hi = -INFINITY;
+    unsigned long long used = 0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        int ix, iy;
+        if (!isfinite(z) || !rasterize(x, y, g, ix, iy)) continue;
+        z = z + 0.0f;
+        lo = fminf(lo, z);
+        hi = fmaxf(hi, z);
+        ++used;
+    }
+    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+    __shared__ unsigned long long s_u[kBlock / 64];
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    used = wave_sum(used);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+        s_u[w] = used;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            lo = fminf(lo, s_lo[i]);
+            hi = fmaxf(hi, s_hi[i]);
+            used += s_u[i];
+        }
+        pmin[blockIdx.x] = lo;
+        pmax[blockIdx.x] = hi;
+        pused[blockIdx.x] = used;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_extent_final(const float* __restrict__ pmin,
+                                                         const float* __restrict__ pmax,
+                                                         const unsigned long long* __restrict__ pused,
+                                                         int nb, ExtentDev* __restrict__ out) {
+    float lo = INFINITY, hi = -INFINITY;
+    unsigned long long used = 0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) {
+        lo = fminf(lo, pmin[i]);
+        hi = fmaxf(hi, pmax[i]);
+        used += pused[i];
+    }
+    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+    __shared__ unsigned long long s_u[kBlock / 64];
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    used = wave_sum(used);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+        s_u[w] = used;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            lo = fminf(lo, s_lo[i]);
+            hi = fmaxf(hi, s_hi[i]);
+            used += s_u[i];
+        }
+        out->zmin = lo;
+        out->zmax = hi;
+        out->used = used;
+    }
+}
+
+constexpr int kExtentBlocks = 2048;
+
+// ------------------------------------------------------------------ binning
+__device__ __forceinline__ bool bin_point(const float* __restrict__ xyz, int64_t i, const GridDev& g,
+                                          int& tile, unsigned& cell, float& z) {
+    float x = xyz[3 * i], y = xyz[3 * i + 1];
+    z = xyz[3 * i + 2];
+    int ix, iy;
+    if (!isfinite(z) || !rasterize(x, y, g, ix, iy)) return false;
+    z = z + 0.0f;
+    int tx = ix / kBuildTileW, ty = iy / g.th;
+    tile = ty * g.ntx + tx;
+    cell = (unsigned)((iy - ty * g.th) * kBuildTileW + (ix - tx * kBuildTileW));
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(unsigned* __restrict__ p, int64_t n, unsigned v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+// Per-tile point counts.  Each workgroup counts its chunk in LDS and adds
+// the non-zero counters to the global ones.
+__global__ __launch_bounds__(kBlock) void k_tile_count(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                       unsigned* __restrict__ gcount) {
+    extern __shared__ unsigned s_cnt[];
+    const bool lds = g.ntiles <= kMaxLdsTiles;
+    if (lds)
+        for (int t = threadIdx.x; t < g.ntiles; t += kBlock) s_cnt[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kBinPPT;
+#pragma unroll 4
+    for (int j = 0; j < kBinPPT; ++j) {
+        int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        int tile;
+        unsigned cell;
+        float z;
+        if (i < n && bin_point(xyz, i, g, tile, cell, z)) {
+            if (lds) atomicAdd(&s_cnt[tile], 1u);
+            else atomicAdd(&gcount[tile], 1u);
+        }
+    }
+    __syncthreads();
+    if (lds)
+        for (int t = threadIdx.x; t < g.ntiles; t += kBlock)
+            if (s_cnt[t]) atomicAdd(&gcount[t], s_cnt[t]);
+}
+
+// Exclusive scan of the tile counts (one workgroup): off[0..ntiles], and
+// the scatter cursors start at the offsets.
+__global__ __launch_bounds__(1024) void k_scan_tiles(const unsigned* __restrict__ cnt, int ntiles,
+                                                     unsigned* __restrict__ off, unsigned* __restrict__ cursor) {
+    __shared__ unsigned s_part[1024];
+    const int per = (ntiles + 1023) / 1024;
+    const int b = threadIdx.x * per, e = min(b + per, ntiles);
+    unsigned sum = 0;
+    for (int i = b; i < e; ++i) sum += cnt[i];
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        unsigned v = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s_part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned run = s_part[threadIdx.x] - sum;
+    for (int i = b; i < e; ++i) {
+        off[i] = run;
+        cursor[i] = run;
+        run += cnt[i];
+    }
+    if (threadIdx.x == 1023) off[ntiles] = s_part[1023];
+}
+
+// Scatter of packed records (height, cell-in-tile[, point id]) into tile
+// order.  A workgroup counts its chunk per tile in LDS, reserves one range
+// per touched tile with a single global atomic, then places points with LDS
+// atomics.  The order inside a tile is not fixed; the tile reduce does not
+// depend on it.
+template <bool IDS>
+__global__ __launch_bounds__(kBlock) void k_tile_scatter(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                         unsigned* __restrict__ cursor, float* __restrict__ rz,
+                                                         unsigned* __restrict__ rmeta, int* __restrict__ rid) {
+    extern __shared__ unsigned s_mem[];
+    const bool lds = g.ntiles <= kMaxLdsTiles;
+    unsigned* s_cnt = s_mem;
+    unsigned* s_base = s_mem + (lds ? g.ntiles : 0);
+    if (lds)
+        for (int t = threadIdx.x; t < g.ntiles; t += kBlock) s_cnt[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kBinPPT;
+    int tile[kBinPPT];
+    unsigned cell[kBinPPT];
+    float zz[kBinPPT];
+#pragma unroll
+    for (int j = 0; j < kBinPPT; ++j) {
+        int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        tile[j] = -1;
+        if (i < n && bin_point(xyz, i, g, tile[j], cell[j], zz[j])) {
+            if (lds) atomicAdd(&s_cnt[tile[j]], 1u);
+        } else {
+            tile[j] = -1;
+        }
+    }
+    __syncthreads();
+    if (lds) {
+        for (int t = threadIdx.x; t < g.ntiles; t += kBlock) {
+            unsigned c = s_cnt[t];
+            if (c) s_base[t] = atomicAdd(&cursor[t], c);
+            s_cnt[t] = 0;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBinPPT; ++j) {
+        if (tile[j] < 0) continue;
+        unsigned pos = lds ? s_base[tile[j]] + atomicAdd(&s_cnt[tile[j]], 1u) : atomicAdd(&cursor[tile[j]], 1u);
+        rz[pos] = zz[j];
+        rmeta[pos] = cell[j];
+        if (IDS) rid[pos] = (int)(base + (int64_t)j * kBlock + threadIdx.x);
+    }
+}
+
+// ------------------------------------------------------------------ reduce
+__device__ __forceinline__ bool rec_less(float za, int ia, float zb, int ib, bool ids) {
+    return za < zb || (ids && za == zb && ia < ib);
+}
+
+// One cell: sort its heights (ties by point id) and sweep the planes.
+template <bool IDS>
+__device__ void sweep_cell(float* zs, int* is, int n, int ix, int iy, const GridDev& g, float zmin, float ds,
+                           int N, float* __restrict__ ground, float* __restrict__ ceil, int* __restrict__ ag,
+                           int* __restrict__ ac) {
+    for (int a = 1; a < n; ++a) {
+        float z = zs[a];
+        int id = IDS ? is[a] : 0;
+        int b = a - 1;
+        while (b >= 0 && rec_less(z, id, zs[b], IDS ? is[b] : 0, IDS)) {
+            zs[b + 1] = zs[b];
+            if (IDS) is[b + 1] = is[b];
+            --b;
+        }
+        zs[b + 1] = z;
+        if (IDS) is[b + 1] = id;
+    }
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    int64_t o = (int64_t)iy * g.nx + ix;
+    int j = 0, rs = 0;
+    float znext = n > 0 ? zs[0] : INFINITY;
+    for (int k = 0; k < N; ++k, o += plane) {
+        const float hk = plane_height(zmin, ds, k);
+        while (j < n && znext <= hk) {
+            if (j == 0 || znext != zs[j - 1]) rs = j;
+            ++j;
+            znext = j < n ? zs[j] : INFINITY;
+        }
+        ground[o] = j > 0 ? zs[j - 1] : -INFINITY;
+        ceil[o] = znext;
+        if (IDS) {
+            ag[o] = j > 0 ? is[rs] : -1;
+            ac[o] = j < n ? is[j] : -1;
+        }
+    }
+}
+
+// A cell with more points than the LDS holds: per plane, a block-wide
+// max/min reduction over the tile's records (ties to the lowest id).
+template <bool IDS>
+__device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __restrict__ rz,
+                          const unsigned* __restrict__ rmeta, const int* __restrict__ rid, int ix, int iy,
+                          const GridDev& g, float zmin, float ds, int N, float* __restrict__ ground,
+                          float* __restrict__ ceil, int* __restrict__ ag, int* __restrict__ ac) {
+    __shared__ float s_gz[kBlock], s_cz[kBlock];
+    __shared__ int s_gi[kBlock], s_ci[kBlock];
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    for (int k = 0; k < N; ++k) {
+        const float hk = plane_height(zmin, ds, k);
+        float gz = -INFINITY, cz = INFINITY;
+        int gi = 0x7fffffff, ci = 0x7fffffff;
+        for (unsigned r = r0 + threadIdx.x; r < r1; r += kBlock) {
+            if (rmeta[r] != c) continue;
+            float z = rz[r];
+            int id = IDS ? rid[r] : 0;
+            if (z <= hk) {
+                if (z > gz || (z == gz && id < gi)) { gz = z; gi = id; }
+            } else {
+                if (z < cz || (z == cz && id < ci)) { cz = z; ci = id; }
+            }
+        }
+        s_gz[threadIdx.x] = gz; s_gi[threadIdx.x] = gi;
+        s_cz[threadIdx.x] = cz; s_ci[threadIdx.x] = ci;
+        __syncthreads();
+        for (int s = kBlock / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                float z2 = s_gz[threadIdx.x + s];
+                int i2 = s_gi[threadIdx.x + s];
+                if (z2 > s_gz[threadIdx.x] || (z2 == s_gz[threadIdx.x] && i2 < s_gi[threadIdx.x])) {
+                    s_gz[threadIdx.x] = z2; s_gi[threadIdx.x] = i2;
+                }
+                z2 = s_cz[threadIdx.x + s];
+                i2 = s_ci[threadIdx.x + s];
+                if (z2 < s_cz[threadIdx.x] || (z2 == s_cz[threadIdx.x] && i2 < s_ci[threadIdx.x])) {
+                    s_cz[threadIdx.x] = z2; s_ci[threadIdx.x] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            int64_t o = (int64_t)k * plane + (int64_t)iy * g.nx + ix;
+            ground[o] = s_gz[0];
+            ceil[o] = s_cz[0];
+            if (IDS) {
+                ag[o] = isfinite(s_gz[0]) ? s_gi[0] : -1;
+                ac[o] = isfinite(s_cz[0]) ? s_ci[0] : -1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool IDS>
+__global__ __launch_bounds__(kBlock) void k_tile_reduce(const unsigned* __restrict__ off,
+                                                        const float* __restrict__ rz,
+                                                        const unsigned* __restrict__ rmeta,
+                                                        const int* __restrict__ rid, GridDev g, float zmin,
+                                                        float ds, int N, float* __restrict__ ground,
+                                                        float* __restrict__ ceil, int* __restrict__ ag,
+                                                        int* __restrict__ ac) {
+    constexpr int CAP = IDS ? kReduceCapIds : kReduceCap;
+    extern __shared__ unsigned s_mem[];
+    const int cells = kBuildTileW * g.th;
+    unsigned* s_cnt = s_mem;                 // cells
+    unsigned* s_start = s_cnt + cells;       // cells + 1
+    float* s_z = (float*)(s_start + cells + 1);
+    int* s_id = (int*)(s_z + CAP);
+
+    const int t = blockIdx.x;
+    const int tx = t % g.ntx, ty = t / g.ntx;
+    const unsigned r0 = off[t], r1 = off[t + 1];
+
+    for (int c = threadIdx.x; c < cells; c += kBlock) s_cnt[c] = 0;
+    __syncthreads();
+    for (unsigned r = r0 + threadIdx.x; r < r1; r += kBlock) atomicAdd(&s_cnt[rmeta[r]], 1u);
+    __syncthreads();
+    // exclusive scan of the per-cell counts; thread i owns a contiguous run
+    {
+        __shared__ unsigned s_part[kBlock];
+        const int per = (cells + kBlock - 1) / kBlock;
+        const int b = threadIdx.x * per, e = min(b + per, cells);
+        unsigned sum = 0;
+        for (int i = b; i < e; ++i) sum += s_cnt[i];
+        s_part[threadIdx.x] = sum;
+        __syncthreads();
+        for (int d = 1; d < kBlock; d <<= 1) {
+            unsigned v = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0u;
+            __syncthreads();
+            s_part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        unsigned run = s_part[threadIdx.x] - sum;
+        for (int i = b; i < e; ++i) {
+            s_start[i] = run;
+            run += s_cnt[i];
+        }
+        if (threadIdx.x == kBlock - 1) s_start[cells] = s_part[kBlock - 1];
+    }
+    __syncthreads();
+
+    int c_lo = 0;
+    while (c_lo < cells) {
+        // largest group [c_lo, c_hi) whose records fit in LDS
+        int lo = c_lo + 1, hi = cells;
+        if (s_start[c_lo + 1] - s_start[c_lo] > (unsigned)CAP) {
+            hi = c_lo + 1;
+        } else {
+            while (lo < hi) {
+                int mid = (lo + hi + 1) / 2;
+                if (s_start[mid] - s_start[c_lo] <= (unsigned)CAP) lo = mid;
+                else hi = mid - 1;
+            }
+            hi = lo;
+        }
+        const int c_hi = hi;
+        const unsigned g0 = s_start[c_lo];
+        if (c_hi == c_lo + 1 && s_start[c_hi] - g0 > (unsigned)CAP) {
+            const int ix = tx * kBuildTileW + (c_lo % kBuildTileW);
+            const int iy = ty * g.th + c_lo / kBuildTileW;
+            huge_cell<IDS>((unsigned)c_lo, r0, r1, rz, rmeta, rid, ix, iy, g, zmin, ds, N, ground, ceil, ag, ac);
+        } else {
+            for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) s_cnt[c] = 0;
+            __syncthreads();
+            for (unsigned r = r0 + threadIdx.x; r < r1; r += kBlock) {
+                unsigned c = rmeta[r];
+                if ((int)c < c_lo || (int)c >= c_hi) continue;
+                unsigned pos = s_start[c] - g0 + atomicAdd(&s_cnt[c], 1u);
+                s_z[pos] = rz[r];
+                if (IDS) s_id[pos] = rid[r];
+            }
+            __syncthreads();
+            for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) {
+                const int ix = tx * kBuildTileW + (c % kBuildTileW);
+                const int iy = ty * g.th + c / kBuildTileW;
+                if (ix >= g.nx || iy >= g.ny) continue;
+                const unsigned s = s_start[c] - g0;
+                sweep_cell<IDS>(s_z + s, s_id + s, (int)(s_start[c + 1] - s_start[c]), ix, iy, g, zmin, ds, N,
+                                ground, ceil, ag, ac);
+            }
+        }
+        __syncthreads();
+        c_lo = c_hi;
+    }
+}
+
+inline size_t reduce_lds_bytes(const GridDev& g, bool ids) {
+    const int cells = kBuildTileW * g.th;
+    return sizeof(unsigned) * (2 * cells + 1) + (ids ? (size_t)kReduceCapIds * 8 : (size_t)kReduceCap * 4);
+}
+
+struct BuildWs {
+    unsigned *count, *off, *cursor;
+    float* rz;
+    unsigned* rmeta;
+    int* rid;
+    size_t bytes;
+};
+
+BuildWs carve_build_ws(void* base, int64_t n, const GridDev& g, bool ids) {
+    BuildWs w{};
+    char* p = (char*)base;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* r = p ? p + o : nullptr;
+        o += align_up(bytes);
+        return r;
+    };
+    w.count = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
+    w.off = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
+    w.cursor = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
+    w.rz = (float*)take(sizeof(float) * (size_t)n);
+    w.rmeta = (unsigned*)take(sizeof(unsigned) * (size_t)n);
+    w.rid = ids ? (int*)take(sizeof(int) * (size_t)n) : nullptr;
+    w.bytes = o;
+    return w;
+}
+
+}  // namespace
+
+size_t extent_ws_bytes(int64_t) {
+    return align_up(sizeof(float) * kExtentBlocks) * 2 + align_up(sizeof(unsigned long long) * kExtentBlocks) +
+           align_up(sizeof(ExtentDev));
+}
+
+pct_status launch_extent(const float* xyz, int64_t n, const GridDev& g, void* ws, ExtentDev* d_out,
+                         hipStream_t s) {
+    char* p = (char*)ws;
+    float* pmin = (float*)p;
+    float* pmax = (float*)(p + align_up(sizeof(float) * kExtentBlocks));
+    unsigned long long* pused = (unsigned long long*)(p + 2 * align_up(sizeof(float) * kExtentBlocks));
+    int nb = (int)std::min<int64_t>(kExtentBlocks, std::max<int64_t>(1, (n + kBlock * 8 - 1) / (kBlock * 8)));
+    hipLaunchKernelGGL(k_extent, dim3(nb), dim3(kBlock), 0, s, xyz, n, g, pmin, pmax, pused);
+    PCT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_extent_final, dim3(1), dim3(kBlock), 0, s, pmin, pmax, pused, nb, d_out);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+size_t build_ws_bytes(int64_t n, const GridDev& g, bool ids) { return carve_build_ws(nullptr, n, g, ids).bytes; }
+
+pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmin, float ds, int N, float* ground,
+                        float* ceil, int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes, hipStream_t s) {
+    const bool ids = ag != nullptr;
+    BuildWs w = carve_build_ws(ws, n, g, ids);
+    if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "build workspace too small: %zu < %zu", ws_bytes, w.bytes);
+    const bool lds = g.ntiles <= kMaxLdsTiles;
+    const int fill_blocks = std::min(1024, (g.ntiles + kBlock) / kBlock + 1);
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(kBlock), 0, s, w.count, (int64_t)g.ntiles + 1, 0u);
+    PCT_LAUNCH_CHECK();
+    const int64_t chunks = (n + (int64_t)kBlock * kBinPPT - 1) / ((int64_t)kBlock * kBinPPT);
+    if (chunks > 0) {
+        hipLaunchKernelGGL(k_tile_count, dim3((unsigned)chunks), dim3(kBlock), lds ? sizeof(unsigned) * g.ntiles : 0, s,
+                           xyz, n, g, w.count);
+        PCT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
+    PCT_LAUNCH_CHECK();
+    if (chunks > 0) {
+        size_t lds_b = lds ? 2 * sizeof(unsigned) * g.ntiles : 0;
+        if (ids)
+            hipLaunchKernelGGL(k_tile_scatter<true>, dim3((unsigned)chunks), dim3(kBlock), lds_b, s, xyz, n, g,
+                               w.cursor, w.rz, w.rmeta, w.rid);
+        else
+            hipLaunchKernelGGL(k_tile_scatter<false>, dim3((unsigned)chunks), dim3(kBlock), lds_b, s, xyz, n, g,
+                               w.cursor, w.rz, w.rmeta, w.rid);
+        PCT_LAUNCH_CHECK();
+    }
+    const size_t rl = reduce_lds_bytes(g, ids);
+    if (ids)
+        hipLaunchKernelGGL(k_tile_reduce<true>, dim3(g.ntiles), dim3(kBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
+                           zmin, ds, N, ground, ceil, ag, ac);
+    else
+        hipLaunchKernelGGL(k_tile_reduce<false>, dim3(g.ntiles), dim3(kBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
+                           zmin, ds, N, ground, ceil, ag, ac);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+GridDev make_grid_dev(const pct_grid& gr) {
+    GridDev g{};
+    g.x0 = gr.x0;
+    g.y0 = gr.y0;
+    g.res = gr.res;
+    g.nx = gr.nx;
+    g.ny = gr.ny;
+    g.fnx = (float)gr.nx;
+    g.fny = (float)gr.ny;
+    g.ntx = (gr.nx + kBuildTileW - 1) / kBuildTileW;
+    g.th = 8;
+    while (g.th < 32 && (int64_t)g.ntx * ((gr.ny + g.th - 1) / g.th) > kMaxLdsTiles) g.th *= 2;
+    g.nty = (gr.ny + g.th - 1) / g.th;
+    g.ntiles = g.ntx * g.nty;
+    return g;
+}
+
+}  // namespace pct

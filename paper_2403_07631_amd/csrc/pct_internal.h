@@ -1,0 +1,109 @@
+// Internal declarations of libpct: device parameter blocks, launch helpers
+// and the kernel launchers shared between the API and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "pct.h"
+
+namespace pct {
+
+// ---------------------------------------------------------------- errors
+pct_status fail(pct_status code, const char* fmt, ...);
+void clear_error();
+
+#define PCT_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::pct::fail(PCT_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define PCT_LAUNCH_CHECK()                                                                \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return ::pct::fail(PCT_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- grids
+// Construction tiles are 64 cells wide (one wavefront per row) and
+// `th` cells tall; th grows with the grid so that the tile count fits the
+// LDS-privatised counters of the binning kernels.
+constexpr int kBuildTileW = 64;
+constexpr int kMaxLdsTiles = 8192;
+
+struct GridDev {
+    float x0, y0, res, fnx, fny;
+    int nx, ny;
+    int th, ntx, nty;   // construction tiling
+    int ntiles;
+};
+
+GridDev make_grid_dev(const pct_grid& g);
+
+// On-device rasterisation (Sec. III-A): one FP32 subtraction and one
+// correctly rounded FP32 division per axis, then the half-open range test.
+__device__ __forceinline__ bool rasterize(float x, float y, const GridDev& g, int& ix, int& iy) {
+    float qx = (x - g.x0) / g.res;
+    float qy = (y - g.y0) / g.res;
+    if (!(qx >= 0.0f && qx < g.fnx)) return false;
+    if (!(qy >= 0.0f && qy < g.fny)) return false;
+    ix = (int)qx;
+    iy = (int)qy;
+    return true;
+}
+
+// Plane k: z_min + (k+1) * d_s as one FP32 multiply and one FP32 add
+// (the library is compiled with contraction off, so no FMA forms here).
+__host__ __device__ __forceinline__ float plane_height(float zmin, float ds, int k) {
+    float step = (float)(k + 1) * ds;
+    return zmin + step;
+}
+
+// ---------------------------------------------------------------- extent
+struct ExtentDev {
+    float zmin, zmax;
+    unsigned long long used;
+};
+
+// ---------------------------------------------------------------- eval
+constexpr int kEvalTileW = 64;
+constexpr int kEvalTileH = 16;
+constexpr int kKmax = PCT_MAX_KERNEL_RADIUS + 1;
+
+struct EvalParams {
+    int nx, ny, N, R;
+    long long plane;
+    float d_min, d_ref, cB, alpha_d;
+    float Tb;    // barrier:  max(|dx|, |dy|) > theta_b * 2r   (dx, dy: raw ground differences)
+    float Ts2;   // gentle:   dx^2 + dy^2 < (theta_s * 2r)^2
+    float As;    // gentle cost  alpha_s / (theta_s * 2r)^2 * (dx^2 + dy^2)
+    float Ab;    // step cost    alpha_b / (theta_b * 2r)^2 * max(dx^2, dy^2)
+    int rp, kp;  // patch radius, count threshold floor(theta_p * P)
+    float K[kKmax][kKmax];  // K[a][j]: Eq. (6) weight at horizontal offset a, vertical offset j
+};
+
+pct_status make_eval_params(const pct_robot& r, const pct_grid& g, int N, EvalParams* out);
+
+// ---------------------------------------------------------------- launchers
+pct_status launch_extent(const float* xyz, int64_t n, const GridDev& g, void* ws, ExtentDev* d_out,
+                         hipStream_t s);
+size_t extent_ws_bytes(int64_t n);
+
+size_t build_ws_bytes(int64_t n, const GridDev& g, bool ids);
+pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmin, float ds, int N,
+                        float* ground, float* ceil, int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes,
+                        hipStream_t s);
+
+size_t eval_ws_bytes(int N, int n_robots);
+pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost,
+                       hipStream_t s);
+pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
+                           void* ws, hipStream_t s);
+
+}  // namespace pct

@@ -146,3 +146,15 @@ def test_invariants_random_clouds(oracle_lib, seed):
     # a cell with points has ground or ceiling in every slice
     occupied = np.isfinite(eG) | np.isfinite(eC)
     assert np.all(occupied == occupied[0:1])
+
+
+def test_window_build_equals_full_build(oracle_lib):
+    """The windowed loop (used for full-size checks) is the full loop cut to
+    the window, including windows at the grid edge."""
+    sc = scenes.config0_scene()
+    tm = oracle_lib.tomogram(sc.points, sc.grid)
+    full = (tm["ground"], tm["ceil"], tm["arg_ground"], tm["arg_ceil"])
+    for wx0, wy0, wnx, wny in [(37, 150, 50, 21), (0, 0, 7, 9), (190, 180, 10, 20)]:
+        w = oracle_lib.build_window(sc.points, sc.grid, tm["h"], wx0, wy0, wnx, wny)
+        for a, b in zip(w, full):
+            np.testing.assert_array_equal(a, b[:, wy0:wy0 + wny, wx0:wx0 + wnx])
