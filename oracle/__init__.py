@@ -83,22 +83,19 @@ def lib():
 
 
 def _register_grad(L):
-    """Signatures of the sampling and adjoint functions, when present."""
+    """Signatures of the sampling and adjoint functions."""
     f32p, f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
-    i32p = C.POINTER(C.c_int32)
-    if hasattr(L, "o_sample_fwd"):
-        L.o_sample_fwd.argtypes = [f64p, f32p, C.c_int, C.c_int, C.c_int, C.POINTER(Grid),
-                                   C.c_double, C.c_double, f32p, i32p, C.c_int, C.c_int, f64p]
-    if hasattr(L, "o_sample_bwd"):
-        L.o_sample_bwd.argtypes = [f64p, f32p, C.c_int, C.c_int, C.c_int, C.POINTER(Grid),
-                                   C.c_double, C.c_double, f32p, i32p, C.c_int, C.c_int, f64p,
-                                   f64p, f64p, f64p]
-    if hasattr(L, "o_eval_bwd"):
-        L.o_eval_bwd.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double,
-                                 C.POINTER(Robot), f64p, f64p, f64p]
-        L.o_eval_bwd.restype = C.c_int
-    if hasattr(L, "o_route"):
-        L.o_route.argtypes = [f64p, f64p, i32p, i32p, C.c_int64, C.c_int64, f64p]
+    i32p, u8p = C.POINTER(C.c_int32), C.POINTER(C.c_uint8)
+    L.o_sample_fwd.argtypes = [f64p, f32p, C.c_int, C.c_int, C.c_int, C.POINTER(Grid), C.c_double, C.c_double,
+                               f32p, i32p, C.c_int, C.c_int, f64p]
+    L.o_sample_bwd.argtypes = [f64p, f32p, C.c_int, C.c_int, C.c_int, C.POINTER(Grid), C.c_double, C.c_double,
+                               f32p, i32p, C.c_int, C.c_int, f64p, f64p, f64p, f64p]
+    L.o_eval_bwd.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(Robot), f64p, f64p,
+                             f64p, u8p, C.c_double]
+    L.o_eval_bwd.restype = C.c_int
+    L.o_route.argtypes = [f64p, f64p, i32p, i32p, C.c_int64, C.c_int64, f64p]
+    L.o_eval_signature.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(Robot), i32p]
+    L.o_eval_signature.restype = C.c_int
 
 
 def threads() -> int:
@@ -288,3 +285,78 @@ def simplify_check(eG, lo, hi, c_barrier, tol, keep):
     N, ny, nx = eG.shape
     return int(lib().o_simplify_check(_p(eG, C.c_float), _p(lo, C.c_double), _p(hi, C.c_double),
                                       N, nx, ny, float(np.float32(c_barrier)), tol, _p(kp, C.c_uint8)))
+
+
+# ---------------------------------------------------------------------------
+# trajectory cost sampling and adjoints
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def sample_fwd(cT, eG, grid, w_z, d_ref, wp, slices):
+    """Per-trajectory cost f [T] (FP64)."""
+    cT, eG = _f64(cT), _f32(eG)
+    wp = _f32(wp)
+    sl = np.ascontiguousarray(slices, dtype=np.int32)
+    T, W = sl.shape
+    N, ny, nx = eG.shape
+    f = np.empty(T, np.float64)
+    g = grid_struct(grid)
+    lib().o_sample_fwd(_p(cT, C.c_double), _p(eG, C.c_float), N, nx, ny, C.byref(g), float(w_z), float(d_ref),
+                       _p(wp, C.c_float), _p(sl, C.c_int32), T, W, _p(f, C.c_double))
+    return f
+
+
+def sample_bwd(cT, eG, grid, w_z, d_ref, wp, slices, gf):
+    """(gwp [T,W,3], gcT [N,ny,nx], gG [N,ny,nx]) for upstream gradient gf [T]."""
+    cT, eG = _f64(cT), _f32(eG)
+    wp = _f32(wp)
+    sl = np.ascontiguousarray(slices, dtype=np.int32)
+    T, W = sl.shape
+    N, ny, nx = eG.shape
+    gf = _f64(gf)
+    gwp = np.zeros((T, W, 3), np.float64)
+    gcT = np.zeros((N, ny, nx), np.float64)
+    gG = np.zeros((N, ny, nx), np.float64)
+    g = grid_struct(grid)
+    lib().o_sample_bwd(_p(cT, C.c_double), _p(eG, C.c_float), N, nx, ny, C.byref(g), float(w_z), float(d_ref),
+                       _p(wp, C.c_float), _p(sl, C.c_int32), T, W, _p(gf, C.c_double), _p(gwp, C.c_double),
+                       _p(gcT, C.c_double), _p(gG, C.c_double))
+    return gwp, gcT, gG
+
+
+def eval_bwd(eG, eC, res, robot, gcT, tau=4e-6):
+    """(gG, gC, uncertain) for upstream gradient gcT [N,ny,nx]."""
+    eG, eC, gcT = _f32(eG), _f32(eC), _f64(gcT)
+    N, ny, nx = eG.shape
+    gG = np.zeros((N, ny, nx), np.float64)
+    gC = np.zeros((N, ny, nx), np.float64)
+    unc = np.zeros((N, ny, nx), np.uint8)
+    rb = robot_struct(robot)
+    R = lib().o_eval_bwd(_p(eG, C.c_float), _p(eC, C.c_float), N, nx, ny, float(np.float32(res)), C.byref(rb),
+                         _p(gcT, C.c_double), _p(gG, C.c_double), _p(gC, C.c_double), _p(unc, C.c_uint8), tau)
+    if R < 0:
+        raise ValueError("invalid inflation kernel parameters")
+    return gG, gC, unc.astype(bool)
+
+
+def route(gG, gC, aG, aC, n_points):
+    """dL/dz per point from dL/de^G, dL/de^C and the recorded point ids."""
+    gG, gC = _f64(gG), _f64(gC)
+    aG = np.ascontiguousarray(aG, np.int32)
+    aC = np.ascontiguousarray(aC, np.int32)
+    gz = np.zeros(n_points, np.float64)
+    lib().o_route(_p(gG, C.c_double), _p(gC, C.c_double), _p(aG, C.c_int32), _p(aC, C.c_int32), gG.size,
+                  n_points, _p(gz, C.c_double))
+    return gz
+
+
+def eval_signature(eG, eC, res, robot):
+    eG, eC = _f32(eG), _f32(eC)
+    N, ny, nx = eG.shape
+    sig = np.empty((N, ny, nx), np.int32)
+    rb = robot_struct(robot)
+    lib().o_eval_signature(_p(eG, C.c_float), _p(eC, C.c_float), N, nx, ny, float(np.float32(res)), C.byref(rb),
+                           _p(sig, C.c_int32))
+    return sig

@@ -526,3 +526,306 @@ int o_simplify_check(const float* eG, const double* lo, const double* hi, int N,
     }
     return -1;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Trajectory cost sampling (Sec. III-E, Eq. (11)) and adjoints, in FP64.
+ *
+ * The trajectory optimisation penalises the travel cost C along the
+ * trajectory and the deviation of the body height from Z_ref = e^G + d_ref.
+ * Reading: a waypoint (x, y, z) on slice k contributes
+ *     f = C_k(x, y) + w_z (z - G_k(x, y) - d_ref)^2
+ * where C_k and G_k are cell-centred bilinear interpolations of c^T_k and
+ * e^G_k (clamped to the grid edge, with zero slope across the clamp).  The
+ * height term is dropped when any of the four ground corners is missing.  A
+ * trajectory's cost is the sum over its waypoints.  Waypoints with a
+ * non-finite coordinate or a slice outside [0, N) contribute nothing. */
+
+static void o_axis(double q, int n, int* i0, int* i1, double* f, double* dq) {
+    if (n == 1) { *i0 = *i1 = 0; *f = 0.0; *dq = 0.0; return; }
+    double qc = q;
+    int clamped = 0;
+    if (q < 0.0) { qc = 0.0; clamped = 1; }
+    else if (q > (double)(n - 1)) { qc = (double)(n - 1); clamped = 1; }
+    int a = (int)floor(qc);
+    if (a > n - 2) a = n - 2;
+    *i0 = a;
+    *i1 = a + 1;
+    *f = qc - a;
+    *dq = clamped ? 0.0 : 1.0;
+}
+
+typedef struct {
+    int ok, hterm;
+    int64_t c00, c10, c01, c11;
+    double fu, fv, du, dv, C, G, res;
+} o_bil;
+
+static o_bil o_bilinear(const double* cT, const float* eG, int N, int nx, int ny, const o_grid* g,
+                        const float* wp, int k) {
+    o_bil b;
+    memset(&b, 0, sizeof b);
+    if (k < 0 || k >= N || !isfinite(wp[0]) || !isfinite(wp[1]) || !isfinite(wp[2])) return b;
+    b.ok = 1;
+    double r = (double)g->res;
+    double u = ((double)wp[0] - (double)g->x0) / r - 0.5;
+    double v = ((double)wp[1] - (double)g->y0) / r - 0.5;
+    int i0, i1, j0, j1;
+    o_axis(u, nx, &i0, &i1, &b.fu, &b.du);
+    o_axis(v, ny, &j0, &j1, &b.fv, &b.dv);
+    b.du /= r;
+    b.dv /= r;
+    if (nx == 1) i1 = 0;
+    if (ny == 1) j1 = 0;
+    int64_t base = (int64_t)k * nx * ny;
+    b.c00 = base + (int64_t)j0 * nx + i0;
+    b.c10 = base + (int64_t)j0 * nx + i1;
+    b.c01 = base + (int64_t)j1 * nx + i0;
+    b.c11 = base + (int64_t)j1 * nx + i1;
+    double w00 = (1 - b.fu) * (1 - b.fv), w10 = b.fu * (1 - b.fv), w01 = (1 - b.fu) * b.fv, w11 = b.fu * b.fv;
+    b.C = w00 * cT[b.c00] + w10 * cT[b.c10] + w01 * cT[b.c01] + w11 * cT[b.c11];
+    b.hterm = isfinite(eG[b.c00]) && isfinite(eG[b.c10]) && isfinite(eG[b.c01]) && isfinite(eG[b.c11]);
+    if (b.hterm)
+        b.G = w00 * eG[b.c00] + w10 * eG[b.c10] + w01 * eG[b.c01] + w11 * eG[b.c11];
+    return b;
+}
+
+void o_sample_fwd(const double* cT, const float* eG, int N, int nx, int ny, const o_grid* g, double w_z,
+                  double d_ref, const float* wp, const int32_t* slice, int T, int W, double* f) {
+    for (int t = 0; t < T; ++t) {
+        double acc = 0.0;
+        for (int w = 0; w < W; ++w) {
+            const float* p = wp + 3 * ((int64_t)t * W + w);
+            o_bil b = o_bilinear(cT, eG, N, nx, ny, g, p, slice[(int64_t)t * W + w]);
+            if (!b.ok) continue;
+            acc += b.C;
+            if (b.hterm) {
+                double e = (double)p[2] - b.G - d_ref;
+                acc += w_z * e * e;
+            }
+        }
+        f[t] = acc;
+    }
+}
+
+/* Adjoint of o_sample_fwd: gwp [T][W][3] (overwritten), gcT and gG
+ * [N][ny][nx] (accumulated). */
+void o_sample_bwd(const double* cT, const float* eG, int N, int nx, int ny, const o_grid* g, double w_z,
+                  double d_ref, const float* wp, const int32_t* slice, int T, int W, const double* gf,
+                  double* gwp, double* gcT, double* gG) {
+    for (int t = 0; t < T; ++t)
+        for (int w = 0; w < W; ++w) {
+            int64_t i = (int64_t)t * W + w;
+            const float* p = wp + 3 * i;
+            double* gp = gwp + 3 * i;
+            gp[0] = gp[1] = gp[2] = 0.0;
+            o_bil b = o_bilinear(cT, eG, N, nx, ny, g, p, slice[i]);
+            if (!b.ok) continue;
+            double s = gf[t];
+            double w00 = (1 - b.fu) * (1 - b.fv), w10 = b.fu * (1 - b.fv), w01 = (1 - b.fu) * b.fv, w11 = b.fu * b.fv;
+            /* travel cost term */
+            double dCdu = (1 - b.fv) * (cT[b.c10] - cT[b.c00]) + b.fv * (cT[b.c11] - cT[b.c01]);
+            double dCdv = (1 - b.fu) * (cT[b.c01] - cT[b.c00]) + b.fu * (cT[b.c11] - cT[b.c10]);
+            gp[0] += s * dCdu * b.du;
+            gp[1] += s * dCdv * b.dv;
+            gcT[b.c00] += s * w00;
+            gcT[b.c10] += s * w10;
+            gcT[b.c01] += s * w01;
+            gcT[b.c11] += s * w11;
+            if (b.hterm) {
+                double e = (double)p[2] - b.G - d_ref;
+                double de = 2.0 * w_z * e * s;   /* d/d(z - G) */
+                double dGdu = (1 - b.fv) * ((double)eG[b.c10] - eG[b.c00]) + b.fv * ((double)eG[b.c11] - eG[b.c01]);
+                double dGdv = (1 - b.fu) * ((double)eG[b.c01] - eG[b.c00]) + b.fu * ((double)eG[b.c11] - eG[b.c10]);
+                gp[0] -= de * dGdu * b.du;
+                gp[1] -= de * dGdv * b.dv;
+                gp[2] += de;
+                gG[b.c00] -= de * w00;
+                gG[b.c10] -= de * w10;
+                gG[b.c01] -= de * w01;
+                gG[b.c11] -= de * w11;
+            }
+        }
+}
+
+/* Adjoint of the traversability evaluation (Eqs. (1)-(6)): given dL/dc^T,
+ * accumulate dL/de^G and dL/de^C.
+ *   inflation: c^T(p) = K(t*) c^init(p + t*) for the maximising tap t*
+ *     (first maximum in row-major window order, rows outer), so the
+ *     gradient goes to c^init(p + t*) times K(t*);
+ *   Eq. (5): passes to c^I and c^G where c^I + c^G < c^B, else stops;
+ *   Eq. (1): d c^I / d e^G = alpha_d = -d c^I / d e^C where
+ *     alpha_d (d_ref - d^I) > 0 and d^I >= d_min; zero otherwise;
+ *   Eqs. (3)-(4): gentle cost alpha_s |g|^2 / theta_s^2 and step cost
+ *     alpha_b max(g_x^2, g_y^2) / theta_b^2 (the larger axis; x on a tie)
+ *     differentiate through the central differences g = (e+ - e-) / 2r;
+ *     barrier branches and the neighbour count have no gradient.
+ * `uncertain` (nullable, [N][ny][nx]) marks gradient entries that an FP32
+ * evaluation may route differently: the cells touched from a window whose
+ * maximum is within tau of a different tap's product, or whose c^init has a
+ * predicate, the clip, the interval kink or the step axis within tau. */
+static int o_cell_uncertain(const o_cell* o, const o_robot* rb, int namb_gentle, int kp, double tau) {
+    if (o->branch == 0) return 0;
+    if (o_near(o->dI, rb->d_min, tau) || o_near(o->mxy, rb->theta_b, tau) || o_near(o->mgrad, rb->theta_s, tau))
+        return 1;
+    if (namb_gentle) return 1;
+    (void)kp;
+    double s = o->cI + o->cG;
+    if (o_near(s, rb->c_barrier, tau)) return 1;
+    if (!(o->dI < rb->d_min) && o_near((double)rb->d_ref - o->dI, 0.0, tau)) return 1;
+    if (o->branch == 3 && o_near(fabs(o->gx), fabs(o->gy), tau)) return 1;
+    return 0;
+}
+
+int o_eval_bwd(const float* eG, const float* eC, int N, int nx, int ny, double res, const o_robot* rb,
+               const double* gcT, double* gG, double* gC, uint8_t* uncertain, double tau) {
+    double K[(2 * O_RMAX + 1) * (2 * O_RMAX + 1)];
+    int R = o_kernel(res, rb->d_inf, rb->d_sm, O_RMAX, K);
+    if (R < 0) return R;
+    const int w = 2 * O_RMAX + 1;
+    const int64_t plane = (int64_t)nx * ny;
+    const int kp = o_patch_threshold(rb);
+    const double cB = rb->c_barrier;
+    o_cell* cells = (o_cell*)malloc(sizeof(o_cell) * plane);
+    uint8_t* unc = (uint8_t*)malloc(plane);
+    for (int k = 0; k < N; ++k) {
+        const float* g = eG + k * plane;
+        const float* c = eC + k * plane;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) cells[(int64_t)y * nx + x] = o_eval_cell(g, c, nx, ny, res, rb, x, y);
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                /* ambiguous gentle flags among the patch neighbours */
+                int namb = 0, rp = rb->patch_radius;
+                for (int dy = -rp; dy <= rp; ++dy)
+                    for (int dx = -rp; dx <= rp; ++dx) {
+                        int qx = x + dx, qy = y + dy;
+                        if ((dx || dy) && qx >= 0 && qy >= 0 && qx < nx && qy < ny) {
+                            const o_cell* q = &cells[(int64_t)qy * nx + qx];
+                            namb += q->branch != 0 && o_near(q->mgrad, rb->theta_s, tau);
+                        }
+                    }
+                const o_cell* o = &cells[(int64_t)y * nx + x];
+                int cnt_near = namb && (o->branch == 3 || o->branch == 4);
+                unc[(int64_t)y * nx + x] = (uint8_t)o_cell_uncertain(o, rb, cnt_near, kp, tau);
+            }
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t ip = k * plane + (int64_t)y * nx + x;
+                double gc = gcT[ip];
+                if (gc == 0.0) continue;
+                /* the maximising tap (first in window order) and the runner-up */
+                double best = -INFINITY, second = -INFINITY;
+                int bx = 0, by = 0, sx = -1, sy = -1;
+                for (int n = -R; n <= R; ++n)
+                    for (int m = -R; m <= R; ++m) {
+                        double kw = K[(n + O_RMAX) * w + (m + O_RMAX)];
+                        int qx = x + m, qy = y + n;
+                        if (kw <= 0.0 || qx < 0 || qy < 0 || qx >= nx || qy >= ny) continue;
+                        double v = kw * cells[(int64_t)qy * nx + qx].cinit;
+                        if (v > best) {
+                            second = best; sx = bx; sy = by;
+                            best = v; bx = qx; by = qy;
+                        } else if (v > second) {
+                            second = v; sx = qx; sy = qy;
+                        }
+                    }
+                double kw = K[(by - y + O_RMAX) * w + (bx - x + O_RMAX)];
+                int tie = sx >= 0 && best - second <= tau * fmax(1.0, best) &&
+                          !(K[(sy - y + O_RMAX) * w + (sx - x + O_RMAX)] == kw &&
+                            cells[(int64_t)sy * nx + sx].cinit == cells[(int64_t)by * nx + bx].cinit);
+                const o_cell* q = &cells[(int64_t)by * nx + bx];
+                int64_t iq = k * plane + (int64_t)by * nx + bx;
+                if (uncertain && (tie || unc[(int64_t)by * nx + bx])) {
+                    int pts[2][2] = {{bx, by}, {sx, sy}};
+                    for (int a = 0; a < (tie ? 2 : 1); ++a)
+                        for (int d = 0; d < 5; ++d) {
+                            int ux = pts[a][0] + (d == 1) - (d == 2), uy = pts[a][1] + (d == 3) - (d == 4);
+                            if (ux >= 0 && uy >= 0 && ux < nx && uy < ny) uncertain[k * plane + (int64_t)uy * nx + ux] = 1;
+                        }
+                }
+                double gq = kw * gc;
+                if (q->branch == 0) continue;
+                if (!(q->cI + q->cG < cB)) continue;
+                if (!(q->dI < (double)rb->d_min) && (double)rb->alpha_d * ((double)rb->d_ref - q->dI) > 0.0) {
+                    gG[iq] += (double)rb->alpha_d * gq;
+                    gC[iq] -= (double)rb->alpha_d * gq;
+                }
+                double dgx = 0.0, dgy = 0.0;   /* dL/dg^x, dL/dg^y */
+                if (q->branch == 2) {
+                    double ts = rb->theta_s;
+                    dgx = 2.0 * rb->alpha_s * q->gx / (ts * ts) * gq;
+                    dgy = 2.0 * rb->alpha_s * q->gy / (ts * ts) * gq;
+                } else if (q->branch == 3) {
+                    double tb = rb->theta_b;
+                    if (fabs(q->gx) >= fabs(q->gy)) dgx = 2.0 * rb->alpha_b * q->gx / (tb * tb) * gq;
+                    else dgy = 2.0 * rb->alpha_b * q->gy / (tb * tb) * gq;
+                }
+                if (dgx != 0.0) {
+                    gG[iq + 1] += dgx / (2.0 * res);
+                    gG[iq - 1] -= dgx / (2.0 * res);
+                }
+                if (dgy != 0.0) {
+                    gG[iq + nx] += dgy / (2.0 * res);
+                    gG[iq - nx] -= dgy / (2.0 * res);
+                }
+            }
+    }
+    free(cells);
+    free(unc);
+    return R;
+}
+
+/* Adjoint of the construction: each stored ground or ceiling value is the
+ * height of one point (its recorded id), so its gradient is added to that
+ * point's z.  gz [n] is accumulated. */
+void o_route(const double* gG, const double* gC, const int32_t* aG, const int32_t* aC, int64_t ncs, int64_t n,
+             double* gz) {
+    for (int64_t i = 0; i < ncs; ++i) {
+        if (aG[i] >= 0 && aG[i] < n) gz[aG[i]] += gG[i];
+        if (aC[i] >= 0 && aC[i] < n) gz[aC[i]] += gC[i];
+    }
+}
+
+/* Discrete decisions of the evaluation per cell-slice, for finite-difference
+ * checks (a central difference is exact when no decision changes inside the
+ * step): bits 0-2 the Eq. (1)-(4) branch of c^init, bit 3 the Eq. (5) clip,
+ * bits 4-5 the regime of c^I (barrier / positive / zero), bit 6 the step
+ * axis, bits 8.. the maximising tap of the inflation window. */
+int o_eval_signature(const float* eG, const float* eC, int N, int nx, int ny, double res, const o_robot* rb,
+                     int32_t* sig) {
+    double K[(2 * O_RMAX + 1) * (2 * O_RMAX + 1)];
+    int R = o_kernel(res, rb->d_inf, rb->d_sm, O_RMAX, K);
+    if (R < 0) return R;
+    const int w = 2 * O_RMAX + 1;
+    const int64_t plane = (int64_t)nx * ny;
+    o_cell* cells = (o_cell*)malloc(sizeof(o_cell) * plane);
+    for (int k = 0; k < N; ++k) {
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                cells[(int64_t)y * nx + x] = o_eval_cell(eG + k * plane, eC + k * plane, nx, ny, res, rb, x, y);
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const o_cell* o = &cells[(int64_t)y * nx + x];
+                int code = o->branch;
+                if (o->branch) {
+                    code |= (o->cI + o->cG >= rb->c_barrier) << 3;
+                    int reg = o->dI < (double)rb->d_min ? 0 : ((double)rb->d_ref - o->dI > 0.0 ? 1 : 2);
+                    code |= reg << 4;
+                    code |= (o->branch == 3 && !(fabs(o->gx) >= fabs(o->gy))) << 6;
+                }
+                double best = -INFINITY;
+                int arg = 0, idx = 0;
+                for (int n = -R; n <= R; ++n)
+                    for (int m = -R; m <= R; ++m, ++idx) {
+                        double kw = K[(n + O_RMAX) * w + (m + O_RMAX)];
+                        int qx = x + m, qy = y + n;
+                        if (kw <= 0.0 || qx < 0 || qy < 0 || qx >= nx || qy >= ny) continue;
+                        double v = kw * cells[(int64_t)qy * nx + qx].cinit;
+                        if (v > best) { best = v; arg = idx; }
+                    }
+                sig[k * plane + (int64_t)y * nx + x] = code | (arg << 8);
+            }
+    }
+    free(cells);
+    return R;
+}

@@ -131,6 +131,194 @@ __global__ __launch_bounds__(kBlock) void k_eval(const float* __restrict__ groun
     }
 }
 
+// ------------------------------------------------------------ strip kernel
+//
+// The common case (patch radius 1, inflation radius <= 8): each wavefront
+// owns a strip of 64 columns of one slice and walks down its rows, keeping
+// the rows it still needs in registers:
+//   ground rows  y+R-1 .. y+R+2   (stencils of the flags and of c^init),
+//   gentle flags y+R-1 .. y+R+1   (the 3x3 patch count),
+//   c^init rows  y-R   .. y+R     (the column pass of the inflation).
+// Horizontal neighbours come from adjacent lanes (DPP shifts by one lane,
+// ds_bpermute for the row pass).  The 2 (R+2) edge lanes are halo: they
+// compute but do not store, so a strip writes 64 - 2 (R+2) columns.
+// Per element the arithmetic is the same sequence of FP32 operations as in
+// the tiled kernel above, so both give identical bits.
+
+__device__ __forceinline__ float from_prev(float v) {   // lane i receives lane i-1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_next(float v) {   // lane i receives lane i+1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int from_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int from_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+
+#ifndef PCT_EVAL_PREFETCH
+#define PCT_EVAL_PREFETCH 4
+#endif
+#ifndef PCT_EVAL_STRIP_ROWS
+#define PCT_EVAL_STRIP_ROWS 256
+#endif
+constexpr int kPrefetch = PCT_EVAL_PREFETCH;   // rows fetched ahead per wavefront
+constexpr int kStripRows = PCT_EVAL_STRIP_ROWS; // output rows per strip (upper bound)
+
+struct StripGeom {
+    int rows;   // output rows per strip
+    int n_sx, n_sy, n_work;
+};
+
+// Max of two non-negative floats (+0 included, no NaN) on their bit patterns:
+// for such values the unsigned order of the encodings is the numeric order,
+// so this is exact, and it avoids the NaN-quieting moves fmaxf needs.
+__device__ __forceinline__ float maxnn(float a, float b) {
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)));
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
+                                                       const EvalParams p, float* __restrict__ cost, const StripGeom sg) {
+    constexpr int HX = R + 2;            // halo columns: inflation R, patch 1, stencil 1
+    constexpr int OUTW = 64 - 2 * HX;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin; give
+    // each XCD a contiguous range of strips so that neighbours share an L2.
+    const int per_xcd = gridDim.x / 8;
+    const int wb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int w = wb * (kBlock / 64) + (int)(threadIdx.x / 64);
+    if (w >= sg.n_work) return;
+    const int sx = w % sg.n_sx;
+    const int t = w / sg.n_sx;
+    const int sy = t % sg.n_sy;
+    const int k = t / sg.n_sy;
+    const int lane = threadIdx.x & 63;
+    const int nx = p.nx, ny = p.ny;
+    const int x = sx * OUTW - HX + lane;
+    const bool xin = x >= 0 && x < nx;
+    const unsigned xc = (unsigned)min(max(x, 0), nx - 1);
+    const bool xout = lane >= HX && lane < HX + OUTW && x < nx;
+    const int Y0 = sy * sg.rows, Y1 = min(ny, Y0 + sg.rows);
+    const float* gk = ground + (long long)k * p.plane;
+    const float* ck = ceil + (long long)k * p.plane;
+    float* ok = cost + (long long)k * p.plane;
+
+    // Loads use clamped addresses; the raw value of row r is fetched one
+    // step ahead and masked (outside the grid: no ground) when consumed, so
+    // the load latency overlaps a whole step and the loop has no branches.
+    auto addr = [&](int row) { return (unsigned)min(max(row, 0), ny - 1) * (unsigned)nx + xc; };
+
+    float gR[4];          // ground rows y+R-1 .. y+R+2
+    int fR[3];            // gentle flags rows y+R-1 .. y+R+1
+    float cR[2 * R + 1];  // c^init rows y-R .. y+R
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gR[i] = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fR[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 2 * R + 1; ++i) cR[i] = 0.0f;
+
+    // raw rows fetched kPrefetch steps ahead (memory-level parallelism)
+    int y = Y0 - 2 * HX;
+    float gRaw[kPrefetch], cRaw[kPrefetch];
+#pragma unroll
+    for (int d = 0; d < kPrefetch; ++d) {
+        gRaw[d] = gk[addr(y + HX + d)];
+        cRaw[d] = ck[addr(y + R + d)];
+    }
+    for (; y < Y1; ++y) {
+        const int rg = y + HX, rc = y + R;
+        const float gIn = (xin & (rg >= 0) & (rg < ny)) ? gRaw[0] : -INFINITY;
+        const float cIn = cRaw[0];
+        const bool crow = xin & (rc >= 0) & (rc < ny);
+#pragma unroll
+        for (int d = 0; d + 1 < kPrefetch; ++d) {
+            gRaw[d] = gRaw[d + 1];
+            cRaw[d] = cRaw[d + 1];
+        }
+        gRaw[kPrefetch - 1] = gk[addr(rg + kPrefetch)];
+        cRaw[kPrefetch - 1] = ck[addr(rc + kPrefetch)];
+
+#pragma unroll
+        for (int i = 0; i < 3; ++i) gR[i] = gR[i + 1];
+        gR[3] = gIn;
+
+        // gentle flag of row y+R+1
+        {
+            const float Gc = gR[2], Gd = gR[1], Gu = gR[3];
+            const float Gl = from_prev(Gc), Gr = from_next(Gc);
+            const bool ok5 = isfinite(Gc) & isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
+            const float s2 = sumsq(Gr - Gl, Gu - Gd);
+            const int f = (ok5 & (s2 < p.Ts2)) ? 1 : 0;
+            fR[0] = fR[1];
+            fR[1] = fR[2];
+            fR[2] = f;
+        }
+
+        // c^init of row y+R, Eqs. (1)-(5), computed without branches
+        {
+            const float G = gR[1], Gd = gR[0], Gu = gR[2];
+            const float Gl = from_prev(G), Gr = from_next(G);
+            const int colsum = fR[0] + fR[1] + fR[2];
+            const int cnt = colsum + from_prev_i(colsum) + from_next_i(colsum) - fR[1];
+            const float dI = cIn - G;
+            const float cI = dI < p.d_min ? p.cB : fmaxf(0.0f, p.alpha_d * (p.d_ref - dI));
+            const bool v4 = isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
+            const float dx = Gr - Gl, dy = Gu - Gd;
+            const float s2 = sumsq(dx, dy);
+            const float c_gentle = p.As * s2;
+            const float c_edge = p.Ab * maxnn(dx * dx, dy * dy);
+            const float c_step = cnt > p.kp ? c_edge : p.cB;
+            float cG = s2 < p.Ts2 ? c_gentle : c_step;
+            const bool passable = v4 & !(maxnn(fabsf(dx), fabsf(dy)) > p.Tb);
+            cG = passable ? cG : p.cB;
+            float ci = isfinite(G) ? fminf(p.cB, cI + cG) : p.cB;
+            ci = crow ? ci : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) cR[i] = cR[i + 1];
+            cR[2 * R] = ci;
+        }
+
+        // inflation of row y: column pass from the register rows, row pass
+        // across lanes (all operands are >= 0)
+        float P[R + 1];
+        P[0] = cR[R];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) P[j] = maxnn(cR[R - j], cR[R + j]);
+        float v = 0.0f;
+#pragma unroll
+        for (int a = 0; a <= R; ++a) {
+            float h = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= R; ++j) h = maxnn(h, p.K[a][j] * P[j]);
+            if (a == 0) v = h;
+            else v = maxnn(v, maxnn(__shfl(h, lane - a, 64), __shfl(h, lane + a, 64)));
+        }
+        if (y >= Y0 && xout) ok[(unsigned)y * (unsigned)nx + (unsigned)x] = v;
+    }
+}
+
+StripGeom strip_geom(const EvalParams& p) {
+    const int outw = 64 - 2 * (p.R + 2);
+    StripGeom g{};
+    g.n_sx = (p.nx + outw - 1) / outw;
+    g.rows = kStripRows;
+    auto work = [&](int rows) { return (long long)p.N * g.n_sx * ((p.ny + rows - 1) / rows); };
+    while (g.rows > 32 && work(g.rows) < 16384) g.rows /= 2;
+    g.n_sy = (p.ny + g.rows - 1) / g.rows;
+    g.n_work = (int)work(g.rows);
+    return g;
+}
+
+template <int R>
+pct_status launch_eval_strip(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s) {
+    const StripGeom sg = strip_geom(p);
+    const int waves_per_block = kBlock / 64;
+    int blocks = (sg.n_work + waves_per_block - 1) / waves_per_block;
+    blocks = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_eval_strip<R>, dim3(blocks), dim3(kBlock), 0, s, ground, ceil, p, cost, sg);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
 template <int R>
 size_t eval_lds(int rp) {
     const int HG = R + rp + 1, HF = R + rp;
@@ -247,6 +435,14 @@ size_t eval_ws_bytes(int N, int) {
 }
 
 pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s) {
+    if (p.rp == 1 && p.R <= 8) {
+        switch (p.R) {
+#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s);
+            PCT_S(0) PCT_S(1) PCT_S(2) PCT_S(3) PCT_S(4) PCT_S(5) PCT_S(6) PCT_S(7) PCT_S(8)
+#undef PCT_S
+            default: break;
+        }
+    }
     switch (p.R) {
 #define PCT_R(r) case r: return launch_eval_r<r>(ground, ceil, p, cost, s);
         PCT_R(0) PCT_R(1) PCT_R(2) PCT_R(3) PCT_R(4) PCT_R(5) PCT_R(6) PCT_R(7) PCT_R(8)
