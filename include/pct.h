@@ -176,6 +176,69 @@ pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, c
                                    const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
                                    float* d_cost, uint8_t* d_keep, void* d_ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Trajectory cost sampling (Sec. III-E) and adjoints                     */
+
+/* Flag for the gradient entry points: add into the gradient outputs instead
+ * of overwriting them (without it the outputs are zero-filled first). */
+#define PCT_ACCUMULATE 1
+
+/* The cost and height terms of the trajectory optimisation, Eq. (11):
+ * travel cost C and preferred height Z_ref = e^G + d_ref along a trajectory.
+ * A waypoint (x, y, z) on slice k contributes
+ *     f = C_k(x, y) + w_z (z - G_k(x, y) - d_ref)^2,
+ * where C_k and G_k interpolate c^T_k and e^G_k bilinearly between cell
+ * centres (clamped at the grid edge, zero slope across the clamp); the
+ * height term is dropped when one of the four ground corners is missing.
+ * A trajectory's cost is the sum over its waypoints; waypoints with a
+ * non-finite coordinate or a slice outside [0, N) contribute nothing.
+ * d_cost, d_ground: float32 [N][ny][nx] (one robot's c^T and the ground);
+ * d_wp: float32 [n_traj][n_wp][3]; d_wp_slice: int32 [n_traj][n_wp];
+ * d_f: float32 [n_traj], overwritten.  d_ref is h_robot->d_ref. */
+pct_status pct_sample_cost_fwd(const float* d_cost, const float* d_ground, const pct_grid* grid,
+                               const pct_extent* extent, const pct_robot* h_robot, float w_z, const float* d_wp,
+                               const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, float* d_f, void* stream);
+
+/* Adjoint of pct_sample_cost_fwd for upstream gradients d_gf [n_traj]:
+ * d_gwp [n_traj][n_wp][3] (overwritten) = dL/d(x, y, z); d_gcost and
+ * d_gground [N][ny][nx] (nullable) = dL/dc^T and the height term's dL/de^G
+ * (bilinear scatter to the four corners). */
+pct_status pct_sample_cost_bwd(const float* d_cost, const float* d_ground, const pct_grid* grid,
+                               const pct_extent* extent, const pct_robot* h_robot, float w_z, const float* d_wp,
+                               const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
+                               float* d_gwp, float* d_gcost, float* d_gground, int32_t flags, void* stream);
+
+/* Adjoint of pct_eval_traversability (one robot) for dL/dc^T = d_gcost:
+ * dL/de^G and dL/de^C [N][ny][nx].  Each c^T value is K(t) c^init at the
+ * maximising tap t of its Eq. (6) window (the first maximum in row-major
+ * window order), so its gradient goes to that cell; there Eq. (5) passes it
+ * on unless the clip is active, Eq. (1) gives +alpha_d to e^G and -alpha_d
+ * to e^C where the interval cost is positive, and the gentle and step costs
+ * of Eqs. (3)-(4) differentiate through the central differences (the step
+ * cost through its larger axis, x on a tie); barrier branches and the
+ * neighbour count give none. */
+pct_status pct_eval_traversability_bwd(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                       const pct_extent* extent, const pct_robot* h_robot, const float* d_gcost,
+                                       float* d_gground, float* d_gceil, int32_t flags, void* stream);
+
+/* Adjoint of pct_build_tomogram: every ground/ceiling value is the height
+ * of the point recorded in d_arg_ground/d_arg_ceil, so d_gz[id] (float32
+ * [n_points]) receives the sum of the gradients of the values it holds.
+ * d_gceil may be null. */
+pct_status pct_route_grad_to_points(const float* d_gground, const float* d_gceil, const int32_t* d_arg_ground,
+                                    const int32_t* d_arg_ceil, const pct_grid* grid, const pct_extent* extent,
+                                    int64_t n_points, float* d_gz, int32_t flags, void* stream);
+
+/* The three adjoints above in one pass, without dense gradient grids:
+ * from d_gf to d_gwp (overwritten) and to d_gz [n_points], the gradient of
+ * every point height through the sampled costs, the traversability
+ * evaluation and the construction.  d_cost is the robot's c^T. */
+pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, const float* d_cost,
+                                   const int32_t* d_arg_ground, const int32_t* d_arg_ceil, const pct_grid* grid,
+                                   const pct_extent* extent, const pct_robot* h_robot, float w_z, const float* d_wp,
+                                   const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
+                                   int64_t n_points, float* d_gwp, float* d_gz, int32_t flags, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

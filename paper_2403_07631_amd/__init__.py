@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpct.so")
 
 PCT_OK, PCT_ERR_ARG, PCT_ERR_WORKSPACE, PCT_ERR_CAPACITY, PCT_ERR_DEVICE = 0, -1, -2, -3, -4
 PCT_MAX_SLICES = 1024
+PCT_ACCUMULATE = 1
 
 
 class PctError(RuntimeError):
@@ -77,6 +78,12 @@ def lib():
         "pct_build_tomogram": ([vp, i64, G, E, vp, vp, vp, vp, vp, sz, vp], i32),
         "pct_eval_workspace_bytes": ([G, E, i32], sz),
         "pct_eval_traversability": ([vp, vp, G, E, Rb, i32, vp, vp, vp, sz, vp], i32),
+        "pct_sample_cost_fwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp], i32),
+        "pct_sample_cost_bwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp, vp, vp, i32, vp], i32),
+        "pct_eval_traversability_bwd": ([vp, vp, G, E, Rb, vp, vp, vp, i32, vp], i32),
+        "pct_route_grad_to_points": ([vp, vp, vp, vp, G, E, i64, vp, i32, vp], i32),
+        "pct_trajectory_cost_bwd": ([vp, vp, vp, vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, i64, vp, vp, i32,
+                                     vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -227,3 +234,143 @@ def pct_eval_traversability(ground, ceil, grid, extent: pct_extent, robots, keep
                                          len(robots), _ptr(cost), _ptr(kp), _ptr(ws), ws.numel(),
                                          _stream(dev)))
     return cost, kp
+
+
+# --------------------------------------------------------------------- trajectory cost
+
+def _wp(wp, slices):
+    if not (wp.is_cuda and wp.dtype == torch.float32 and wp.dim() == 3 and wp.shape[2] == 3):
+        raise ValueError("waypoints must be a CUDA float32 tensor [T, W, 3]")
+    if not (slices.is_cuda and slices.dtype == torch.int32 and tuple(slices.shape) == tuple(wp.shape[:2])):
+        raise ValueError("slice ids must be a CUDA int32 tensor [T, W]")
+    return wp.contiguous(), slices.contiguous()
+
+
+def pct_sample_cost_fwd(cost, ground, grid, extent, robot, w_z, wp, slices):
+    """f [T]: per-trajectory sum of c^T + w_z (z - e^G - d_ref)^2 (bilinear)."""
+    wp, slices = _wp(wp, slices)
+    g, rb = grid_struct(grid), robot_struct(robot)
+    T, W = slices.shape
+    f = torch.empty(T, dtype=torch.float32, device=wp.device)
+    _check("pct_sample_cost_fwd",
+           lib().pct_sample_cost_fwd(_ptr(cost), _ptr(ground), C.byref(g), C.byref(extent), C.byref(rb), float(w_z),
+                                     _ptr(wp), _ptr(slices), T, W, _ptr(f), _stream(wp.device)))
+    return f
+
+
+def pct_sample_cost_bwd(cost, ground, grid, extent, robot, w_z, wp, slices, gf, grids=True):
+    """(gwp [T, W, 3], gcost, gground) - the grid gradients are [N, ny, nx]
+    (None unless ``grids``)."""
+    wp, slices = _wp(wp, slices)
+    g, rb = grid_struct(grid), robot_struct(robot)
+    T, W = slices.shape
+    dev = wp.device
+    gwp = torch.empty_like(wp)
+    gcost = torch.empty_like(cost) if grids else None
+    gground = torch.empty_like(ground) if grids else None
+    _check("pct_sample_cost_bwd",
+           lib().pct_sample_cost_bwd(_ptr(cost), _ptr(ground), C.byref(g), C.byref(extent), C.byref(rb), float(w_z),
+                                     _ptr(wp), _ptr(slices), T, W, _ptr(gf.contiguous()), _ptr(gwp), _ptr(gcost),
+                                     _ptr(gground), 0, _stream(dev)))
+    return gwp, gcost, gground
+
+
+def pct_eval_traversability_bwd(ground, ceil, grid, extent, robot, gcost):
+    """(dL/de^G, dL/de^C) [N, ny, nx] for dL/dc^T = gcost (one robot)."""
+    g, rb = grid_struct(grid), robot_struct(robot)
+    gG, gC = torch.empty_like(ground), torch.empty_like(ceil)
+    _check("pct_eval_traversability_bwd",
+           lib().pct_eval_traversability_bwd(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(rb),
+                                             _ptr(gcost.contiguous()), _ptr(gG), _ptr(gC), 0,
+                                             _stream(ground.device)))
+    return gG, gC
+
+
+def pct_route_grad_to_points(gground, gceil, arg_ground, arg_ceil, grid, extent, n_points):
+    """dL/dz [n_points] from grid gradients and the recorded point ids."""
+    g = grid_struct(grid)
+    gz = torch.empty(n_points, dtype=torch.float32, device=gground.device)
+    _check("pct_route_grad_to_points",
+           lib().pct_route_grad_to_points(_ptr(gground), _ptr(gceil), _ptr(arg_ground), _ptr(arg_ceil), C.byref(g),
+                                          C.byref(extent), n_points, _ptr(gz), 0, _stream(gground.device)))
+    return gz
+
+
+def pct_trajectory_cost_bwd(ground, ceil, cost, arg_ground, arg_ceil, grid, extent, robot, w_z, wp, slices, gf,
+                            n_points):
+    """(gwp [T, W, 3], gz [n_points]) in one pass (no dense gradient grids)."""
+    wp, slices = _wp(wp, slices)
+    g, rb = grid_struct(grid), robot_struct(robot)
+    T, W = slices.shape
+    gwp = torch.empty_like(wp)
+    gz = torch.empty(n_points, dtype=torch.float32, device=wp.device)
+    _check("pct_trajectory_cost_bwd",
+           lib().pct_trajectory_cost_bwd(_ptr(ground), _ptr(ceil), _ptr(cost), _ptr(arg_ground), _ptr(arg_ceil),
+                                         C.byref(g), C.byref(extent), C.byref(rb), float(w_z), _ptr(wp),
+                                         _ptr(slices), T, W, _ptr(gf.contiguous()), n_points, _ptr(gwp), _ptr(gz), 0,
+                                         _stream(wp.device)))
+    return gwp, gz
+
+
+# --------------------------------------------------------------------- autograd
+
+class BuildTomogram(torch.autograd.Function):
+    """points [n, 3] -> (ground, ceil) [N, ny, nx]; the backward routes the
+    grid gradients to the z of the points that hold the values."""
+
+    @staticmethod
+    def forward(ctx, xyz, grid, extent):
+        ground, ceil, ag, ac = pct_build_tomogram(xyz.detach(), grid, extent, with_ids=True)
+        ctx.save_for_backward(ag, ac)
+        ctx.grid, ctx.extent, ctx.n = grid, extent, xyz.shape[0]
+        ctx.mark_non_differentiable(ag, ac)
+        return ground, ceil, ag, ac
+
+    @staticmethod
+    def backward(ctx, g_ground, g_ceil, _ga, _gc):
+        ag, ac = ctx.saved_tensors
+        gG = g_ground.contiguous() if g_ground is not None else torch.zeros_like(ag, dtype=torch.float32)
+        gC = g_ceil.contiguous() if g_ceil is not None else None
+        gz = pct_route_grad_to_points(gG, gC, ag, ac if gC is not None else None, ctx.grid, ctx.extent, ctx.n)
+        gxyz = torch.zeros((ctx.n, 3), dtype=torch.float32, device=gz.device)
+        gxyz[:, 2] = gz
+        return gxyz, None, None
+
+
+class EvalTraversability(torch.autograd.Function):
+    """(ground, ceil) -> c^T [N, ny, nx] for one robot."""
+
+    @staticmethod
+    def forward(ctx, ground, ceil, grid, extent, robot):
+        cost, _ = pct_eval_traversability(ground.detach().contiguous(), ceil.detach().contiguous(), grid, extent,
+                                          [robot], keep=False)
+        ctx.save_for_backward(ground, ceil)
+        ctx.grid, ctx.extent, ctx.robot = grid, extent, robot
+        return cost[0]
+
+    @staticmethod
+    def backward(ctx, g_cost):
+        ground, ceil = ctx.saved_tensors
+        gG, gC = pct_eval_traversability_bwd(ground.detach().contiguous(), ceil.detach().contiguous(), ctx.grid,
+                                             ctx.extent, ctx.robot, g_cost.contiguous())
+        return gG, gC, None, None, None
+
+
+class TrajectoryCost(torch.autograd.Function):
+    """(cost, ground, waypoints) -> f [T]: the Eq. (11) cost and height
+    terms summed along each trajectory."""
+
+    @staticmethod
+    def forward(ctx, cost, ground, wp, slices, grid, extent, robot, w_z):
+        f = pct_sample_cost_fwd(cost.detach().contiguous(), ground.detach().contiguous(), grid, extent, robot, w_z,
+                                wp.detach(), slices)
+        ctx.save_for_backward(cost, ground, wp, slices)
+        ctx.grid, ctx.extent, ctx.robot, ctx.w_z = grid, extent, robot, w_z
+        return f
+
+    @staticmethod
+    def backward(ctx, gf):
+        cost, ground, wp, slices = ctx.saved_tensors
+        gwp, gcost, gground = pct_sample_cost_bwd(cost.detach().contiguous(), ground.detach().contiguous(), ctx.grid,
+                                                  ctx.extent, ctx.robot, ctx.w_z, wp.detach(), slices, gf)
+        return gcost, gground, gwp, None, None, None, None, None

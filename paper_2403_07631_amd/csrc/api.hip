@@ -308,4 +308,134 @@ pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, c
     return PCT_OK;
 }
 
+namespace {
+
+pct_status check_sampling(const pct_grid* grid, const pct_extent* extent, const pct_robot* robot, int32_t T, int32_t W,
+                          const void* wp, const void* slice) {
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    st = check_robot(robot, grid->res);
+    if (st != PCT_OK) return st;
+    if (T < 0 || W < 0) return fail(PCT_ERR_ARG, "trajectory counts must be >= 0");
+    if ((long long)T * W > (long long)INT32_MAX) return fail(PCT_ERR_CAPACITY, "too many waypoints");
+    if ((long long)T * W > 0 && (!wp || !slice)) return fail(PCT_ERR_ARG, "waypoint pointers are null");
+    return PCT_OK;
+}
+
+}  // namespace
+
+pct_status pct_sample_cost_fwd(const float* d_cost, const float* d_ground, const pct_grid* grid,
+                               const pct_extent* extent, const pct_robot* h_robot, float w_z, const float* d_wp,
+                               const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, float* d_f, void* stream) {
+    clear_error();
+    pct_status st = check_sampling(grid, extent, h_robot, n_traj, n_wp, d_wp, d_wp_slice);
+    if (st != PCT_OK) return st;
+    if (!isfinite(w_z)) return fail(PCT_ERR_ARG, "w_z must be finite");
+    if (n_traj == 0) return PCT_OK;
+    if (!d_f) return fail(PCT_ERR_ARG, "d_f is null");
+    if (extent->n_slices > 0 && (!d_cost || !d_ground)) return fail(PCT_ERR_ARG, "grid pointers are null");
+    return launch_sample_fwd(d_cost, d_ground, *grid, extent->n_slices, h_robot->d_ref, w_z, d_wp, d_wp_slice, n_traj,
+                             n_wp, d_f, (hipStream_t)stream);
+}
+
+pct_status pct_sample_cost_bwd(const float* d_cost, const float* d_ground, const pct_grid* grid,
+                               const pct_extent* extent, const pct_robot* h_robot, float w_z, const float* d_wp,
+                               const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
+                               float* d_gwp, float* d_gcost, float* d_gground, int32_t flags, void* stream) {
+    clear_error();
+    pct_status st = check_sampling(grid, extent, h_robot, n_traj, n_wp, d_wp, d_wp_slice);
+    if (st != PCT_OK) return st;
+    if (!isfinite(w_z)) return fail(PCT_ERR_ARG, "w_z must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    const long long cells = (long long)extent->n_slices * grid->nx * grid->ny;
+    if (!(flags & PCT_ACCUMULATE)) {
+        st = launch_zero(d_gcost, cells, s);
+        if (st != PCT_OK) return st;
+        st = launch_zero(d_gground, cells, s);
+        if (st != PCT_OK) return st;
+    }
+    if ((long long)n_traj * n_wp == 0) return PCT_OK;
+    if (!d_gf || !d_gwp) return fail(PCT_ERR_ARG, "d_gf and d_gwp are required");
+    if (extent->n_slices > 0 && (!d_cost || !d_ground)) return fail(PCT_ERR_ARG, "grid pointers are null");
+    return launch_sample_bwd(d_cost, d_ground, nullptr, *grid, extent->n_slices, h_robot->d_ref, w_z, d_wp, d_wp_slice,
+                             n_traj, n_wp, d_gf, d_gwp, d_gcost, d_gground, nullptr, nullptr, nullptr, nullptr, 0, s);
+}
+
+pct_status pct_eval_traversability_bwd(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                       const pct_extent* extent, const pct_robot* h_robot, const float* d_gcost,
+                                       float* d_gground, float* d_gceil, int32_t flags, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    const int N = extent->n_slices;
+    if (N == 0) return PCT_OK;
+    if (!d_ground || !d_ceil || !d_gcost || !d_gground || !d_gceil) return fail(PCT_ERR_ARG, "device pointers are null");
+    EvalParams p;
+    st = make_eval_params(*h_robot, *grid, N, &p);
+    if (st != PCT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & PCT_ACCUMULATE)) {
+        st = launch_zero(d_gground, p.plane * N, s);
+        if (st != PCT_OK) return st;
+        st = launch_zero(d_gceil, p.plane * N, s);
+        if (st != PCT_OK) return st;
+    }
+    return launch_eval_bwd(d_ground, d_ceil, d_gcost, p, d_gground, d_gceil, s);
+}
+
+pct_status pct_route_grad_to_points(const float* d_gground, const float* d_gceil, const int32_t* d_arg_ground,
+                                    const int32_t* d_arg_ceil, const pct_grid* grid, const pct_extent* extent,
+                                    int64_t n_points, float* d_gz, int32_t flags, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (n_points < 0) return fail(PCT_ERR_ARG, "n_points must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & PCT_ACCUMULATE)) {
+        st = launch_zero(d_gz, n_points, s);
+        if (st != PCT_OK) return st;
+    }
+    if (extent->n_slices == 0 || n_points == 0) return PCT_OK;
+    if (!d_gz || !d_gground || !d_arg_ground) return fail(PCT_ERR_ARG, "device pointers are null");
+    if (d_gceil && !d_arg_ceil) return fail(PCT_ERR_ARG, "d_arg_ceil is required with d_gceil");
+    return launch_route(d_gground, d_gceil, d_arg_ground, d_arg_ceil, (long long)grid->nx * grid->ny,
+                        extent->n_slices, n_points, d_gz, s);
+}
+
+pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, const float* d_cost,
+                                   const int32_t* d_arg_ground, const int32_t* d_arg_ceil, const pct_grid* grid,
+                                   const pct_extent* extent, const pct_robot* h_robot, float w_z, const float* d_wp,
+                                   const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
+                                   int64_t n_points, float* d_gwp, float* d_gz, int32_t flags, void* stream) {
+    clear_error();
+    pct_status st = check_sampling(grid, extent, h_robot, n_traj, n_wp, d_wp, d_wp_slice);
+    if (st != PCT_OK) return st;
+    if (!isfinite(w_z)) return fail(PCT_ERR_ARG, "w_z must be finite");
+    if (n_points < 0) return fail(PCT_ERR_ARG, "n_points must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & PCT_ACCUMULATE)) {
+        st = launch_zero(d_gz, n_points, s);
+        if (st != PCT_OK) return st;
+    }
+    const int N = extent->n_slices;
+    if ((long long)n_traj * n_wp == 0) return PCT_OK;
+    if (!d_gf || !d_gwp || !d_gz) return fail(PCT_ERR_ARG, "d_gf, d_gwp and d_gz are required");
+    if (N > 0 && (!d_ground || !d_ceil || !d_cost || !d_arg_ground || !d_arg_ceil))
+        return fail(PCT_ERR_ARG, "grid pointers are null");
+    EvalParams p;
+    st = make_eval_params(*h_robot, *grid, std::max(N, 1), &p);
+    if (st != PCT_OK) return st;
+    p.N = N;
+    return launch_sample_bwd(d_cost, d_ground, d_ceil, *grid, N, h_robot->d_ref, w_z, d_wp, d_wp_slice, n_traj, n_wp,
+                             d_gf, d_gwp, nullptr, nullptr, &p, d_arg_ground, d_arg_ceil, d_gz, n_points, s);
+}
+
 }  // extern "C"

@@ -1,7 +1,7 @@
 // Tomogram construction on gfx950 (Sec. III-A, Algorithm 1).
 //
 // Algorithm 1 compares every point with every plane.  Here the points are
-// first binned by a counting sort into construction tiles (64 x th cells),
+// first binned by a counting sort into construction tiles (256 x th cells),
 // with LDS-privatised integer counters; then one workgroup per tile sorts
 // each cell's heights in LDS and sweeps the planes once:
 //   ground e^G_k = the largest height <= h_k, ceiling e^C_k = the next one.
@@ -127,15 +127,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(unsigned* __restrict__ p, i
         p[i] = v;
 }
 
-// Per-tile point counts.  Each workgroup counts its chunk in LDS and adds
-// the non-zero counters to the global ones.
+// Per-tile point counts with global atomics (used when the tile count
+// exceeds the LDS-privatised path).
 __global__ __launch_bounds__(kBlock) void k_tile_count(const float* __restrict__ xyz, int64_t n, GridDev g,
                                                        unsigned* __restrict__ gcount) {
-    extern __shared__ unsigned s_cnt[];
-    const bool lds = g.ntiles <= kMaxLdsTiles;
-    if (lds)
-        for (int t = threadIdx.x; t < g.ntiles; t += kBlock) s_cnt[t] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBlock * kBinPPT;
 #pragma unroll 4
     for (int j = 0; j < kBinPPT; ++j) {
@@ -143,15 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const float* __restrict__
         int tile;
         unsigned cell;
         float z;
-        if (i < n && bin_point(xyz, i, g, tile, cell, z)) {
-            if (lds) atomicAdd(&s_cnt[tile], 1u);
-            else atomicAdd(&gcount[tile], 1u);
-        }
+        if (i < n && bin_point(xyz, i, g, tile, cell, z)) atomicAdd(&gcount[tile], 1u);
     }
-    __syncthreads();
-    if (lds)
-        for (int t = threadIdx.x; t < g.ntiles; t += kBlock)
-            if (s_cnt[t]) atomicAdd(&gcount[t], s_cnt[t]);
 }
 
 // Exclusive scan of the tile counts (one workgroup): off[0..ntiles], and
@@ -181,51 +169,85 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const unsigned* __restrict_
 }
 
 // Scatter of packed records (height, cell-in-tile[, point id]) into tile
-// order.  A workgroup counts its chunk per tile in LDS, reserves one range
-// per touched tile with a single global atomic, then places points with LDS
-// atomics.  The order inside a tile is not fixed; the tile reduce does not
-// depend on it.
+// order with a global atomic cursor per tile (used when the tile count
+// exceeds the LDS-privatised path).  The order inside a tile is not fixed;
+// the tile reduce does not depend on it.
 template <bool IDS>
 __global__ __launch_bounds__(kBlock) void k_tile_scatter(const float* __restrict__ xyz, int64_t n, GridDev g,
                                                          unsigned* __restrict__ cursor, float* __restrict__ rz,
                                                          unsigned* __restrict__ rmeta, int* __restrict__ rid) {
-    extern __shared__ unsigned s_mem[];
-    const bool lds = g.ntiles <= kMaxLdsTiles;
-    unsigned* s_cnt = s_mem;
-    unsigned* s_base = s_mem + (lds ? g.ntiles : 0);
-    if (lds)
-        for (int t = threadIdx.x; t < g.ntiles; t += kBlock) s_cnt[t] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kBlock * kBinPPT;
-    int tile[kBinPPT];
-    unsigned cell[kBinPPT];
-    float zz[kBinPPT];
-#pragma unroll
     for (int j = 0; j < kBinPPT; ++j) {
-        int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
-        tile[j] = -1;
-        if (i < n && bin_point(xyz, i, g, tile[j], cell[j], zz[j])) {
-            if (lds) atomicAdd(&s_cnt[tile[j]], 1u);
-        } else {
-            tile[j] = -1;
-        }
+        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+        int tile;
+        unsigned cell;
+        float z;
+        if (i >= n || !bin_point(xyz, i, g, tile, cell, z)) continue;
+        const unsigned pos = atomicAdd(&cursor[tile], 1u);
+        rz[pos] = z;
+        rmeta[pos] = cell;
+        if (IDS) rid[pos] = (int)i;
+    }
+}
+
+// Blocked binning (the tile count fits in LDS): radix-sort style, no
+// global atomics.  Workgroup b counts its chunk of points per tile in LDS
+// and writes the whole count row; a column scan turns the rows into
+// per-(tile, workgroup) offsets; the scatter then places each point with an
+// LDS atomic on its workgroup's cursor for the tile.
+constexpr int kBinBlock = 512;
+
+__global__ __launch_bounds__(kBinBlock) void k_block_hist(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                          int64_t chunk, unsigned* __restrict__ cnt) {
+    extern __shared__ unsigned s_cnt[];
+    for (int t = threadIdx.x; t < g.ntiles; t += kBinBlock) s_cnt[t] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kBinBlock) {
+        int tile;
+        unsigned cell;
+        float z;
+        if (bin_point(xyz, i, g, tile, cell, z)) atomicAdd(&s_cnt[tile], 1u);
     }
     __syncthreads();
-    if (lds) {
-        for (int t = threadIdx.x; t < g.ntiles; t += kBlock) {
-            unsigned c = s_cnt[t];
-            if (c) s_base[t] = atomicAdd(&cursor[t], c);
-            s_cnt[t] = 0;
-        }
+    unsigned* row = cnt + (int64_t)blockIdx.x * g.ntiles;
+    for (int t = threadIdx.x; t < g.ntiles; t += kBinBlock) row[t] = s_cnt[t];
+}
+
+// Per tile, exclusive scan of the counts down the workgroup rows; the
+// column total goes to total[t].
+__global__ __launch_bounds__(kBlock) void k_scan_cols(unsigned* __restrict__ cnt, int nb, int ntiles,
+                                                      unsigned* __restrict__ total) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ntiles) return;
+    unsigned s = 0;
+    for (int b = 0; b < nb; ++b) {
+        const unsigned v = cnt[(int64_t)b * ntiles + t];
+        cnt[(int64_t)b * ntiles + t] = s;
+        s += v;
     }
+    total[t] = s;
+}
+
+template <bool IDS>
+__global__ __launch_bounds__(kBinBlock) void k_block_scatter(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                             int64_t chunk, const unsigned* __restrict__ cnt,
+                                                             const unsigned* __restrict__ off, float* __restrict__ rz,
+                                                             unsigned* __restrict__ rmeta, int* __restrict__ rid) {
+    extern __shared__ unsigned s_cur[];
+    const unsigned* row = cnt + (int64_t)blockIdx.x * g.ntiles;
+    for (int t = threadIdx.x; t < g.ntiles; t += kBinBlock) s_cur[t] = off[t] + row[t];
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kBinPPT; ++j) {
-        if (tile[j] < 0) continue;
-        unsigned pos = lds ? s_base[tile[j]] + atomicAdd(&s_cnt[tile[j]], 1u) : atomicAdd(&cursor[tile[j]], 1u);
-        rz[pos] = zz[j];
-        rmeta[pos] = cell[j];
-        if (IDS) rid[pos] = (int)(base + (int64_t)j * kBlock + threadIdx.x);
+    const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kBinBlock) {
+        int tile;
+        unsigned cell;
+        float z;
+        if (!bin_point(xyz, i, g, tile, cell, z)) continue;
+        const unsigned pos = atomicAdd(&s_cur[tile], 1u);
+        rz[pos] = z;
+        rmeta[pos] = cell;
+        if (IDS) rid[pos] = (int)i;
     }
 }
 
@@ -425,7 +447,9 @@ inline size_t reduce_lds_bytes(const GridDev& g, bool ids) {
 }
 
 struct BuildWs {
-    unsigned *count, *off, *cursor;
+    unsigned *count, *off, *cursor, *bcount;
+    int64_t chunk;
+    int nb;
     float* rz;
     unsigned* rmeta;
     int* rid;
@@ -441,6 +465,13 @@ BuildWs carve_build_ws(void* base, int64_t n, const GridDev& g, bool ids) {
         o += align_up(bytes);
         return r;
     };
+    // chunk of the blocked binning: at least 16384 points per workgroup,
+    // doubled until the per-workgroup count matrix has <= 2^26 entries
+    w.chunk = 16384;
+    while (((n + w.chunk - 1) / w.chunk) * (int64_t)g.ntiles > (int64_t(1) << 26)) w.chunk *= 2;
+    w.nb = (int)std::max<int64_t>(1, (n + w.chunk - 1) / w.chunk);
+    const bool blocked = g.ntiles <= kMaxLdsTiles;
+    w.bcount = blocked ? (unsigned*)take(sizeof(unsigned) * (size_t)w.nb * g.ntiles) : nullptr;
     w.count = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
     w.off = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
     w.cursor = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
@@ -480,26 +511,52 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
     BuildWs w = carve_build_ws(ws, n, g, ids);
     if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "build workspace too small: %zu < %zu", ws_bytes, w.bytes);
     const bool lds = g.ntiles <= kMaxLdsTiles;
-    const int fill_blocks = std::min(1024, (g.ntiles + kBlock) / kBlock + 1);
-    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(kBlock), 0, s, w.count, (int64_t)g.ntiles + 1, 0u);
-    PCT_LAUNCH_CHECK();
-    const int64_t chunks = (n + (int64_t)kBlock * kBinPPT - 1) / ((int64_t)kBlock * kBinPPT);
-    if (chunks > 0) {
-        hipLaunchKernelGGL(k_tile_count, dim3((unsigned)chunks), dim3(kBlock), lds ? sizeof(unsigned) * g.ntiles : 0, s,
-                           xyz, n, g, w.count);
+    if (lds) {
+        // blocked binning: per-workgroup counts, column scan, tile scan, scatter
+        if (n > 0) {
+            hipLaunchKernelGGL(k_block_hist, dim3(w.nb), dim3(kBinBlock), sizeof(unsigned) * g.ntiles, s, xyz, n, g,
+                               w.chunk, w.bcount);
+            PCT_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_scan_cols, dim3((g.ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, w.bcount, w.nb,
+                               g.ntiles, w.count);
+            PCT_LAUNCH_CHECK();
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3(std::min(1024, g.ntiles / kBlock + 1)), dim3(kBlock), 0, s, w.count,
+                               (int64_t)g.ntiles + 1, 0u);
+            PCT_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
         PCT_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
-    PCT_LAUNCH_CHECK();
-    if (chunks > 0) {
-        size_t lds_b = lds ? 2 * sizeof(unsigned) * g.ntiles : 0;
-        if (ids)
-            hipLaunchKernelGGL(k_tile_scatter<true>, dim3((unsigned)chunks), dim3(kBlock), lds_b, s, xyz, n, g,
-                               w.cursor, w.rz, w.rmeta, w.rid);
-        else
-            hipLaunchKernelGGL(k_tile_scatter<false>, dim3((unsigned)chunks), dim3(kBlock), lds_b, s, xyz, n, g,
-                               w.cursor, w.rz, w.rmeta, w.rid);
+        if (n > 0) {
+            if (ids)
+                hipLaunchKernelGGL(k_block_scatter<true>, dim3(w.nb), dim3(kBinBlock), sizeof(unsigned) * g.ntiles, s,
+                                   xyz, n, g, w.chunk, w.bcount, w.off, w.rz, w.rmeta, w.rid);
+            else
+                hipLaunchKernelGGL(k_block_scatter<false>, dim3(w.nb), dim3(kBinBlock), sizeof(unsigned) * g.ntiles, s,
+                                   xyz, n, g, w.chunk, w.bcount, w.off, w.rz, w.rmeta, w.rid);
+            PCT_LAUNCH_CHECK();
+        }
+    } else {
+        // more tiles than LDS holds: global atomics on the tile counters
+        const int fill_blocks = std::min(1024, (g.ntiles + kBlock) / kBlock + 1);
+        hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(kBlock), 0, s, w.count, (int64_t)g.ntiles + 1, 0u);
         PCT_LAUNCH_CHECK();
+        const int64_t chunks = (n + (int64_t)kBlock * kBinPPT - 1) / ((int64_t)kBlock * kBinPPT);
+        if (chunks > 0) {
+            hipLaunchKernelGGL(k_tile_count, dim3((unsigned)chunks), dim3(kBlock), 0, s, xyz, n, g, w.count);
+            PCT_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
+        PCT_LAUNCH_CHECK();
+        if (chunks > 0) {
+            if (ids)
+                hipLaunchKernelGGL(k_tile_scatter<true>, dim3((unsigned)chunks), dim3(kBlock), 0, s, xyz, n, g,
+                                   w.cursor, w.rz, w.rmeta, w.rid);
+            else
+                hipLaunchKernelGGL(k_tile_scatter<false>, dim3((unsigned)chunks), dim3(kBlock), 0, s, xyz, n, g,
+                                   w.cursor, w.rz, w.rmeta, w.rid);
+            PCT_LAUNCH_CHECK();
+        }
     }
     const size_t rl = reduce_lds_bytes(g, ids);
     if (ids)
@@ -522,8 +579,8 @@ GridDev make_grid_dev(const pct_grid& gr) {
     g.fnx = (float)gr.nx;
     g.fny = (float)gr.ny;
     g.ntx = (gr.nx + kBuildTileW - 1) / kBuildTileW;
-    g.th = 8;
-    while (g.th < 32 && (int64_t)g.ntx * ((gr.ny + g.th - 1) / g.th) > kMaxLdsTiles) g.th *= 2;
+    g.th = 2;
+    while (g.th < 8 && (int64_t)g.ntx * ((gr.ny + g.th - 1) / g.th) > kMaxLdsTiles) g.th *= 2;
     g.nty = (gr.ny + g.th - 1) / g.th;
     g.ntiles = g.ntx * g.nty;
     return g;

@@ -1,0 +1,427 @@
+// Trajectory cost sampling and adjoints on gfx950.
+//
+// Sampling (the cost and height terms of the trajectory optimisation of
+// Sec. III-E, Eq. (11)): a waypoint (x, y, z) on slice k contributes
+//     f = C_k(x, y) + w_z (z - G_k(x, y) - d_ref)^2,
+// with C_k, G_k cell-centred bilinear interpolations of c^T_k and e^G_k
+// (clamped at the grid edge, zero slope across the clamp); the height term
+// is dropped when a ground corner is missing; a trajectory sums its
+// waypoints.  Waypoints with a non-finite coordinate or a slice outside
+// [0, N) contribute nothing.
+//
+// Adjoints: bilinear weights scatter dL/dC and dL/dG to the four corners;
+// the traversability adjoint routes dL/dc^T through the maximising tap of
+// the Eq. (6) window (first maximum in row-major window order) into the
+// Eq. (1)-(5) derivatives at that cell; the construction adjoint adds each
+// ground/ceiling gradient to the z of the point that holds the value.  The
+// maximising tap is found by recomputing c^init with the same FP32
+// operation sequence as the forward kernels, so it reproduces the forward
+// maximum exactly.  Gradient sums use float atomics.
+#include "pct_internal.h"
+
+namespace pct {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ float sumsq(float dx, float dy) { return __builtin_fmaf(dx, dx, dy * dy); }
+
+__device__ __forceinline__ float gval(const float* __restrict__ gk, int nx, int ny, int x, int y) {
+    return (x >= 0 && y >= 0 && x < nx && y < ny) ? gk[(long long)y * nx + x] : -INFINITY;
+}
+
+__device__ bool gentle_at(const float* __restrict__ gk, int nx, int ny, int x, int y, const EvalParams& p) {
+    const float G = gval(gk, nx, ny, x, y);
+    const float l = gval(gk, nx, ny, x - 1, y), r = gval(gk, nx, ny, x + 1, y);
+    const float d = gval(gk, nx, ny, x, y - 1), u = gval(gk, nx, ny, x, y + 1);
+    if (!(isfinite(G) && isfinite(l) && isfinite(r) && isfinite(d) && isfinite(u))) return false;
+    return sumsq(r - l, u - d) < p.Ts2;
+}
+
+struct Cinit {
+    float ci, dx, dy, dI;
+    int branch;   // 0 no ground, 1 barrier, 2 gentle, 3 step, 4 step without support
+    bool ipos;    // interval term active: d^I >= d_min and alpha_d (d_ref - d^I) > 0
+    bool pass;    // c^I + c^G < c^B (the clip of Eq. (5) is not active)
+};
+
+// c^init of cell (x, y) of one slice, Eqs. (1)-(5), with the values needed
+// by its adjoint.  Same FP32 operation sequence as the forward kernels.
+__device__ Cinit cinit_at(const float* __restrict__ gk, const float* __restrict__ ck, int x, int y,
+                          const EvalParams& p) {
+    const int nx = p.nx, ny = p.ny;
+    Cinit o{};
+    const float G = gk[(long long)y * nx + x];
+    if (!isfinite(G)) {
+        o.ci = p.cB;
+        o.branch = 0;
+        return o;
+    }
+    const float C = ck[(long long)y * nx + x];
+    o.dI = C - G;
+    const float cI = o.dI < p.d_min ? p.cB : fmaxf(0.0f, p.alpha_d * (p.d_ref - o.dI));
+    o.ipos = !(o.dI < p.d_min) && p.alpha_d * (p.d_ref - o.dI) > 0.0f;
+    const float l = gval(gk, nx, ny, x - 1, y), r = gval(gk, nx, ny, x + 1, y);
+    const float d = gval(gk, nx, ny, x, y - 1), u = gval(gk, nx, ny, x, y + 1);
+    float cG = p.cB;
+    o.branch = 1;
+    if (isfinite(l) && isfinite(r) && isfinite(d) && isfinite(u)) {
+        o.dx = r - l;
+        o.dy = u - d;
+        if (!(fmaxf(fabsf(o.dx), fabsf(o.dy)) > p.Tb)) {
+            const float s2 = sumsq(o.dx, o.dy);
+            if (s2 < p.Ts2) {
+                cG = p.As * s2;
+                o.branch = 2;
+            } else {
+                int cnt = 0;
+                for (int dyp = -p.rp; dyp <= p.rp; ++dyp)
+                    for (int dxp = -p.rp; dxp <= p.rp; ++dxp)
+                        if (dxp | dyp) cnt += gentle_at(gk, nx, ny, x + dxp, y + dyp, p) ? 1 : 0;
+                if (cnt > p.kp) {
+                    cG = p.Ab * fmaxf(o.dx * o.dx, o.dy * o.dy);
+                    o.branch = 3;
+                } else {
+                    o.branch = 4;
+                }
+            }
+        }
+    }
+    const float s = cI + cG;
+    o.pass = s < p.cB;
+    o.ci = fminf(p.cB, s);
+    return o;
+}
+
+// Gradient sink: dense grids (nullable) and/or point heights via the ids.
+struct Sink {
+    float* gG;          // [N][ny][nx] or null
+    float* gC;          // [N][ny][nx] or null
+    const int* aG;      // point ids, for routing to gz (null: no routing)
+    const int* aC;
+    float* gz;
+    long long n_points;
+};
+
+__device__ __forceinline__ void add_ground(const Sink& s, long long i, float v) {
+    if (v == 0.0f) return;
+    if (s.gG) atomicAdd(&s.gG[i], v);
+    if (s.gz) {
+        const int id = s.aG[i];
+        if (id >= 0 && id < s.n_points) atomicAdd(&s.gz[id], v);
+    }
+}
+__device__ __forceinline__ void add_ceil(const Sink& s, long long i, float v) {
+    if (v == 0.0f) return;
+    if (s.gC) atomicAdd(&s.gC[i], v);
+    if (s.gz) {
+        const int id = s.aC[i];
+        if (id >= 0 && id < s.n_points) atomicAdd(&s.gz[id], v);
+    }
+}
+
+// dL/dc^T(k, x, y) = gc: inflation argmax, then the Eq. (1)-(5) adjoint.
+__device__ void eval_adjoint_cell(const float* __restrict__ ground, const float* __restrict__ ceil, int k, int x,
+                                  int y, float gc, const EvalParams& p, const Sink& s) {
+    const long long base = (long long)k * p.plane;
+    const float* gk = ground + base;
+    const float* ck = ceil + base;
+    const int nx = p.nx, ny = p.ny, R = p.R;
+    float best = -INFINITY, bk = 0.0f;
+    int bx = x, by = y;
+    for (int n = -R; n <= R; ++n) {
+        const int qy = y + n;
+        if (qy < 0 || qy >= ny) continue;
+        for (int m = -R; m <= R; ++m) {
+            const int qx = x + m;
+            const float kw = p.K[abs(m)][abs(n)];
+            if (kw <= 0.0f || qx < 0 || qx >= nx) continue;
+            const float v = kw * cinit_at(gk, ck, qx, qy, p).ci;
+            if (v > best) {
+                best = v;
+                bk = kw;
+                bx = qx;
+                by = qy;
+            }
+        }
+    }
+    const Cinit q = cinit_at(gk, ck, bx, by, p);
+    if (q.branch == 0 || !q.pass) return;
+    const float gq = bk * gc;
+    const long long iq = base + (long long)by * nx + bx;
+    if (q.ipos) {
+        add_ground(s, iq, p.alpha_d * gq);
+        add_ceil(s, iq, -p.alpha_d * gq);
+    }
+    float ddx = 0.0f, ddy = 0.0f;   // dL/d(dx), dL/d(dy) for the raw differences
+    if (q.branch == 2) {
+        ddx = 2.0f * p.As * q.dx * gq;
+        ddy = 2.0f * p.As * q.dy * gq;
+    } else if (q.branch == 3) {
+        if (fabsf(q.dx) >= fabsf(q.dy)) ddx = 2.0f * p.Ab * q.dx * gq;
+        else ddy = 2.0f * p.Ab * q.dy * gq;
+    }
+    if (ddx != 0.0f) {
+        add_ground(s, iq + 1, ddx);
+        add_ground(s, iq - 1, -ddx);
+    }
+    if (ddy != 0.0f) {
+        add_ground(s, iq + nx, ddy);
+        add_ground(s, iq - nx, -ddy);
+    }
+}
+
+// ----------------------------------------------------------------- sampling
+struct SampleArgs {
+    float x0, y0, res, inv_res, d_ref, w_z;
+    int nx, ny, N;
+    long long plane;
+    int T, W;
+};
+
+struct Bil {
+    bool ok, hterm;
+    long long c00, c10, c01, c11;
+    float fu, fv, du, dv;
+};
+
+__device__ __forceinline__ void axis(float q, int n, int& i0, int& i1, float& f, float& dq) {
+    if (n == 1) {
+        i0 = i1 = 0;
+        f = 0.0f;
+        dq = 0.0f;
+        return;
+    }
+    float qc = q;
+    bool clamped = false;
+    if (q < 0.0f) { qc = 0.0f; clamped = true; }
+    else if (q > (float)(n - 1)) { qc = (float)(n - 1); clamped = true; }
+    int a = (int)floorf(qc);
+    if (a > n - 2) a = n - 2;
+    i0 = a;
+    i1 = a + 1;
+    f = qc - (float)a;
+    dq = clamped ? 0.0f : 1.0f;
+}
+
+__device__ Bil bilinear(const float* __restrict__ ground, const SampleArgs& a, float x, float y, float z, int k) {
+    Bil b{};
+    if (k < 0 || k >= a.N || !isfinite(x) || !isfinite(y) || !isfinite(z)) return b;
+    b.ok = true;
+    const float u = (x - a.x0) / a.res - 0.5f;
+    const float v = (y - a.y0) / a.res - 0.5f;
+    int i0, i1, j0, j1;
+    axis(u, a.nx, i0, i1, b.fu, b.du);
+    axis(v, a.ny, j0, j1, b.fv, b.dv);
+    b.du *= a.inv_res;
+    b.dv *= a.inv_res;
+    const long long base = (long long)k * a.plane;
+    b.c00 = base + (long long)j0 * a.nx + i0;
+    b.c10 = base + (long long)j0 * a.nx + i1;
+    b.c01 = base + (long long)j1 * a.nx + i0;
+    b.c11 = base + (long long)j1 * a.nx + i1;
+    b.hterm = isfinite(ground[b.c00]) && isfinite(ground[b.c10]) && isfinite(ground[b.c01]) && isfinite(ground[b.c11]);
+    return b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sample_fwd(const float* __restrict__ cost, const float* __restrict__ ground,
+                                                       const float* __restrict__ wp, const int* __restrict__ slice,
+                                                       SampleArgs a, float* __restrict__ f) {
+    const int t = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x / 64);
+    if (t >= a.T) return;
+    const int lane = threadIdx.x & 63;
+    float acc = 0.0f;
+    for (int w = lane; w < a.W; w += 64) {
+        const long long i = (long long)t * a.W + w;
+        const float x = wp[3 * i], y = wp[3 * i + 1], z = wp[3 * i + 2];
+        const Bil b = bilinear(ground, a, x, y, z, slice[i]);
+        if (!b.ok) continue;
+        const float w00 = (1.0f - b.fu) * (1.0f - b.fv), w10 = b.fu * (1.0f - b.fv);
+        const float w01 = (1.0f - b.fu) * b.fv, w11 = b.fu * b.fv;
+        acc += w00 * cost[b.c00] + w10 * cost[b.c10] + w01 * cost[b.c01] + w11 * cost[b.c11];
+        if (b.hterm) {
+            const float G = w00 * ground[b.c00] + w10 * ground[b.c10] + w01 * ground[b.c01] + w11 * ground[b.c11];
+            const float e = z - G - a.d_ref;
+            acc += a.w_z * e * e;
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane == 0) f[t] = acc;
+}
+
+// Per waypoint: dL/dwp (written), the bilinear scatter of dL/dC to c^T
+// (dense gcost and/or, with `eval`, straight through the traversability
+// adjoint into the sink) and of the height term to e^G.
+__global__ __launch_bounds__(kBlock) void k_sample_bwd(const float* __restrict__ cost, const float* __restrict__ ground,
+                                                       const float* __restrict__ ceil, const float* __restrict__ wp,
+                                                       const int* __restrict__ slice, SampleArgs a,
+                                                       const float* __restrict__ gf, float* __restrict__ gwp,
+                                                       float* __restrict__ gcost, const EvalParams ep, int eval,
+                                                       Sink s) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (long long)a.T * a.W) return;
+    const int t = (int)(i / a.W);
+    const float x = wp[3 * i], y = wp[3 * i + 1], z = wp[3 * i + 2];
+    const int k = slice[i];
+    const Bil b = bilinear(ground, a, x, y, z, k);
+    float gx = 0.0f, gy = 0.0f, gzw = 0.0f;
+    if (b.ok) {
+        const float g = gf[t];
+        const float w00 = (1.0f - b.fu) * (1.0f - b.fv), w10 = b.fu * (1.0f - b.fv);
+        const float w01 = (1.0f - b.fu) * b.fv, w11 = b.fu * b.fv;
+        const float c00 = cost[b.c00], c10 = cost[b.c10], c01 = cost[b.c01], c11 = cost[b.c11];
+        const float dCdu = (1.0f - b.fv) * (c10 - c00) + b.fv * (c11 - c01);
+        const float dCdv = (1.0f - b.fu) * (c01 - c00) + b.fu * (c11 - c10);
+        gx = g * dCdu * b.du;
+        gy = g * dCdv * b.dv;
+        const long long cs[4] = {b.c00, b.c10, b.c01, b.c11};
+        const float ws[4] = {w00, w10, w01, w11};
+        if (b.hterm) {
+            const float G00 = ground[b.c00], G10 = ground[b.c10], G01 = ground[b.c01], G11 = ground[b.c11];
+            const float G = w00 * G00 + w10 * G10 + w01 * G01 + w11 * G11;
+            const float de = 2.0f * a.w_z * (z - G - a.d_ref) * g;
+            const float dGdu = (1.0f - b.fv) * (G10 - G00) + b.fv * (G11 - G01);
+            const float dGdv = (1.0f - b.fu) * (G01 - G00) + b.fu * (G11 - G10);
+            gx -= de * dGdu * b.du;
+            gy -= de * dGdv * b.dv;
+            gzw = de;
+            for (int c = 0; c < 4; ++c) add_ground(s, cs[c], -de * ws[c]);
+        }
+        for (int c = 0; c < 4; ++c) {
+            const float gc = g * ws[c];
+            if (gcost && gc != 0.0f) atomicAdd(&gcost[cs[c]], gc);
+            if (eval && gc != 0.0f) {
+                const long long local = cs[c] - (long long)k * a.plane;
+                eval_adjoint_cell(ground, ceil, k, (int)(local % a.nx), (int)(local / a.nx), gc, ep, s);
+            }
+        }
+    }
+    gwp[3 * i] = gx;
+    gwp[3 * i + 1] = gy;
+    gwp[3 * i + 2] = gzw;
+}
+
+// Dense traversability adjoint: one thread per cell-slice with a gradient.
+__global__ __launch_bounds__(kBlock) void k_eval_bwd(const float* __restrict__ ground, const float* __restrict__ ceil,
+                                                     const float* __restrict__ gcost, const EvalParams p, Sink s) {
+    const long long total = p.plane * p.N;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const float gc = gcost[i];
+        if (gc == 0.0f) continue;
+        const int k = (int)(i / p.plane);
+        const long long c = i - (long long)k * p.plane;
+        eval_adjoint_cell(ground, ceil, k, (int)(c % p.nx), (int)(c / p.nx), gc, p, s);
+    }
+}
+
+// Construction adjoint: per cell, walk the slices and add each run of
+// values held by the same point in one atomic.
+__global__ __launch_bounds__(kBlock) void k_route(const float* __restrict__ gG, const float* __restrict__ gC,
+                                                  const int* __restrict__ aG, const int* __restrict__ aC,
+                                                  long long plane, int N, long long n_points, float* __restrict__ gz) {
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= plane) return;
+    for (int which = 0; which < 2; ++which) {
+        const float* g = which ? gC : gG;
+        const int* a = which ? aC : aG;
+        if (!g) continue;
+        int cur = -1;
+        float acc = 0.0f;
+        for (int k = 0; k < N; ++k) {
+            const long long i = (long long)k * plane + c;
+            const int id = a[i];
+            if (id != cur) {
+                if (cur >= 0 && cur < n_points && acc != 0.0f) atomicAdd(&gz[cur], acc);
+                cur = id;
+                acc = 0.0f;
+            }
+            acc += g[i];
+        }
+        if (cur >= 0 && cur < n_points && acc != 0.0f) atomicAdd(&gz[cur], acc);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(float* __restrict__ p, long long n) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        p[i] = 0.0f;
+}
+
+int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + kBlock - 1) / kBlock, 1 << 16)); }
+
+}  // namespace
+
+pct_status launch_zero(float* p, long long n, hipStream_t s) {
+    if (!p || n <= 0) return PCT_OK;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+static SampleArgs make_sample_args(const pct_grid& g, int N, float d_ref, float w_z, int T, int W) {
+    SampleArgs a{};
+    a.x0 = g.x0;
+    a.y0 = g.y0;
+    a.res = g.res;
+    a.inv_res = (float)(1.0 / (double)g.res);
+    a.d_ref = d_ref;
+    a.w_z = w_z;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.N = N;
+    a.plane = (long long)g.nx * g.ny;
+    a.T = T;
+    a.W = W;
+    return a;
+}
+
+pct_status launch_sample_fwd(const float* cost, const float* ground, const pct_grid& g, int N, float d_ref, float w_z,
+                             const float* wp, const int* slice, int T, int W, float* f, hipStream_t s) {
+    const SampleArgs a = make_sample_args(g, N, d_ref, w_z, T, W);
+    const int blocks = (T + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(k_sample_fwd, dim3(blocks), dim3(kBlock), 0, s, cost, ground, wp, slice, a, f);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+pct_status launch_sample_bwd(const float* cost, const float* ground, const float* ceil, const pct_grid& g, int N,
+                             float d_ref, float w_z, const float* wp, const int* slice, int T, int W, const float* gf,
+                             float* gwp, float* gcost, float* gground, const EvalParams* ep, const int* aG,
+                             const int* aC, float* gz, long long n_points, hipStream_t s) {
+    const SampleArgs a = make_sample_args(g, N, d_ref, w_z, T, W);
+    Sink sk{};
+    sk.gG = gground;
+    sk.gC = nullptr;
+    sk.aG = aG;
+    sk.aC = aC;
+    sk.gz = gz;
+    sk.n_points = n_points;
+    EvalParams p = ep ? *ep : EvalParams{};
+    const long long n = (long long)T * W;
+    if (n == 0) return PCT_OK;
+    hipLaunchKernelGGL(k_sample_bwd, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cost, ground, ceil,
+                       wp, slice, a, gf, gwp, gcost, p, ep ? 1 : 0, sk);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+pct_status launch_eval_bwd(const float* ground, const float* ceil, const float* gcost, const EvalParams& p,
+                           float* gground, float* gceil, hipStream_t s) {
+    Sink sk{};
+    sk.gG = gground;
+    sk.gC = gceil;
+    hipLaunchKernelGGL(k_eval_bwd, dim3(grid_for(p.plane * p.N)), dim3(kBlock), 0, s, ground, ceil, gcost, p, sk);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+pct_status launch_route(const float* gG, const float* gC, const int* aG, const int* aC, long long plane, int N,
+                        long long n_points, float* gz, hipStream_t s) {
+    hipLaunchKernelGGL(k_route, dim3((unsigned)((plane + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, gG, gC, aG, aC,
+                       plane, N, n_points, gz);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+}  // namespace pct

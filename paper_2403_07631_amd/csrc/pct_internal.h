@@ -31,10 +31,11 @@ void clear_error();
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- grids
-// Construction tiles are 64 cells wide (one wavefront per row) and
-// `th` cells tall; th grows with the grid so that the tile count fits the
-// LDS-privatised counters of the binning kernels.
-constexpr int kBuildTileW = 64;
+// Construction tiles are 256 cells wide (each output row of a tile is one
+// contiguous 1 KB run per slice) and `th` cells tall; th grows with the grid
+// so that the tile count fits the LDS-privatised counters of the binning
+// kernels.
+constexpr int kBuildTileW = 256;
 constexpr int kMaxLdsTiles = 8192;
 
 struct GridDev {
@@ -105,5 +106,17 @@ pct_status launch_eval(const float* ground, const float* ceil, const EvalParams&
                        hipStream_t s);
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
                            void* ws, hipStream_t s);
+
+pct_status launch_zero(float* p, long long n, hipStream_t s);
+pct_status launch_sample_fwd(const float* cost, const float* ground, const pct_grid& g, int N, float d_ref, float w_z,
+                             const float* wp, const int* slice, int T, int W, float* f, hipStream_t s);
+pct_status launch_sample_bwd(const float* cost, const float* ground, const float* ceil, const pct_grid& g, int N,
+                             float d_ref, float w_z, const float* wp, const int* slice, int T, int W, const float* gf,
+                             float* gwp, float* gcost, float* gground, const EvalParams* ep, const int* aG,
+                             const int* aC, float* gz, long long n_points, hipStream_t s);
+pct_status launch_eval_bwd(const float* ground, const float* ceil, const float* gcost, const EvalParams& p,
+                           float* gground, float* gceil, hipStream_t s);
+pct_status launch_route(const float* gG, const float* gC, const int* aG, const int* aC, long long plane, int N,
+                        long long n_points, float* gz, hipStream_t s);
 
 }  // namespace pct
