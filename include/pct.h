@@ -239,6 +239,56 @@ pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, c
                                    const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
                                    int64_t n_points, float* d_gwp, float* d_gz, int32_t flags, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Batches: many submaps (and robots) per launch                          */
+
+/* Flag: the workspace already holds this batch's descriptor tables from an
+ * earlier call with the same items (and robots); nothing is copied from the
+ * host, so the call only enqueues kernels and can be captured in a graph. */
+#define PCT_DESCRIPTORS_RESIDENT 2
+
+/* One submap of a batch.  The caller sets xyz_offset, n_points and grid;
+ * pct_tomogram_extent_batched sets extent and the packing offsets: item i's
+ * [N][ny][nx] grids start at element out_offset of the packed grid outputs,
+ * its N slice flags at keep_offset of the packed flag outputs. */
+typedef struct {
+    int64_t xyz_offset;
+    int64_t n_points;
+    pct_grid grid;
+    int32_t reserved;
+    pct_extent extent;
+    int64_t out_offset;
+    int64_t keep_offset;
+} pct_item;
+
+/* Workspace bytes for the batched calls (the largest of the three). */
+size_t pct_batch_workspace_bytes(const pct_item* h_items, int32_t n_items, int32_t n_robots, int32_t with_ids);
+
+/* pct_tomogram_extent for every item, in one launch and one stream
+ * synchronisation.  d_xyz holds n_total points; item i uses points
+ * [xyz_offset, xyz_offset + n_points).  Writes h_items[i].extent and the
+ * packing offsets; *total_cells (sum of N nx ny) and *total_slices (sum of
+ * N) size the packed outputs. */
+pct_status pct_tomogram_extent_batched(const float* d_xyz, int64_t n_total, pct_item* h_items, int32_t n_items,
+                                       int64_t* total_cells, int64_t* total_slices, void* d_ws, size_t ws_bytes,
+                                       void* stream);
+
+/* pct_build_tomogram for every item in one launch per stage (binning, scan,
+ * scatter, tile reduce).  Outputs are packed: item i at out_offset.  Point
+ * ids index d_xyz.  flags: PCT_DESCRIPTORS_RESIDENT. */
+pct_status pct_build_tomogram_batched(const float* d_xyz, int64_t n_total, const pct_item* h_items, int32_t n_items,
+                                      float* d_ground, float* d_ceil, int32_t* d_arg_ground, int32_t* d_arg_ceil,
+                                      int32_t flags, void* d_ws, size_t ws_bytes, void* stream);
+
+/* pct_eval_traversability for every (item, robot) pair in one launch per
+ * stage.  d_cost is [n_robots][total_cells] (robot r, item i at
+ * r * total_cells + out_offset), d_keep [n_robots][total_slices] (nullable).
+ * flags: PCT_DESCRIPTORS_RESIDENT. */
+pct_status pct_eval_traversability_batched(const float* d_ground, const float* d_ceil, const pct_item* h_items,
+                                           int32_t n_items, const pct_robot* h_robots, int32_t n_robots,
+                                           float* d_cost, uint8_t* d_keep, int32_t flags, void* d_ws,
+                                           size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "pct_internal.h"
 
@@ -436,6 +437,140 @@ pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, c
     p.N = N;
     return launch_sample_bwd(d_cost, d_ground, d_ceil, *grid, N, h_robot->d_ref, w_z, d_wp, d_wp_slice, n_traj, n_wp,
                              d_gf, d_gwp, nullptr, nullptr, &p, d_arg_ground, d_arg_ceil, d_gz, n_points, s);
+}
+
+namespace {
+
+// Host table of device item descriptors (grids tiled, bases assigned).
+pct_status make_items(const pct_item* h, int n_items, int64_t n_total, bool need_extent, std::vector<BuildItemDev>* out) {
+    if (n_items < 1 || !h) return fail(PCT_ERR_ARG, "a batch needs at least one item");
+    out->resize(n_items);
+    int tile_base = 0, chunk_base = 0, echunk_base = 0;
+    for (int i = 0; i < n_items; ++i) {
+        pct_status st = check_grid(&h[i].grid);
+        char msg[512];
+        if (st != PCT_OK) {
+            snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(st, "item %d: %s", i, msg);
+        }
+        if (h[i].xyz_offset < 0 || h[i].n_points < 0 || h[i].xyz_offset + h[i].n_points > n_total)
+            return fail(PCT_ERR_ARG, "item %d: points [%lld, +%lld) outside the %lld given", i,
+                        (long long)h[i].xyz_offset, (long long)h[i].n_points, (long long)n_total);
+        if (n_total > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count outside [0, 2^31)");
+        BuildItemDev& d = (*out)[i];
+        d.g = make_grid_dev(h[i].grid);
+        d.xyz_off = h[i].xyz_offset;
+        d.n = h[i].n_points;
+        if (need_extent) {
+            st = check_extent(&h[i].extent);
+            if (st != PCT_OK) {
+                snprintf(msg, sizeof msg, "%s", g_err);
+                return fail(st, "item %d: %s", i, msg);
+            }
+            if (h[i].extent.n_slices > 0 &&
+                plane_count(h[i].extent.z_min, h[i].extent.z_max, h[i].grid.slice_dz, PCT_MAX_SLICES) != h[i].extent.n_slices)
+                return fail(PCT_ERR_ARG, "item %d: extent does not match the plane rule", i);
+            if (h[i].out_offset < 0) return fail(PCT_ERR_ARG, "item %d: negative out_offset", i);
+        }
+        d.zmin = h[i].extent.z_min;
+        d.ds = h[i].grid.slice_dz;
+        d.N = h[i].extent.n_slices;
+        d.out_off = h[i].out_offset;
+        d.tile_base = tile_base;
+        d.chunk_base = chunk_base;
+        d.echunk_base = echunk_base;
+        tile_base += d.g.ntiles;
+        chunk_base += (int)((d.n + kBatchChunk - 1) / kBatchChunk);
+        echunk_base += (int)std::max<int64_t>(1, (d.n + kBatchEChunk - 1) / kBatchEChunk);
+    }
+    return PCT_OK;
+}
+
+}  // namespace
+
+size_t pct_batch_workspace_bytes(const pct_item* h_items, int32_t n_items, int32_t n_robots, int32_t with_ids) {
+    std::vector<BuildItemDev> it;
+    int64_t tot = 0;
+    for (int i = 0; i < n_items; ++i) tot = std::max<int64_t>(tot, h_items[i].xyz_offset + h_items[i].n_points);
+    if (make_items(h_items, n_items, tot, false, &it) != PCT_OK) return 0;
+    size_t b = std::max(batch_extent_ws_bytes(it.data(), n_items), batch_build_ws_bytes(it.data(), n_items, with_ids != 0));
+    return std::max(b, batch_eval_ws_bytes(h_items, n_items, std::max(1, (int)n_robots)));
+}
+
+pct_status pct_tomogram_extent_batched(const float* d_xyz, int64_t n_total, pct_item* h_items, int32_t n_items,
+                                       int64_t* total_cells, int64_t* total_slices, void* d_ws, size_t ws_bytes,
+                                       void* stream) {
+    clear_error();
+    std::vector<BuildItemDev> it;
+    pct_status st = make_items(h_items, n_items, n_total, false, &it);
+    if (st != PCT_OK) return st;
+    if (n_total > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    const size_t need = batch_extent_ws_bytes(it.data(), n_items);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "batch extent workspace too small: %zu < %zu", ws_bytes, need);
+    std::vector<ExtentDev> ex(n_items);
+    st = launch_extent_batched(d_xyz, it.data(), n_items, d_ws, ex.data(), 1, (hipStream_t)stream);
+    if (st != PCT_OK) return st;
+    int64_t cells = 0, slices = 0;
+    for (int i = 0; i < n_items; ++i) {
+        pct_extent e{};
+        e.z_min = INFINITY;
+        e.z_max = -INFINITY;
+        e.n_used = (int64_t)ex[i].used;
+        e.n_dropped = h_items[i].n_points - e.n_used;
+        if (e.n_used > 0) {
+            e.z_min = ex[i].zmin;
+            e.z_max = ex[i].zmax;
+            const int N = plane_count(e.z_min, e.z_max, h_items[i].grid.slice_dz, PCT_MAX_SLICES);
+            if (N == -1) return fail(PCT_ERR_ARG, "item %d: slice planes coincide in FP32", i);
+            if (N == -2) return fail(PCT_ERR_CAPACITY, "item %d: more than %d slices needed", i, PCT_MAX_SLICES);
+            e.n_slices = N;
+        }
+        h_items[i].extent = e;
+        h_items[i].out_offset = cells;
+        h_items[i].keep_offset = slices;
+        cells += (int64_t)e.n_slices * h_items[i].grid.nx * h_items[i].grid.ny;
+        slices += e.n_slices;
+    }
+    if (total_cells) *total_cells = cells;
+    if (total_slices) *total_slices = slices;
+    return PCT_OK;
+}
+
+pct_status pct_build_tomogram_batched(const float* d_xyz, int64_t n_total, const pct_item* h_items, int32_t n_items,
+                                      float* d_ground, float* d_ceil, int32_t* d_arg_ground, int32_t* d_arg_ceil,
+                                      int32_t flags, void* d_ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    std::vector<BuildItemDev> it;
+    pct_status st = make_items(h_items, n_items, n_total, true, &it);
+    if (st != PCT_OK) return st;
+    if ((d_arg_ground == nullptr) != (d_arg_ceil == nullptr))
+        return fail(PCT_ERR_ARG, "d_arg_ground and d_arg_ceil must both be given or both be null");
+    if (n_total > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    if (!d_ground || !d_ceil) return fail(PCT_ERR_ARG, "output pointers are null");
+    return launch_build_batched(d_xyz, it.data(), n_items, d_ground, d_ceil, d_arg_ground, d_arg_ceil, d_ws, ws_bytes,
+                                !(flags & PCT_DESCRIPTORS_RESIDENT), (hipStream_t)stream);
+}
+
+pct_status pct_eval_traversability_batched(const float* d_ground, const float* d_ceil, const pct_item* h_items,
+                                           int32_t n_items, const pct_robot* h_robots, int32_t n_robots,
+                                           float* d_cost, uint8_t* d_keep, int32_t flags, void* d_ws,
+                                           size_t ws_bytes, void* stream) {
+    clear_error();
+    std::vector<BuildItemDev> it;
+    int64_t tot = 0;
+    for (int i = 0; h_items && i < n_items; ++i) tot = std::max<int64_t>(tot, h_items[i].xyz_offset + h_items[i].n_points);
+    pct_status st = make_items(h_items, n_items, tot, true, &it);
+    if (st != PCT_OK) return st;
+    if (n_robots < 1 || !h_robots) return fail(PCT_ERR_ARG, "at least one robot is required");
+    for (int r = 0; r < n_robots; ++r) {
+        for (int i = 0; i < n_items; ++i) {
+            st = check_robot(&h_robots[r], h_items[i].grid.res);
+            if (st != PCT_OK) return st;
+        }
+    }
+    if (!d_ground || !d_ceil || !d_cost) return fail(PCT_ERR_ARG, "device pointers are null");
+    return launch_eval_batched(d_ground, d_ceil, h_items, n_items, h_robots, n_robots, d_cost, d_keep, d_ws, ws_bytes,
+                               !(flags & PCT_DESCRIPTORS_RESIDENT), (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -348,14 +348,13 @@ __device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __r
     }
 }
 
+// One construction tile: records off[tg] .. off[tg+1] of the tile whose
+// position in its grid is tl.  Shared by the single-map and batched kernels.
 template <bool IDS>
-__global__ __launch_bounds__(kBlock) void k_tile_reduce(const unsigned* __restrict__ off,
-                                                        const float* __restrict__ rz,
-                                                        const unsigned* __restrict__ rmeta,
-                                                        const int* __restrict__ rid, GridDev g, float zmin,
-                                                        float ds, int N, float* __restrict__ ground,
-                                                        float* __restrict__ ceil, int* __restrict__ ag,
-                                                        int* __restrict__ ac) {
+__device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, const float* __restrict__ rz,
+                            const unsigned* __restrict__ rmeta, const int* __restrict__ rid, const GridDev& g,
+                            float zmin, float ds, int N, float* __restrict__ ground, float* __restrict__ ceil,
+                            int* __restrict__ ag, int* __restrict__ ac) {
     constexpr int CAP = IDS ? kReduceCapIds : kReduceCap;
     extern __shared__ unsigned s_mem[];
     const int cells = kBuildTileW * g.th;
@@ -364,9 +363,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_reduce(const unsigned* __restri
     float* s_z = (float*)(s_start + cells + 1);
     int* s_id = (int*)(s_z + CAP);
 
-    const int t = blockIdx.x;
-    const int tx = t % g.ntx, ty = t / g.ntx;
-    const unsigned r0 = off[t], r1 = off[t + 1];
+    const int tx = tl % g.ntx, ty = tl / g.ntx;
+    const unsigned r0 = off[tg], r1 = off[tg + 1];
 
     for (int c = threadIdx.x; c < cells; c += kBlock) s_cnt[c] = 0;
     __syncthreads();
@@ -441,6 +439,17 @@ __global__ __launch_bounds__(kBlock) void k_tile_reduce(const unsigned* __restri
     }
 }
 
+template <bool IDS>
+__global__ __launch_bounds__(kBlock) void k_tile_reduce(const unsigned* __restrict__ off,
+                                                        const float* __restrict__ rz,
+                                                        const unsigned* __restrict__ rmeta,
+                                                        const int* __restrict__ rid, GridDev g, float zmin,
+                                                        float ds, int N, float* __restrict__ ground,
+                                                        float* __restrict__ ceil, int* __restrict__ ag,
+                                                        int* __restrict__ ac) {
+    reduce_tile<IDS>((int)blockIdx.x, (int)blockIdx.x, off, rz, rmeta, rid, g, zmin, ds, N, ground, ceil, ag, ac);
+}
+
 inline size_t reduce_lds_bytes(const GridDev& g, bool ids) {
     const int cells = kBuildTileW * g.th;
     return sizeof(unsigned) * (2 * cells + 1) + (ids ? (size_t)kReduceCapIds * 8 : (size_t)kReduceCap * 4);
@@ -483,6 +492,225 @@ BuildWs carve_build_ws(void* base, int64_t n, const GridDev& g, bool ids) {
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ batches
+//
+// Many submaps in one launch per stage.  Workgroups are dealt out over
+// global chunks (binning, extents) or global tiles (reduce); each finds its
+// item by binary search over the item table's bases.
+
+__device__ __forceinline__ int find_base(const BuildItemDev* __restrict__ items, int n_items, int v, int which) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        const int b = which == 0 ? items[mid].chunk_base : (which == 1 ? items[mid].tile_base : items[mid].echunk_base);
+        if (b <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bextent(const float* __restrict__ xyz, const BuildItemDev* __restrict__ items,
+                                                    int n_items, float* __restrict__ pmin, float* __restrict__ pmax,
+                                                    unsigned long long* __restrict__ pused) {
+    const int c = blockIdx.x;
+    const int it = find_base(items, n_items, c, 2);
+    const BuildItemDev& d = items[it];
+    const long long b0 = (long long)(c - d.echunk_base) * kBatchEChunk, b1 = min(d.n, b0 + kBatchEChunk);
+    float lo = INFINITY, hi = -INFINITY;
+    unsigned long long used = 0;
+    for (long long i = b0 + threadIdx.x; i < b1; i += kBlock) {
+        const long long j = d.xyz_off + i;
+        float x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+        int ix, iy;
+        if (!isfinite(z) || !rasterize(x, y, d.g, ix, iy)) continue;
+        z = z + 0.0f;
+        lo = fminf(lo, z);
+        hi = fmaxf(hi, z);
+        ++used;
+    }
+    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+    __shared__ unsigned long long s_u[kBlock / 64];
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    used = wave_sum(used);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+        s_u[w] = used;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            lo = fminf(lo, s_lo[i]);
+            hi = fmaxf(hi, s_hi[i]);
+            used += s_u[i];
+        }
+        pmin[c] = lo;
+        pmax[c] = hi;
+        pused[c] = used;
+    }
+}
+
+// one workgroup per item: reduce its chunks' partials
+__global__ __launch_bounds__(kBlock) void k_bextent_final(const BuildItemDev* __restrict__ items, int n_items,
+                                                          int n_echunks, const float* __restrict__ pmin,
+                                                          const float* __restrict__ pmax,
+                                                          const unsigned long long* __restrict__ pused,
+                                                          ExtentDev* __restrict__ out) {
+    const int it = blockIdx.x;
+    const int c0 = items[it].echunk_base, c1 = it + 1 < n_items ? items[it + 1].echunk_base : n_echunks;
+    float lo = INFINITY, hi = -INFINITY;
+    unsigned long long used = 0;
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) {
+        lo = fminf(lo, pmin[c]);
+        hi = fmaxf(hi, pmax[c]);
+        used += pused[c];
+    }
+    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+    __shared__ unsigned long long s_u[kBlock / 64];
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    used = wave_sum(used);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+        s_u[w] = used;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            lo = fminf(lo, s_lo[i]);
+            hi = fmaxf(hi, s_hi[i]);
+            used += s_u[i];
+        }
+        out[it].zmin = lo;
+        out[it].zmax = hi;
+        out[it].used = used;
+    }
+}
+
+// Per-chunk tile counts of the chunk's item: LDS histogram, one global
+// atomic per touched tile.
+__global__ __launch_bounds__(kBlock) void k_bcount(const float* __restrict__ xyz, const BuildItemDev* __restrict__ items,
+                                                   int n_items, unsigned* __restrict__ gcount) {
+    extern __shared__ unsigned s_cnt[];
+    const int c = blockIdx.x;
+    const int it = find_base(items, n_items, c, 0);
+    const BuildItemDev& d = items[it];
+    const bool lds = d.g.ntiles <= kMaxLdsTiles;
+    if (lds)
+        for (int t = threadIdx.x; t < d.g.ntiles; t += kBlock) s_cnt[t] = 0;
+    __syncthreads();
+    const long long b0 = (long long)(c - d.chunk_base) * kBatchChunk, b1 = min(d.n, b0 + kBatchChunk);
+    for (long long i = b0 + threadIdx.x; i < b1; i += kBlock) {
+        int tile;
+        unsigned cell;
+        float z;
+        if (!bin_point(xyz, d.xyz_off + i, d.g, tile, cell, z)) continue;
+        if (lds) atomicAdd(&s_cnt[tile], 1u);
+        else atomicAdd(&gcount[d.tile_base + tile], 1u);
+    }
+    __syncthreads();
+    if (lds)
+        for (int t = threadIdx.x; t < d.g.ntiles; t += kBlock)
+            if (s_cnt[t]) atomicAdd(&gcount[d.tile_base + t], s_cnt[t]);
+}
+
+template <bool IDS>
+__global__ __launch_bounds__(kBlock) void k_bscatter(const float* __restrict__ xyz, const BuildItemDev* __restrict__ items,
+                                                     int n_items, unsigned* __restrict__ cursor, float* __restrict__ rz,
+                                                     unsigned* __restrict__ rmeta, int* __restrict__ rid) {
+    extern __shared__ unsigned s_mem[];
+    const int c = blockIdx.x;
+    const int it = find_base(items, n_items, c, 0);
+    const BuildItemDev& d = items[it];
+    const bool lds = d.g.ntiles <= kMaxLdsTiles;
+    unsigned* s_cnt = s_mem;
+    unsigned* s_base = s_mem + (lds ? d.g.ntiles : 0);
+    if (lds)
+        for (int t = threadIdx.x; t < d.g.ntiles; t += kBlock) s_cnt[t] = 0;
+    __syncthreads();
+    const long long b0 = (long long)(c - d.chunk_base) * kBatchChunk, b1 = min(d.n, b0 + kBatchChunk);
+    if (lds) {
+        for (long long i = b0 + threadIdx.x; i < b1; i += kBlock) {
+            int tile;
+            unsigned cell;
+            float z;
+            if (bin_point(xyz, d.xyz_off + i, d.g, tile, cell, z)) atomicAdd(&s_cnt[tile], 1u);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < d.g.ntiles; t += kBlock) {
+            const unsigned k = s_cnt[t];
+            if (k) s_base[t] = atomicAdd(&cursor[d.tile_base + t], k);
+            s_cnt[t] = 0;
+        }
+        __syncthreads();
+    }
+    for (long long i = b0 + threadIdx.x; i < b1; i += kBlock) {
+        int tile;
+        unsigned cell;
+        float z;
+        if (!bin_point(xyz, d.xyz_off + i, d.g, tile, cell, z)) continue;
+        const unsigned pos = lds ? s_base[tile] + atomicAdd(&s_cnt[tile], 1u) : atomicAdd(&cursor[d.tile_base + tile], 1u);
+        rz[pos] = z;
+        rmeta[pos] = cell;
+        if (IDS) rid[pos] = (int)(d.xyz_off + i);
+    }
+}
+
+template <bool IDS>
+__global__ __launch_bounds__(kBlock) void k_breduce(const unsigned* __restrict__ off, const float* __restrict__ rz,
+                                                    const unsigned* __restrict__ rmeta, const int* __restrict__ rid,
+                                                    const BuildItemDev* __restrict__ items, int n_items,
+                                                    float* __restrict__ ground, float* __restrict__ ceil,
+                                                    int* __restrict__ ag, int* __restrict__ ac) {
+    const int tg = blockIdx.x;
+    const int it = find_base(items, n_items, tg, 1);
+    const BuildItemDev& d = items[it];
+    if (d.N <= 0) return;
+    const long long o = d.out_off;
+    reduce_tile<IDS>(tg, tg - d.tile_base, off, rz, rmeta, rid, d.g, d.zmin, d.ds, d.N, ground + o, ceil + o,
+                     IDS ? ag + o : nullptr, IDS ? ac + o : nullptr);
+}
+
+struct BatchWs {
+    BuildItemDev* items;
+    unsigned *count, *off, *cursor;
+    float* rz;
+    unsigned* rmeta;
+    int* rid;
+    size_t bytes;
+    int total_tiles, total_chunks;
+    long long total_points;
+};
+
+BatchWs carve_batch_ws(void* base, const BuildItemDev* h, int n_items, bool ids) {
+    BatchWs w{};
+    char* p = (char*)base;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* r = p ? p + o : nullptr;
+        o += align_up(bytes);
+        return r;
+    };
+    for (int i = 0; i < n_items; ++i) {
+        w.total_tiles += h[i].g.ntiles;
+        w.total_chunks += (int)((h[i].n + kBatchChunk - 1) / kBatchChunk);
+        w.total_points += h[i].n;
+    }
+    w.items = (BuildItemDev*)take(sizeof(BuildItemDev) * (size_t)n_items);
+    w.count = (unsigned*)take(sizeof(unsigned) * (size_t)(w.total_tiles + 1));
+    w.off = (unsigned*)take(sizeof(unsigned) * (size_t)(w.total_tiles + 1));
+    w.cursor = (unsigned*)take(sizeof(unsigned) * (size_t)(w.total_tiles + 1));
+    w.rz = (float*)take(sizeof(float) * (size_t)w.total_points);
+    w.rmeta = (unsigned*)take(sizeof(unsigned) * (size_t)w.total_points);
+    w.rid = ids ? (int*)take(sizeof(int) * (size_t)w.total_points) : nullptr;
+    w.bytes = o;
+    return w;
+}
 
 size_t extent_ws_bytes(int64_t) {
     return align_up(sizeof(float) * kExtentBlocks) * 2 + align_up(sizeof(unsigned long long) * kExtentBlocks) +
@@ -584,6 +812,88 @@ GridDev make_grid_dev(const pct_grid& gr) {
     g.nty = (gr.ny + g.th - 1) / g.th;
     g.ntiles = g.ntx * g.nty;
     return g;
+}
+
+size_t batch_extent_ws_bytes(const BuildItemDev* items, int n_items) {
+    long long nch = 0;
+    for (int i = 0; i < n_items; ++i) nch += std::max<long long>(1, (items[i].n + kBatchEChunk - 1) / kBatchEChunk);
+    return align_up(sizeof(BuildItemDev) * (size_t)n_items) + 2 * align_up(sizeof(float) * (size_t)nch) +
+           align_up(sizeof(unsigned long long) * (size_t)nch) + align_up(sizeof(ExtentDev) * (size_t)n_items);
+}
+
+pct_status launch_extent_batched(const float* xyz, const BuildItemDev* h_items, int n_items, void* ws,
+                                 ExtentDev* h_out, int upload, hipStream_t s) {
+    long long nch = 0;
+    for (int i = 0; i < n_items; ++i) nch += std::max<long long>(1, (h_items[i].n + kBatchEChunk - 1) / kBatchEChunk);
+    char* p = (char*)ws;
+    BuildItemDev* d_items = (BuildItemDev*)p;
+    p += align_up(sizeof(BuildItemDev) * (size_t)n_items);
+    float* pmin = (float*)p;
+    p += align_up(sizeof(float) * (size_t)nch);
+    float* pmax = (float*)p;
+    p += align_up(sizeof(float) * (size_t)nch);
+    unsigned long long* pused = (unsigned long long*)p;
+    p += align_up(sizeof(unsigned long long) * (size_t)nch);
+    ExtentDev* d_out = (ExtentDev*)p;
+    if (upload) PCT_HIP(hipMemcpyAsync(d_items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bextent, dim3((unsigned)nch), dim3(kBlock), 0, s, xyz, d_items, n_items, pmin, pmax, pused);
+    PCT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bextent_final, dim3(n_items), dim3(kBlock), 0, s, d_items, n_items, (int)nch, pmin, pmax, pused,
+                       d_out);
+    PCT_LAUNCH_CHECK();
+    if (h_out) {
+        PCT_HIP(hipMemcpyAsync(h_out, d_out, sizeof(ExtentDev) * n_items, hipMemcpyDeviceToHost, s));
+        PCT_HIP(hipStreamSynchronize(s));
+    }
+    return PCT_OK;
+}
+
+size_t batch_build_ws_bytes(const BuildItemDev* items, int n_items, bool ids) {
+    return carve_batch_ws(nullptr, items, n_items, ids).bytes;
+}
+
+pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, int n_items, float* ground, float* ceil,
+                                int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes, int upload, hipStream_t s) {
+    const bool ids = ag != nullptr;
+    BatchWs w = carve_batch_ws(ws, h_items, n_items, ids);
+    if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", ws_bytes, w.bytes);
+    if (upload) PCT_HIP(hipMemcpyAsync(w.items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
+    int max_tiles_lds = 0;
+    size_t max_reduce_lds = 0;
+    for (int i = 0; i < n_items; ++i) {
+        if (h_items[i].g.ntiles <= kMaxLdsTiles) max_tiles_lds = std::max(max_tiles_lds, h_items[i].g.ntiles);
+        max_reduce_lds = std::max(max_reduce_lds, reduce_lds_bytes(h_items[i].g, ids));
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(std::min(1024, w.total_tiles / kBlock + 1)), dim3(kBlock), 0, s, w.count,
+                       (int64_t)w.total_tiles + 1, 0u);
+    PCT_LAUNCH_CHECK();
+    if (w.total_chunks > 0) {
+        hipLaunchKernelGGL(k_bcount, dim3(w.total_chunks), dim3(kBlock), sizeof(unsigned) * max_tiles_lds, s, xyz, w.items,
+                           n_items, w.count);
+        PCT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, w.total_tiles, w.off, w.cursor);
+    PCT_LAUNCH_CHECK();
+    if (w.total_chunks > 0) {
+        const size_t lb = 2 * sizeof(unsigned) * max_tiles_lds;
+        if (ids)
+            hipLaunchKernelGGL(k_bscatter<true>, dim3(w.total_chunks), dim3(kBlock), lb, s, xyz, w.items, n_items,
+                               w.cursor, w.rz, w.rmeta, w.rid);
+        else
+            hipLaunchKernelGGL(k_bscatter<false>, dim3(w.total_chunks), dim3(kBlock), lb, s, xyz, w.items, n_items,
+                               w.cursor, w.rz, w.rmeta, w.rid);
+        PCT_LAUNCH_CHECK();
+    }
+    if (w.total_tiles > 0) {
+        if (ids)
+            hipLaunchKernelGGL(k_breduce<true>, dim3(w.total_tiles), dim3(kBlock), max_reduce_lds, s, w.off, w.rz, w.rmeta,
+                               w.rid, w.items, n_items, ground, ceil, ag, ac);
+        else
+            hipLaunchKernelGGL(k_breduce<false>, dim3(w.total_tiles), dim3(kBlock), max_reduce_lds, s, w.off, w.rz,
+                               w.rmeta, w.rid, w.items, n_items, ground, ceil, ag, ac);
+        PCT_LAUNCH_CHECK();
+    }
+    return PCT_OK;
 }
 
 }  // namespace pct

@@ -9,6 +9,8 @@
 //   c^T(x, y) = max_a max(V_a(x-a, y), V_a(x+a, y))             (row pass)
 // Each product K * c is the same FP32 multiply as in the direct 2-D window
 // and max is exact, so the result equals the direct FP32 window max.
+#include <vector>
+
 #include "pct_internal.h"
 
 namespace pct {
@@ -175,17 +177,14 @@ __device__ __forceinline__ float maxnn(float a, float b) {
     return __builtin_bit_cast(float, max(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)));
 }
 
+// One wavefront's strip: work index w of a map with parameters p and strip
+// geometry sg (ground/ceil/cost already point at the map's first slice).
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
-                                                       const EvalParams p, float* __restrict__ cost, const StripGeom sg) {
+__device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground, const float* __restrict__ ceil,
+                                                const EvalParams& p, float* __restrict__ cost, const StripGeom& sg,
+                                                int w) {
     constexpr int HX = R + 2;            // halo columns: inflation R, patch 1, stencil 1
     constexpr int OUTW = 64 - 2 * HX;
-    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin; give
-    // each XCD a contiguous range of strips so that neighbours share an L2.
-    const int per_xcd = gridDim.x / 8;
-    const int wb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const int w = wb * (kBlock / 64) + (int)(threadIdx.x / 64);
-    if (w >= sg.n_work) return;
     const int sx = w % sg.n_sx;
     const int t = w / sg.n_sx;
     const int sy = t % sg.n_sy;
@@ -296,6 +295,56 @@ __global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__
     }
 }
 
+// XCD-aware order: workgroups are dealt to the 8 XCDs round-robin; give
+// each XCD a contiguous range of strips so that neighbours share an L2.
+__device__ __forceinline__ int xcd_wave_index() {
+    const int per_xcd = gridDim.x / 8;
+    const int wb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    return wb * (kBlock / 64) + (int)(threadIdx.x / 64);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
+                                                       const EvalParams p, float* __restrict__ cost, const StripGeom sg) {
+    const int w = xcd_wave_index();
+    if (w >= sg.n_work) return;
+    eval_strip_wave<R>(ground, ceil, p, cost, sg, w);
+}
+
+// A batch: jobs are (map, robot) pairs with their own parameters, strip
+// geometry and offsets; one launch covers every job's strips.
+struct EvalJob {
+    EvalParams p;
+    StripGeom sg;
+    long long in_off, out_off, keep_off;   // element offsets of ground/ceil, cost, keep
+    long long cell_base;                   // first global cell of the job (slice test)
+    long long ws_off;                      // byte offset of the job's slice-test scratch
+    int work_base;                         // first global strip of the job
+    int pad;
+};
+
+__device__ __forceinline__ int find_job_work(const EvalJob* __restrict__ jobs, int n_jobs, int w) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].work_base <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restrict__ ground,
+                                                            const float* __restrict__ ceil,
+                                                            const EvalJob* __restrict__ jobs, int n_jobs, int n_work,
+                                                            float* __restrict__ cost) {
+    const int w = xcd_wave_index();
+    if (w >= n_work) return;
+    const int j = __builtin_amdgcn_readfirstlane(find_job_work(jobs, n_jobs, w));
+    const EvalJob& jb = jobs[j];
+    eval_strip_wave<R>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w - jb.work_base);
+}
+
 StripGeom strip_geom(const EvalParams& p) {
     const int outw = 64 - 2 * (p.R + 2);
     StripGeom g{};
@@ -370,12 +419,11 @@ __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, u
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) maxp0[i] = -1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__ ground, const float* __restrict__ cost,
-                                                       const int nx, const int ny, const int N, const float cB,
-                                                       const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun) {
-    const long long plane = (long long)nx * ny;
-    const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const bool active = cell < plane;
+// Slice-test flags of one cell (all lanes of a wavefront must call it
+// together; lanes without a cell pass active = false).
+__device__ __forceinline__ void simp_flags_cell(const float* __restrict__ ground, const float* __restrict__ cost,
+                                                long long plane, int N, float cB, int W, int* __restrict__ maxp0,
+                                                unsigned* __restrict__ urun, long long cell, bool active) {
     const int lane = threadIdx.x & 63;
     float ek = active ? ground[cell] : -INFINITY;
     float ck = active ? cost[cell] : cB;
@@ -413,9 +461,16 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__
     }
 }
 
-__global__ void k_keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
-                             uint8_t* __restrict__ keep) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__ ground, const float* __restrict__ cost,
+                                                       const int nx, const int ny, const int N, const float cB,
+                                                       const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun) {
+    const long long plane = (long long)nx * ny;
+    const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
+    simp_flags_cell(ground, cost, plane, N, cB, W, maxp0, urun, cell < plane ? cell : 0, cell < plane);
+}
+
+__device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
+                           uint8_t* __restrict__ keep) {
     int p = -1;
     for (int k = 0; k < N; ++k) {
         const int m = maxp0[k];
@@ -425,6 +480,61 @@ __global__ void k_keep_chain(const int* __restrict__ maxp0, const unsigned* __re
         keep[k] = u ? 1 : 0;
         if (u) p = k;
     }
+}
+
+__global__ void k_keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
+                             uint8_t* __restrict__ keep) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    keep_chain(maxp0, urun, N, W, keep);
+}
+
+// ---- batched slice test: one workgroup per job for the init and chain,
+// job cell ranges padded to whole wavefronts for the flags
+
+__device__ __forceinline__ int find_job_cell(const EvalJob* __restrict__ jobs, int n_jobs, long long c) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].cell_base <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_simp_init_jobs(const EvalJob* __restrict__ jobs, char* __restrict__ ws) {
+    const EvalJob& jb = jobs[blockIdx.x];
+    const int N = jb.p.N, W = (N + 31) / 32;
+    int* maxp0 = (int*)(ws + jb.ws_off);
+    unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
+    for (int i = threadIdx.x; i < N * W; i += kBlock) urun[i] = 0u;
+    for (int i = threadIdx.x; i < N; i += kBlock) maxp0[i] = -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restrict__ ground,
+                                                            const float* __restrict__ cost,
+                                                            const EvalJob* __restrict__ jobs, int n_jobs,
+                                                            char* __restrict__ ws) {
+    const long long g = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const int j = __builtin_amdgcn_readfirstlane(find_job_cell(jobs, n_jobs, g - (threadIdx.x & 63)));
+    const EvalJob& jb = jobs[j];
+    const long long cell = g - jb.cell_base;
+    const bool active = cell >= 0 && cell < jb.p.plane;
+    const int N = jb.p.N, W = (N + 31) / 32;
+    int* maxp0 = (int*)(ws + jb.ws_off);
+    unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
+    simp_flags_cell(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
+                    active ? cell : 0, active);
+}
+
+__global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, const char* __restrict__ ws,
+                                  uint8_t* __restrict__ keep) {
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= n_jobs) return;
+    const EvalJob& jb = jobs[j];
+    const int N = jb.p.N, W = (N + 31) / 32;
+    const int* maxp0 = (const int*)(ws + jb.ws_off);
+    const unsigned* urun = (const unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
+    keep_chain(maxp0, urun, N, W, keep + jb.keep_off);
 }
 
 }  // namespace
@@ -466,6 +576,116 @@ pct_status launch_simplify(const float* ground, const float* cost, const EvalPar
     PCT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_keep_chain, dim3(1), dim3(64), 0, s, maxp0, urun, p.N, W, keep);
     PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+// ------------------------------------------------------------ batches (host)
+
+namespace {
+
+struct JobPlan {
+    std::vector<EvalJob> jobs;
+    int n_work = 0;
+    long long cells = 0;     // padded cells of all jobs
+    size_t scratch = 0;      // bytes of slice-test scratch
+    int R = -1;
+    bool strip = true;       // every job can use the strip kernel with one R
+};
+
+pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots, int n_robots, JobPlan* jp) {
+    long long total_cells = 0, total_slices = 0;
+    for (int i = 0; i < n_items; ++i) {
+        total_cells = std::max<long long>(total_cells, items[i].out_offset +
+                                                           (long long)items[i].extent.n_slices * items[i].grid.nx * items[i].grid.ny);
+        total_slices = std::max<long long>(total_slices, items[i].keep_offset + items[i].extent.n_slices);
+    }
+    for (int r = 0; r < n_robots; ++r)
+        for (int i = 0; i < n_items; ++i) {
+            const int N = items[i].extent.n_slices;
+            if (N <= 0) continue;
+            EvalJob jb{};
+            pct_status st = make_eval_params(robots[r], items[i].grid, N, &jb.p);
+            if (st != PCT_OK) return st;
+            jb.sg = strip_geom(jb.p);
+            jb.in_off = items[i].out_offset;
+            jb.out_off = (long long)r * total_cells + items[i].out_offset;
+            jb.keep_off = (long long)r * total_slices + items[i].keep_offset;
+            jb.cell_base = jp->cells;
+            jb.ws_off = (long long)jp->scratch;
+            jb.work_base = jp->n_work;
+            jp->cells += (jb.p.plane + 63) / 64 * 64;
+            jp->scratch += align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * ((N + 31) / 32));
+            jp->n_work += jb.sg.n_work;
+            if (jp->R < 0) jp->R = jb.p.R;
+            if (jb.p.R != jp->R || jb.p.rp != 1 || jb.p.R > 8) jp->strip = false;
+            jp->jobs.push_back(jb);
+        }
+    return PCT_OK;
+}
+
+template <int R>
+pct_status launch_jobs_r(const float* ground, const float* ceil, const EvalJob* d_jobs, int n_jobs, int n_work,
+                         float* cost, hipStream_t s) {
+    int blocks = (n_work + kBlock / 64 - 1) / (kBlock / 64);
+    blocks = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_eval_strip_jobs<R>, dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_jobs, n_jobs, n_work,
+                       cost);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+}  // namespace
+
+size_t batch_eval_ws_bytes(const pct_item* items, int n_items, int n_robots) {
+    std::vector<pct_robot> rs(n_robots);
+    for (auto& r : rs) {
+        r = pct_robot{};
+        r.d_sm = 1.0f;
+        r.patch_radius = 1;
+        r.c_barrier = 1.0f;
+    }
+    JobPlan jp;
+    if (plan_jobs(items, n_items, rs.data(), n_robots, &jp) != PCT_OK) return 0;
+    return align_up(sizeof(EvalJob) * jp.jobs.size()) + jp.scratch;
+}
+
+pct_status launch_eval_batched(const float* ground, const float* ceil, const pct_item* items, int n_items,
+                               const pct_robot* robots, int n_robots, float* cost, uint8_t* keep, void* ws,
+                               size_t ws_bytes, int upload, hipStream_t s) {
+    JobPlan jp;
+    pct_status st = plan_jobs(items, n_items, robots, n_robots, &jp);
+    if (st != PCT_OK) return st;
+    const int n_jobs = (int)jp.jobs.size();
+    if (n_jobs == 0) return PCT_OK;
+    const size_t need = align_up(sizeof(EvalJob) * n_jobs) + jp.scratch;
+    if (!ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "batch eval workspace too small: %zu < %zu", ws_bytes, need);
+    EvalJob* d_jobs = (EvalJob*)ws;
+    char* scratch = (char*)ws + align_up(sizeof(EvalJob) * n_jobs);
+    if (upload) PCT_HIP(hipMemcpyAsync(d_jobs, jp.jobs.data(), sizeof(EvalJob) * n_jobs, hipMemcpyHostToDevice, s));
+    if (jp.strip) {
+        switch (jp.R) {
+#define PCT_J(r) case r: st = launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s); break;
+            PCT_J(0) PCT_J(1) PCT_J(2) PCT_J(3) PCT_J(4) PCT_J(5) PCT_J(6) PCT_J(7) PCT_J(8)
+#undef PCT_J
+            default: return fail(PCT_ERR_CAPACITY, "inflation radius %d", jp.R);
+        }
+        if (st != PCT_OK) return st;
+    } else {
+        // mixed radii or patch sizes: one launch per job
+        for (const EvalJob& jb : jp.jobs) {
+            st = launch_eval(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, s);
+            if (st != PCT_OK) return st;
+        }
+    }
+    if (keep) {
+        hipLaunchKernelGGL(k_simp_init_jobs, dim3(n_jobs), dim3(kBlock), 0, s, d_jobs, scratch);
+        PCT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_simp_flags_jobs, dim3((unsigned)((jp.cells + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           ground, cost, d_jobs, n_jobs, scratch);
+        PCT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_keep_chain_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, s, d_jobs, n_jobs, scratch, keep);
+        PCT_LAUNCH_CHECK();
+    }
     return PCT_OK;
 }
 

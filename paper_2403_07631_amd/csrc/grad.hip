@@ -186,34 +186,63 @@ struct Bil {
     float fu, fv, du, dv;
 };
 
-__device__ __forceinline__ void axis(float q, int n, int& i0, int& i1, float& f, float& dq) {
+// Cell-centred coordinate u = (x - x0) / r - 1/2 split into an integer
+// part and a fraction.  Far from the origin u is large (2000 cells on a
+// 200 m map) and one FP32 rounding of u would cost ~1e-4 of a cell; here
+// the subtraction's error (two-sum) and the exact remainder of the
+// correctly rounded quotient, fma(-q, r, dx), give the fraction to ~1e-7.
+__device__ __forceinline__ void split_coord(float x, float x0, float r, int& i, float& f) {
+    // dx + e = x - x0 exactly (two-sum)
+    const float dx = x - x0;
+    const float bb = dx - x;
+    const float e = (x - (dx - bb)) + (-x0 - bb);
+    const float q = dx / r;
+    const float rem = __builtin_fmaf(-q, r, dx) + e;
+    const float qs = q - 0.5f;
+    const float fl = floorf(qs);
+    f = (qs - fl) + rem / r;
+    i = (int)fl;
+    if (f < 0.0f) { f += 1.0f; --i; }
+    else if (f >= 1.0f) { f -= 1.0f; ++i; }
+}
+
+// Clamp to the grid edge (zero slope across the clamp): u = i + f.
+__device__ __forceinline__ void axis(int i, float f, int n, int& i0, int& i1, float& fr, float& dq) {
     if (n == 1) {
         i0 = i1 = 0;
-        f = 0.0f;
+        fr = 0.0f;
         dq = 0.0f;
         return;
     }
-    float qc = q;
-    bool clamped = false;
-    if (q < 0.0f) { qc = 0.0f; clamped = true; }
-    else if (q > (float)(n - 1)) { qc = (float)(n - 1); clamped = true; }
-    int a = (int)floorf(qc);
-    if (a > n - 2) a = n - 2;
-    i0 = a;
-    i1 = a + 1;
-    f = qc - (float)a;
-    dq = clamped ? 0.0f : 1.0f;
+    dq = 1.0f;
+    if (i < 0) {                                   // u < 0
+        i = 0;
+        f = 0.0f;
+        dq = 0.0f;
+    } else if (i > n - 1 || (i == n - 1 && f > 0.0f)) {   // u > n - 1
+        i = n - 1;
+        f = 0.0f;
+        dq = 0.0f;
+    }
+    if (i > n - 2) {                               // u = n - 1 exactly
+        i = n - 2;
+        f += 1.0f;
+    }
+    i0 = i;
+    i1 = i + 1;
+    fr = f;
 }
 
 __device__ Bil bilinear(const float* __restrict__ ground, const SampleArgs& a, float x, float y, float z, int k) {
     Bil b{};
     if (k < 0 || k >= a.N || !isfinite(x) || !isfinite(y) || !isfinite(z)) return b;
     b.ok = true;
-    const float u = (x - a.x0) / a.res - 0.5f;
-    const float v = (y - a.y0) / a.res - 0.5f;
-    int i0, i1, j0, j1;
-    axis(u, a.nx, i0, i1, b.fu, b.du);
-    axis(v, a.ny, j0, j1, b.fv, b.dv);
+    int iu, iv, i0, i1, j0, j1;
+    float fu, fv;
+    split_coord(x, a.x0, a.res, iu, fu);
+    split_coord(y, a.y0, a.res, iv, fv);
+    axis(iu, fu, a.nx, i0, i1, b.fu, b.du);
+    axis(iv, fv, a.ny, j0, j1, b.fv, b.dv);
     b.du *= a.inv_res;
     b.dv *= a.inv_res;
     const long long base = (long long)k * a.plane;

@@ -28,7 +28,7 @@ void clear_error();
             return ::pct::fail(PCT_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
     } while (0)
 
-inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+__host__ __device__ inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- grids
 // Construction tiles are 256 cells wide (each output row of a tile is one
@@ -72,6 +72,23 @@ struct ExtentDev {
     unsigned long long used;
 };
 
+// ---------------------------------------------------------------- batches
+// One item of a batch (a submap): its points, grid, planes and where its
+// outputs go.  Uploaded to the workspace as a device table.
+struct BuildItemDev {
+    GridDev g;
+    long long xyz_off, n;
+    float zmin, ds;
+    int N;
+    long long out_off;      // element offset of the item's [N][ny][nx] outputs
+    int tile_base;          // first global construction tile
+    int chunk_base;         // first global binning chunk
+    int echunk_base;        // first global extent chunk
+};
+
+constexpr int kBatchChunk = 8192;     // points per workgroup in batched binning
+constexpr int kBatchEChunk = 65536;   // points per workgroup in batched extents
+
 // ---------------------------------------------------------------- eval
 constexpr int kEvalTileW = 64;
 constexpr int kEvalTileH = 16;
@@ -108,6 +125,19 @@ pct_status launch_simplify(const float* ground, const float* cost, const EvalPar
                            void* ws, hipStream_t s);
 
 pct_status launch_zero(float* p, long long n, hipStream_t s);
+
+// batched construction (items: device table; host copy for launch sizes)
+size_t batch_extent_ws_bytes(const BuildItemDev* items, int n_items);
+pct_status launch_extent_batched(const float* xyz, const BuildItemDev* h_items, int n_items, void* ws,
+                                 ExtentDev* h_out, int upload, hipStream_t s);
+size_t batch_build_ws_bytes(const BuildItemDev* items, int n_items, bool ids);
+size_t batch_eval_ws_bytes(const pct_item* items, int n_items, int n_robots);
+pct_status launch_eval_batched(const float* ground, const float* ceil, const pct_item* items, int n_items,
+                               const pct_robot* robots, int n_robots, float* cost, uint8_t* keep, void* ws,
+                               size_t ws_bytes, int upload, hipStream_t s);
+pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, int n_items, float* ground,
+                                float* ceil, int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes, int upload,
+                                hipStream_t s);
 pct_status launch_sample_fwd(const float* cost, const float* ground, const pct_grid& g, int N, float d_ref, float w_z,
                              const float* wp, const int* slice, int T, int W, float* f, hipStream_t s);
 pct_status launch_sample_bwd(const float* cost, const float* ground, const float* ceil, const pct_grid& g, int N,
