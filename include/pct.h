@@ -244,7 +244,9 @@ pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, c
 
 /* Flag: the workspace already holds this batch's descriptor tables from an
  * earlier call with the same items (and robots); nothing is copied from the
- * host, so the call only enqueues kernels and can be captured in a graph. */
+ * host, so the call only enqueues kernels and can be captured in a graph.
+ * Without the flag the call copies the tables from host memory and waits on
+ * the stream until that copy is done (the host tables are temporary). */
 #define PCT_DESCRIPTORS_RESIDENT 2
 
 /* One submap of a batch.  The caller sets xyz_offset, n_points and grid;
@@ -288,6 +290,33 @@ pct_status pct_eval_traversability_batched(const float* d_ground, const float* d
                                            int32_t n_items, const pct_robot* h_robots, int32_t n_robots,
                                            float* d_cost, uint8_t* d_keep, int32_t flags, void* d_ws,
                                            size_t ws_bytes, void* stream);
+
+/* Workspace bytes for pct_trajectory_cost_multi with n_profiles profiles. */
+size_t pct_trajectory_multi_workspace_bytes(int32_t n_profiles);
+
+/* Many robot profiles on one map in one launch (Sec. III-B evaluation with
+ * the Sec. III-E / Eq. (11) cost and height terms).  Profile p samples its
+ * own trajectories as pct_sample_cost_fwd does with that profile's c^T and,
+ * given d_gf, differentiates them as pct_trajectory_cost_bwd does.  No cost
+ * map is formed: c^T is evaluated by Eqs. (1)-(6) only at the four bilinear
+ * corners of each waypoint, with the same FP32 operations as
+ * pct_eval_traversability, so d_f and d_gwp equal the per-profile path's
+ * bit for bit.
+ * h_robots: host [n_profiles]; d_wp: float32 [n_profiles][n_traj][n_wp][3];
+ * d_wp_slice: int32 [n_profiles][n_traj][n_wp]; d_f: float32
+ * [n_profiles][n_traj], overwritten.  d_gf: float32 [n_profiles][n_traj] or
+ * null (values only).  With d_gf, d_gwp [n_profiles][n_traj][n_wp][3] is
+ * required and overwritten, and the nullable d_gground, d_gceil
+ * [N][ny][nx] and d_gz [n_points] receive sums over all profiles
+ * (zero-filled first unless PCT_ACCUMULATE); d_gz needs d_arg_ground and
+ * d_arg_ceil.  flags: PCT_ACCUMULATE, PCT_DESCRIPTORS_RESIDENT (the profile
+ * table is already in the workspace from a call with the same profiles). */
+pct_status pct_trajectory_cost_multi(const float* d_ground, const float* d_ceil, const int32_t* d_arg_ground,
+                                     const int32_t* d_arg_ceil, const pct_grid* grid, const pct_extent* extent,
+                                     const pct_robot* h_robots, int32_t n_profiles, float w_z, const float* d_wp,
+                                     const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
+                                     float* d_f, float* d_gwp, float* d_gground, float* d_gceil, int64_t n_points,
+                                     float* d_gz, int32_t flags, void* d_ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -16,38 +16,16 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpct.so")
 
-PCT_OK, PCT_ERR_ARG, PCT_ERR_WORKSPACE, PCT_ERR_CAPACITY, PCT_ERR_DEVICE = 0, -1, -2, -3, -4
-PCT_MAX_SLICES = 1024
-PCT_ACCUMULATE = 1
+from .abi import (PCT_ACCUMULATE, PCT_DESCRIPTORS_RESIDENT, PCT_ERR_ARG, PCT_ERR_CAPACITY,  # noqa: F401
+                  PCT_ERR_DEVICE, PCT_ERR_WORKSPACE, PCT_MAX_SLICES, PCT_OK, _ROBOT_FIELDS, pct_extent, pct_grid,
+                  pct_item, pct_robot)
+from . import abi as _abi
 
 
 class PctError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__(f"{fn} failed (status {status}): {msg}")
         self.status = status
-
-
-class pct_grid(C.Structure):
-    _fields_ = [("x0", C.c_float), ("y0", C.c_float), ("res", C.c_float),
-                ("nx", C.c_int32), ("ny", C.c_int32), ("slice_dz", C.c_float)]
-
-
-class pct_extent(C.Structure):
-    _fields_ = [("z_min", C.c_float), ("z_max", C.c_float), ("n_slices", C.c_int32),
-                ("reserved", C.c_int32), ("n_used", C.c_int64), ("n_dropped", C.c_int64)]
-
-
-_ROBOT_FIELDS = ("d_min", "d_ref", "theta_b", "theta_s", "theta_p", "c_barrier", "alpha_d",
-                 "alpha_b", "alpha_s", "d_inf", "d_sm")
-
-
-class pct_robot(C.Structure):
-    _fields_ = [(n, C.c_float) for n in _ROBOT_FIELDS] + [("patch_radius", C.c_int32)]
-
-    def as_dict(self):
-        d = {n: float(getattr(self, n)) for n in _ROBOT_FIELDS}
-        d["patch_radius"] = int(self.patch_radius)
-        return d
 
 
 _lib = None
@@ -61,36 +39,8 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libpct.so not found at {LIB_PATH}; build it with "
                           "`python -m paper_2403_07631_amd.build`")
-    L = C.CDLL(LIB_PATH)
-    vp, sz, i64, i32, f32 = C.c_void_p, C.c_size_t, C.c_int64, C.c_int32, C.c_float
-    G, E, Rb = C.POINTER(pct_grid), C.POINTER(pct_extent), C.POINTER(pct_robot)
-    sig = {
-        "pct_abi_version": ([], i32),
-        "pct_last_error": ([], C.c_char_p),
-        "pct_robot_from_physical": ([f32, f32, f32, f32, f32, f32, f32, Rb], i32),
-        "pct_validate_grid": ([G], i32),
-        "pct_validate_robot": ([Rb, f32], i32),
-        "pct_kernel_radius": ([Rb, f32, C.POINTER(i32)], i32),
-        "pct_plane_heights": ([E, f32, vp, i32], i32),
-        "pct_extent_workspace_bytes": ([i64], sz),
-        "pct_tomogram_extent": ([vp, i64, G, E, vp, sz, vp], i32),
-        "pct_build_workspace_bytes": ([i64, G, E], sz),
-        "pct_build_tomogram": ([vp, i64, G, E, vp, vp, vp, vp, vp, sz, vp], i32),
-        "pct_eval_workspace_bytes": ([G, E, i32], sz),
-        "pct_eval_traversability": ([vp, vp, G, E, Rb, i32, vp, vp, vp, sz, vp], i32),
-        "pct_sample_cost_fwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp], i32),
-        "pct_sample_cost_bwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp, vp, vp, i32, vp], i32),
-        "pct_eval_traversability_bwd": ([vp, vp, G, E, Rb, vp, vp, vp, i32, vp], i32),
-        "pct_route_grad_to_points": ([vp, vp, vp, vp, G, E, i64, vp, i32, vp], i32),
-        "pct_trajectory_cost_bwd": ([vp, vp, vp, vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, i64, vp, vp, i32,
-                                     vp], i32),
-    }
-    for name, (args, res) in sig.items():
-        f = getattr(L, name)
-        f.argtypes = args
-        f.restype = res
-    _lib = L
-    return L
+    _lib = _abi.load(LIB_PATH)
+    return _lib
 
 
 def declared_symbols():
@@ -312,6 +262,48 @@ def pct_trajectory_cost_bwd(ground, ceil, cost, arg_ground, arg_ceil, grid, exte
     return gwp, gz
 
 
+def pct_trajectory_cost_multi(ground, ceil, arg_ground, arg_ceil, grid, extent, robots, w_z, wp, slices, gf=None,
+                              n_points=0, grids=False, flags=0, workspace=None, out=None):
+    """Several robot profiles on one map in one launch, c^T evaluated only at
+    the sampled corners.  wp [P, T, W, 3], slices [P, T, W], gf [P, T] or
+    None.  Returns (f [P, T], gwp [P, T, W, 3], gground, gceil, gz); the
+    gradients are None without gf, the grids None unless ``grids``, gz None
+    unless n_points > 0.  ``out`` passes preallocated (f, gwp, gground,
+    gceil, gz) and ``workspace`` a preallocated workspace (for graphs)."""
+    if isinstance(robots, (pct_robot, dict)):
+        robots = [robots]
+    rs = (pct_robot * len(robots))(*[robot_struct(r) for r in robots])
+    Pn = len(robots)
+    if not (wp.is_cuda and wp.dtype == torch.float32 and wp.dim() == 4 and wp.shape[0] == Pn and wp.shape[3] == 3):
+        raise ValueError("waypoints must be a CUDA float32 tensor [P, T, W, 3]")
+    if not (slices.is_cuda and slices.dtype == torch.int32 and tuple(slices.shape) == tuple(wp.shape[:3])):
+        raise ValueError("slice ids must be a CUDA int32 tensor [P, T, W]")
+    wp, slices = wp.contiguous(), slices.contiguous()
+    T, W = int(wp.shape[1]), int(wp.shape[2])
+    g = grid_struct(grid)
+    dev = wp.device
+    if gf is not None:
+        gf = gf.contiguous()
+        if tuple(gf.shape) != (Pn, T):
+            raise ValueError("gf must be [P, T]")
+    if out is None:
+        f = torch.empty((Pn, T), dtype=torch.float32, device=dev)
+        gwp = torch.empty_like(wp) if gf is not None else None
+        gground = torch.empty_like(ground) if (gf is not None and grids) else None
+        gceil = torch.empty_like(ceil) if (gf is not None and grids) else None
+        gz = torch.empty(n_points, dtype=torch.float32, device=dev) if (gf is not None and n_points > 0) else None
+    else:
+        f, gwp, gground, gceil, gz = out
+    need = lib().pct_trajectory_multi_workspace_bytes(Pn)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    _check("pct_trajectory_cost_multi",
+           lib().pct_trajectory_cost_multi(_ptr(ground), _ptr(ceil), _ptr(arg_ground), _ptr(arg_ceil), C.byref(g),
+                                           C.byref(extent), rs, Pn, float(w_z), _ptr(wp), _ptr(slices), T, W,
+                                           _ptr(gf), _ptr(f), _ptr(gwp), _ptr(gground), _ptr(gceil), int(n_points),
+                                           _ptr(gz), int(flags), _ptr(ws), ws.numel(), _stream(dev)))
+    return f, gwp, gground, gceil, gz
+
+
 # --------------------------------------------------------------------- autograd
 
 class BuildTomogram(torch.autograd.Function):
@@ -374,3 +366,83 @@ class TrajectoryCost(torch.autograd.Function):
         gwp, gcost, gground = pct_sample_cost_bwd(cost.detach().contiguous(), ground.detach().contiguous(), ctx.grid,
                                                   ctx.extent, ctx.robot, ctx.w_z, wp.detach(), slices, gf)
         return gcost, gground, gwp, None, None, None, None, None
+
+
+# --------------------------------------------------------------------- batches
+
+class Batch:
+    """A batch of submaps sharing one point array: item table, packed sizes
+    and a workspace sized for the batched calls."""
+
+    def __init__(self, xyz, specs, n_robots=1, with_ids=False):
+        self.xyz = _points(xyz)
+        self.items = (pct_item * len(specs))()
+        for it, sp in zip(self.items, specs):
+            it.xyz_offset, it.n_points = int(sp["xyz_offset"]), int(sp["n_points"])
+            it.grid = grid_struct(sp["grid"])
+        self.n = len(specs)
+        self.n_robots, self.with_ids = n_robots, with_ids
+        self.ws = None
+        self._size_workspace()
+        self.total_cells = 0
+        self.total_slices = 0
+
+    def _size_workspace(self):
+        nb = lib().pct_batch_workspace_bytes(self.items, self.n, self.n_robots, int(self.with_ids))
+        if nb == 0:
+            raise PctError("pct_batch_workspace_bytes", PCT_ERR_ARG, lib().pct_last_error().decode())
+        if self.ws is None or self.ws.numel() < nb:
+            self.ws = _workspace(nb, self.xyz.device)
+
+    def item_view(self, flat, i):
+        """Item i's [N, ny, nx] view of a packed grid output."""
+        it = self.items[i]
+        n = it.extent.n_slices * it.grid.nx * it.grid.ny
+        return flat[it.out_offset:it.out_offset + n].view(it.extent.n_slices, it.grid.ny, it.grid.nx)
+
+
+def pct_tomogram_extent_batched(batch: Batch):
+    tc, ts = C.c_int64(), C.c_int64()
+    _check("pct_tomogram_extent_batched",
+           lib().pct_tomogram_extent_batched(_ptr(batch.xyz), batch.xyz.shape[0], batch.items, batch.n, C.byref(tc),
+                                             C.byref(ts), _ptr(batch.ws), batch.ws.numel(),
+                                             _stream(batch.xyz.device)))
+    batch.total_cells, batch.total_slices = int(tc.value), int(ts.value)
+    batch._size_workspace()     # the evaluation scratch depends on the slice counts
+    return batch
+
+
+def pct_build_tomogram_batched(batch: Batch, with_ids=False, flags=0, out=None):
+    """Packed (ground, ceil, arg_ground, arg_ceil) of every item."""
+    dev = batch.xyz.device
+    if out is None:
+        ground = torch.empty(max(1, batch.total_cells), dtype=torch.float32, device=dev)
+        ceil = torch.empty_like(ground)
+        ag = torch.empty(max(1, batch.total_cells), dtype=torch.int32, device=dev) if with_ids else None
+        ac = torch.empty_like(ag) if with_ids else None
+    else:
+        ground, ceil, ag, ac = out
+    _check("pct_build_tomogram_batched",
+           lib().pct_build_tomogram_batched(_ptr(batch.xyz), batch.xyz.shape[0], batch.items, batch.n, _ptr(ground),
+                                            _ptr(ceil), _ptr(ag), _ptr(ac), flags, _ptr(batch.ws),
+                                            batch.ws.numel(), _stream(dev)))
+    return ground, ceil, ag, ac
+
+
+def pct_eval_traversability_batched(batch: Batch, ground, ceil, robots, keep=True, flags=0, out=None):
+    """Packed (cost [R, total_cells], keep [R, total_slices]) of every
+    (item, robot) pair."""
+    if isinstance(robots, (pct_robot, dict)):
+        robots = [robots]
+    rs = (pct_robot * len(robots))(*[robot_struct(r) for r in robots])
+    dev = ground.device
+    if out is None:
+        cost = torch.empty((len(robots), max(1, batch.total_cells)), dtype=torch.float32, device=dev)
+        kp = torch.empty((len(robots), max(1, batch.total_slices)), dtype=torch.uint8, device=dev) if keep else None
+    else:
+        cost, kp = out
+    _check("pct_eval_traversability_batched",
+           lib().pct_eval_traversability_batched(_ptr(ground), _ptr(ceil), batch.items, batch.n, rs, len(robots),
+                                                 _ptr(cost), _ptr(kp), flags, _ptr(batch.ws), batch.ws.numel(),
+                                                 _stream(dev)))
+    return cost, kp

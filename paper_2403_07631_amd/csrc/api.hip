@@ -573,4 +573,60 @@ pct_status pct_eval_traversability_batched(const float* d_ground, const float* d
                                !(flags & PCT_DESCRIPTORS_RESIDENT), (hipStream_t)stream);
 }
 
+size_t pct_trajectory_multi_workspace_bytes(int32_t n_profiles) {
+    if (n_profiles < 1) return 0;
+    return align_up(sizeof(EvalParams) * (size_t)n_profiles);
+}
+
+pct_status pct_trajectory_cost_multi(const float* d_ground, const float* d_ceil, const int32_t* d_arg_ground,
+                                     const int32_t* d_arg_ceil, const pct_grid* grid, const pct_extent* extent,
+                                     const pct_robot* h_robots, int32_t n_profiles, float w_z, const float* d_wp,
+                                     const int32_t* d_wp_slice, int32_t n_traj, int32_t n_wp, const float* d_gf,
+                                     float* d_f, float* d_gwp, float* d_gground, float* d_gceil, int64_t n_points,
+                                     float* d_gz, int32_t flags, void* d_ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (n_profiles < 1 || !h_robots) return fail(PCT_ERR_ARG, "at least one profile is required");
+    for (int i = 0; i < n_profiles; ++i) {
+        pct_status st = check_sampling(grid, extent, &h_robots[i], n_traj, n_wp, d_wp, d_wp_slice);
+        if (st != PCT_OK) return st;
+    }
+    if ((long long)n_profiles * n_traj * n_wp > (long long)INT32_MAX) return fail(PCT_ERR_CAPACITY, "too many waypoints");
+    if (!isfinite(w_z)) return fail(PCT_ERR_ARG, "w_z must be finite");
+    if (n_points < 0) return fail(PCT_ERR_ARG, "n_points must be >= 0");
+    if ((long long)n_traj > 0 && !d_f) return fail(PCT_ERR_ARG, "d_f is null");
+    if (d_gf && (long long)n_traj * n_wp > 0 && !d_gwp) return fail(PCT_ERR_ARG, "d_gwp is required with d_gf");
+    if (d_gf && d_gz && n_points > 0 && (!d_arg_ground || !d_arg_ceil))
+        return fail(PCT_ERR_ARG, "d_gz needs d_arg_ground and d_arg_ceil");
+    const int N = extent->n_slices;
+    if (N > 0 && (!d_ground || !d_ceil)) return fail(PCT_ERR_ARG, "grid pointers are null");
+    const size_t need = pct_trajectory_multi_workspace_bytes(n_profiles);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, need);
+    std::vector<EvalParams> ps(n_profiles);
+    for (int i = 0; i < n_profiles; ++i) {
+        pct_status st = make_eval_params(h_robots[i], *grid, std::max(N, 1), &ps[i]);
+        if (st != PCT_OK) return st;
+        ps[i].N = N;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (d_gf && !(flags & PCT_ACCUMULATE)) {
+        const long long cells = (long long)N * grid->nx * grid->ny;
+        pct_status st = launch_zero(d_gground, cells, s);
+        if (st == PCT_OK) st = launch_zero(d_gceil, cells, s);
+        if (st == PCT_OK) st = launch_zero(d_gz, d_gz ? n_points : 0, s);
+        if (st != PCT_OK) return st;
+    }
+    EvalParams* d_ps = (EvalParams*)d_ws;
+    if (!(flags & PCT_DESCRIPTORS_RESIDENT)) {
+        // ps is released on return: wait until the copy has read it
+        PCT_HIP(hipMemcpyAsync(d_ps, ps.data(), sizeof(EvalParams) * n_profiles, hipMemcpyHostToDevice, s));
+        PCT_HIP(hipStreamSynchronize(s));
+    }
+    if ((long long)n_traj * n_wp == 0) {
+        if (n_traj > 0) return launch_zero(d_f, (long long)n_profiles * n_traj, s);
+        return PCT_OK;
+    }
+    return launch_traj_value_grad(d_ground, d_ceil, d_arg_ground, d_arg_ceil, *grid, N, d_ps, n_profiles, w_z, d_wp,
+                                  d_wp_slice, n_traj, n_wp, d_gf, d_f, d_gwp, d_gground, d_gceil, d_gz, n_points, s);
+}
+
 }  // extern "C"

@@ -835,7 +835,10 @@ pct_status launch_extent_batched(const float* xyz, const BuildItemDev* h_items, 
     unsigned long long* pused = (unsigned long long*)p;
     p += align_up(sizeof(unsigned long long) * (size_t)nch);
     ExtentDev* d_out = (ExtentDev*)p;
-    if (upload) PCT_HIP(hipMemcpyAsync(d_items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
+    if (upload) {
+        PCT_HIP(hipMemcpyAsync(d_items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
+        PCT_HIP(hipStreamSynchronize(s));   // the host table is temporary
+    }
     hipLaunchKernelGGL(k_bextent, dim3((unsigned)nch), dim3(kBlock), 0, s, xyz, d_items, n_items, pmin, pmax, pused);
     PCT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_bextent_final, dim3(n_items), dim3(kBlock), 0, s, d_items, n_items, (int)nch, pmin, pmax, pused,
@@ -857,7 +860,12 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
     const bool ids = ag != nullptr;
     BatchWs w = carve_batch_ws(ws, h_items, n_items, ids);
     if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", ws_bytes, w.bytes);
-    if (upload) PCT_HIP(hipMemcpyAsync(w.items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
+    if (upload) {
+        // the table lives in pageable host memory that the caller releases
+        // on return: wait until the copy has read it
+        PCT_HIP(hipMemcpyAsync(w.items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
+        PCT_HIP(hipStreamSynchronize(s));
+    }
     int max_tiles_lds = 0;
     size_t max_reduce_lds = 0;
     for (int i = 0; i < n_items; ++i) {

@@ -661,7 +661,11 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
     if (!ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "batch eval workspace too small: %zu < %zu", ws_bytes, need);
     EvalJob* d_jobs = (EvalJob*)ws;
     char* scratch = (char*)ws + align_up(sizeof(EvalJob) * n_jobs);
-    if (upload) PCT_HIP(hipMemcpyAsync(d_jobs, jp.jobs.data(), sizeof(EvalJob) * n_jobs, hipMemcpyHostToDevice, s));
+    if (upload) {
+        // jp.jobs is released on return: wait until the copy has read it
+        PCT_HIP(hipMemcpyAsync(d_jobs, jp.jobs.data(), sizeof(EvalJob) * n_jobs, hipMemcpyHostToDevice, s));
+        PCT_HIP(hipStreamSynchronize(s));
+    }
     if (jp.strip) {
         switch (jp.R) {
 #define PCT_J(r) case r: st = launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s); break;

@@ -121,6 +121,68 @@ __device__ __forceinline__ void add_ceil(const Sink& s, long long i, float v) {
     }
 }
 
+// c^T of cell (x, y) of one slice, evaluated on demand: the maximum over
+// the Eq. (6) window of K * c^init (first maximum in row-major window
+// order), with the maximising cell and its c^init details.  The same FP32
+// products and maxima as the full-map kernels, so the same value.
+struct WinMax {
+    float v, k;
+    int qx, qy;
+    Cinit q;
+};
+
+__device__ WinMax window_max(const float* __restrict__ gk, const float* __restrict__ ck, int x, int y,
+                             const EvalParams& p) {
+    WinMax o{};
+    o.v = -INFINITY;
+    const int nx = p.nx, ny = p.ny, R = p.R;
+    for (int n = -R; n <= R; ++n) {
+        const int qy = y + n;
+        if (qy < 0 || qy >= ny) continue;
+        for (int m = -R; m <= R; ++m) {
+            const int qx = x + m;
+            const float kw = p.K[abs(m)][abs(n)];
+            if (kw <= 0.0f || qx < 0 || qx >= nx) continue;
+            const Cinit c = cinit_at(gk, ck, qx, qy, p);
+            const float v = kw * c.ci;
+            if (v > o.v) {
+                o.v = v;
+                o.k = kw;
+                o.qx = qx;
+                o.qy = qy;
+                o.q = c;
+            }
+        }
+    }
+    return o;
+}
+
+// Eq. (1)-(5) adjoint at the maximising cell of a window, for gradient gq
+// of its c^init.
+__device__ void cinit_adjoint(const Cinit& q, long long iq, int nx, float gq, const EvalParams& p, const Sink& s) {
+    if (q.branch == 0 || !q.pass) return;
+    if (q.ipos) {
+        add_ground(s, iq, p.alpha_d * gq);
+        add_ceil(s, iq, -p.alpha_d * gq);
+    }
+    float ddx = 0.0f, ddy = 0.0f;
+    if (q.branch == 2) {
+        ddx = 2.0f * p.As * q.dx * gq;
+        ddy = 2.0f * p.As * q.dy * gq;
+    } else if (q.branch == 3) {
+        if (fabsf(q.dx) >= fabsf(q.dy)) ddx = 2.0f * p.Ab * q.dx * gq;
+        else ddy = 2.0f * p.Ab * q.dy * gq;
+    }
+    if (ddx != 0.0f) {
+        add_ground(s, iq + 1, ddx);
+        add_ground(s, iq - 1, -ddx);
+    }
+    if (ddy != 0.0f) {
+        add_ground(s, iq + nx, ddy);
+        add_ground(s, iq - nx, -ddy);
+    }
+}
+
 // dL/dc^T(k, x, y) = gc: inflation argmax, then the Eq. (1)-(5) adjoint.
 __device__ void eval_adjoint_cell(const float* __restrict__ ground, const float* __restrict__ ceil, int k, int x,
                                   int y, float gc, const EvalParams& p, const Sink& s) {
@@ -379,6 +441,88 @@ __global__ __launch_bounds__(kBlock) void k_zero(float* __restrict__ p, long lon
 
 int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + kBlock - 1) / kBlock, 1 << 16)); }
 
+// Value and gradient for many robot profiles in one launch, each profile
+// with its own trajectories, with c^T evaluated on demand at the bilinear
+// corners (no cost maps).  One wavefront per (profile, trajectory), lanes
+// over its waypoints; per waypoint the value and the waypoint gradient are
+// the same FP32 sequences as k_sample_fwd / k_sample_bwd on a materialised
+// map, and the maximising taps found for the value feed the traversability
+// adjoint directly.
+__global__ __launch_bounds__(kBlock) void k_traj_value_grad(const float* __restrict__ ground,
+                                                            const float* __restrict__ ceil,
+                                                            const EvalParams* __restrict__ robots, SampleArgs a,
+                                                            int n_profiles, const float* __restrict__ wp,
+                                                            const int* __restrict__ slice,
+                                                            const float* __restrict__ gf, float* __restrict__ f,
+                                                            float* __restrict__ gwp, Sink s) {
+    const long long wave = (long long)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    if (wave >= (long long)n_profiles * a.T) return;
+    const int prof = __builtin_amdgcn_readfirstlane((int)(wave / a.T));
+    const EvalParams& p = robots[prof];
+    const int lane = threadIdx.x & 63;
+    const float g = gf ? gf[wave] : 0.0f;
+    float acc = 0.0f;
+    for (int w = lane; w < a.W; w += 64) {
+        const long long i = wave * a.W + w;
+        const float x = wp[3 * i], y = wp[3 * i + 1], z = wp[3 * i + 2];
+        const int k = slice[i];
+        const Bil b = bilinear(ground, a, x, y, z, k);
+        float gx = 0.0f, gy = 0.0f, gzw = 0.0f;
+        if (b.ok) {
+            const long long base = (long long)k * a.plane;
+            const float* gk = ground + base;
+            const float* ck = ceil + base;
+            const long long cs[4] = {b.c00, b.c10, b.c01, b.c11};
+            WinMax wm[4];
+            for (int c = 0; c < 4; ++c) {
+                const long long local = cs[c] - base;
+                wm[c] = window_max(gk, ck, (int)(local % a.nx), (int)(local / a.nx), p);
+            }
+            const float w00 = (1.0f - b.fu) * (1.0f - b.fv), w10 = b.fu * (1.0f - b.fv);
+            const float w01 = (1.0f - b.fu) * b.fv, w11 = b.fu * b.fv;
+            const float ws[4] = {w00, w10, w01, w11};
+            acc += w00 * wm[0].v + w10 * wm[1].v + w01 * wm[2].v + w11 * wm[3].v;
+            float G00 = 0.0f, G10 = 0.0f, G01 = 0.0f, G11 = 0.0f, G = 0.0f;
+            if (b.hterm) {
+                G00 = ground[b.c00];
+                G10 = ground[b.c10];
+                G01 = ground[b.c01];
+                G11 = ground[b.c11];
+                G = w00 * G00 + w10 * G10 + w01 * G01 + w11 * G11;
+                const float e = z - G - p.d_ref;
+                acc += a.w_z * e * e;
+            }
+            if (gf) {
+                const float dCdu = (1.0f - b.fv) * (wm[1].v - wm[0].v) + b.fv * (wm[3].v - wm[2].v);
+                const float dCdv = (1.0f - b.fu) * (wm[2].v - wm[0].v) + b.fu * (wm[3].v - wm[1].v);
+                gx = g * dCdu * b.du;
+                gy = g * dCdv * b.dv;
+                if (b.hterm) {
+                    const float de = 2.0f * a.w_z * (z - G - p.d_ref) * g;
+                    const float dGdu = (1.0f - b.fv) * (G10 - G00) + b.fv * (G11 - G01);
+                    const float dGdv = (1.0f - b.fu) * (G01 - G00) + b.fu * (G11 - G10);
+                    gx -= de * dGdu * b.du;
+                    gy -= de * dGdv * b.dv;
+                    gzw = de;
+                    for (int c = 0; c < 4; ++c) add_ground(s, cs[c], -de * ws[c]);
+                }
+                for (int c = 0; c < 4; ++c) {
+                    const float gc = g * ws[c];
+                    if (gc == 0.0f) continue;
+                    cinit_adjoint(wm[c].q, base + (long long)wm[c].qy * a.nx + wm[c].qx, a.nx, wm[c].k * gc, p, s);
+                }
+            }
+        }
+        if (gwp) {
+            gwp[3 * i] = gx;
+            gwp[3 * i + 1] = gy;
+            gwp[3 * i + 2] = gzw;
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane == 0) f[wave] = acc;
+}
+
 }  // namespace
 
 pct_status launch_zero(float* p, long long n, hipStream_t s) {
@@ -449,6 +593,30 @@ pct_status launch_route(const float* gG, const float* gC, const int* aG, const i
                         long long n_points, float* gz, hipStream_t s) {
     hipLaunchKernelGGL(k_route, dim3((unsigned)((plane + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, gG, gC, aG, aC,
                        plane, N, n_points, gz);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+pct_status launch_traj_value_grad(const float* ground, const float* ceil, const int* aG, const int* aC,
+                                  const pct_grid& g, int N, const EvalParams* d_robots, int n_profiles, float w_z,
+                                  const float* wp, const int* slice, int T, int W, const float* gf, float* f,
+                                  float* gwp, float* gground, float* gceil, float* gz, long long n_points,
+                                  hipStream_t s) {
+    const SampleArgs a = make_sample_args(g, N, 0.0f, w_z, T, W);
+    Sink sk{};
+    if (gf) {
+        sk.gG = gground;
+        sk.gC = gceil;
+        sk.aG = aG;
+        sk.aC = aC;
+        sk.gz = n_points > 0 ? gz : nullptr;
+        sk.n_points = n_points;
+    }
+    const long long waves = (long long)n_profiles * T;
+    if (waves == 0) return PCT_OK;
+    const unsigned blocks = (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
+    hipLaunchKernelGGL(k_traj_value_grad, dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_robots, a, n_profiles, wp,
+                       slice, gf, f, gf ? gwp : nullptr, sk);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }

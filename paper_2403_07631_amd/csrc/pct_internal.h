@@ -146,6 +146,11 @@ pct_status launch_sample_bwd(const float* cost, const float* ground, const float
                              const int* aC, float* gz, long long n_points, hipStream_t s);
 pct_status launch_eval_bwd(const float* ground, const float* ceil, const float* gcost, const EvalParams& p,
                            float* gground, float* gceil, hipStream_t s);
+pct_status launch_traj_value_grad(const float* ground, const float* ceil, const int* aG, const int* aC,
+                                  const pct_grid& g, int N, const EvalParams* d_robots, int n_profiles, float w_z,
+                                  const float* wp, const int* slice, int T, int W, const float* gf, float* f,
+                                  float* gwp, float* gground, float* gceil, float* gz, long long n_points,
+                                  hipStream_t s);
 pct_status launch_route(const float* gG, const float* gC, const int* aG, const int* aC, long long plane, int N,
                         long long n_points, float* gz, hipStream_t s);
 

@@ -1,0 +1,457 @@
+"""Runs libpct's kernels on the CPU (the AddressSanitizer build made by
+build_emu.py) on small seeded cases and compares the results with the oracle.
+
+Started by tests/test_emu.py in a child process with the sanitizer runtime
+preloaded:  python tests/emu/driver.py CASE [CASE ...]
+Each case prints one line when it passes; a failed comparison raises, and an
+out-of-bounds access ends the process with the sanitizer's report."""
+import ctypes as C
+import importlib.util
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, HERE)
+
+import build_emu  # noqa: E402
+import oracle  # noqa: E402
+import scenes  # noqa: E402
+
+_spec = importlib.util.spec_from_file_location("pct_abi", os.path.join(ROOT, "paper_2403_07631_amd", "abi.py"))
+abi = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(abi)
+
+L = abi.load(build_emu.LIB)
+L.emu_alloc.argtypes, L.emu_alloc.restype = [C.c_size_t], C.c_void_p
+L.emu_free.argtypes, L.emu_free.restype = [C.c_void_p], None
+TOL = 1e-5
+
+
+def say(msg):
+    print(f"[emu] {msg}", flush=True)
+
+
+class Buf:
+    """A "device" buffer: a heap block of exactly the requested size, filled
+    with a garbage pattern like fresh device memory."""
+
+    def __init__(self, nbytes, fill=0xCD):
+        self.nbytes = int(nbytes)
+        self.ptr = L.emu_alloc(max(1, self.nbytes))
+        C.memset(self.ptr, fill, self.nbytes)
+
+    @classmethod
+    def of(cls, arr):
+        arr = np.ascontiguousarray(arr)
+        b = cls(arr.nbytes)
+        C.memmove(b.ptr, arr.ctypes.data, arr.nbytes)
+        return b
+
+    def get(self, shape, dtype):
+        out = np.empty(shape, dtype)
+        assert out.nbytes <= self.nbytes
+        C.memmove(out.ctypes.data, self.ptr, out.nbytes)
+        return out
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            L.emu_free(self.ptr)
+            self.ptr = None
+
+
+def P(b):
+    return None if b is None else C.c_void_p(b.ptr)
+
+
+def check(fn, status):
+    if status != abi.PCT_OK:
+        raise RuntimeError(f"{fn}: status {status}: {L.pct_last_error().decode()}")
+
+
+def grid_s(g):
+    return abi.pct_grid(float(g["x0"]), float(g["y0"]), float(g["res"]), int(g["nx"]), int(g["ny"]),
+                        float(g["slice_dz"]))
+
+
+def robot_s(r):
+    return abi.pct_robot(*[float(r[n]) for n in abi._ROBOT_FIELDS], int(r.get("patch_radius", 1)))
+
+
+def robot(**kw):
+    r = oracle.robot_from_physical(scenes.ROBOT_CONFIG0, 0.1)
+    r.update(kw)
+    return r
+
+
+def bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+# ------------------------------------------------------------ entry points
+
+def extent(xyz_buf, n, grid):
+    g = grid_s(grid)
+    ws = Buf(L.pct_extent_workspace_bytes(n))
+    e = abi.pct_extent()
+    check("extent", L.pct_tomogram_extent(P(xyz_buf), n, C.byref(g), C.byref(e), P(ws), ws.nbytes, None))
+    return e
+
+
+def build(xyz_buf, n, grid, e, ids=True):
+    g = grid_s(grid)
+    N = e.n_slices
+    cells = N * grid["nx"] * grid["ny"]
+    G, Cc = Buf(4 * cells), Buf(4 * cells)
+    aG, aC = (Buf(4 * cells), Buf(4 * cells)) if ids else (None, None)
+    ws = Buf(L.pct_build_workspace_bytes(n, C.byref(g), C.byref(e)))
+    check("build", L.pct_build_tomogram(P(xyz_buf), n, C.byref(g), C.byref(e), P(G), P(Cc), P(aG), P(aC), P(ws),
+                                        ws.nbytes, None))
+    return G, Cc, aG, aC
+
+
+def evaluate(G, Cc, grid, e, robots, keep=True):
+    g = grid_s(grid)
+    rs = (abi.pct_robot * len(robots))(*[robot_s(r) for r in robots])
+    cells = e.n_slices * grid["nx"] * grid["ny"]
+    cost = Buf(4 * cells * len(robots))
+    kp = Buf(e.n_slices * len(robots)) if keep else None
+    ws = Buf(L.pct_eval_workspace_bytes(C.byref(g), C.byref(e), len(robots)))
+    check("eval", L.pct_eval_traversability(P(G), P(Cc), C.byref(g), C.byref(e), rs, len(robots), P(cost), P(kp),
+                                            P(ws), ws.nbytes, None))
+    return cost, kp
+
+
+def tomogram_case(pts, grid, ids=True, label=""):
+    pts = np.ascontiguousarray(pts, np.float32)
+    xb = Buf.of(pts)
+    e = extent(xb, len(pts), grid)
+    tm = oracle.tomogram(pts, grid)
+    assert e.n_used == tm["n_used"], (e.n_used, tm["n_used"])
+    assert e.n_slices == len(tm["h"])
+    if e.n_slices == 0:
+        return e, tm, None
+    G, Cc, aG, aC = build(xb, len(pts), grid, e, ids)
+    shape = (e.n_slices, grid["ny"], grid["nx"])
+    out = [G.get(shape, np.float32), Cc.get(shape, np.float32)]
+    np.testing.assert_array_equal(bits(out[0]), bits(tm["ground"]))
+    np.testing.assert_array_equal(bits(out[1]), bits(tm["ceil"]))
+    if ids:
+        np.testing.assert_array_equal(aG.get(shape, np.int32), tm["arg_ground"])
+        np.testing.assert_array_equal(aC.get(shape, np.int32), tm["arg_ceil"])
+    say(f"tomogram {label} n={len(pts)} grid={grid['nx']}x{grid['ny']} N={e.n_slices} ids={ids}: bit-exact")
+    return e, tm, (G, Cc)
+
+
+def eval_case(pts, grid, robots, label=""):
+    e, tm, dev = tomogram_case(pts, grid, ids=False, label=label)
+    cost, kp = evaluate(dev[0], dev[1], grid, e, robots)
+    shape = (len(robots), e.n_slices, grid["ny"], grid["nx"])
+    c = cost.get(shape, np.float32)
+    keep = kp.get((len(robots), e.n_slices), np.uint8)
+    for i, r in enumerate(robots):
+        lo, hi, _ = oracle.envelope(tm["ground"], tm["ceil"], grid["res"], r)
+        ci = c[i].astype(np.float64)
+        assert np.all(ci >= lo - TOL) and np.all(ci <= hi + TOL), f"robot {i}: cost outside the oracle envelope"
+        assert oracle.simplify_check(tm["ground"], lo, hi, r["c_barrier"], TOL, keep[i]) == -1
+    say(f"eval {label} robots={len(robots)}: within envelope, keep admissible")
+    return c, keep
+
+
+# ------------------------------------------------------------------ cases
+
+def case_tiny():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from conftest import load_golden
+    g = load_golden("tiny_tomogram.json")
+    tomogram_case(np.array(g["points"], np.float32), g["grid"], True, "tiny golden")
+
+
+def case_config0():
+    sc = scenes.config0_scene()
+    tomogram_case(sc.points, sc.grid, True, "config0")
+    eval_case(sc.points, sc.grid, [robot()], "config0")
+
+
+def case_edges():
+    rng = np.random.default_rng(5)
+    grid = dict(x0=-1.0, y0=2.0, res=0.125, nx=130, ny=19, slice_dz=0.25)
+    pts = np.array([[-5, 3, 1], [100, 3, 1], [0, np.nan, 1], [0, 3, np.inf]], np.float32)
+    e, _, _ = tomogram_case(pts, grid, True, "empty")
+    assert e.n_slices == 0
+    tomogram_case(np.array([[0.0, 2.5, -0.0]], np.float32), grid, True, "one point")
+    huge = np.column_stack([np.full(20_000, 0.3), np.full(20_000, 2.3),
+                            rng.choice([-0.0, 0.25, 0.5, 1.0, 1.75], 20_000)]).astype(np.float32)
+    spread = np.column_stack([rng.uniform(-1.0, 7.0, 9000), rng.uniform(2.0, 3.0, 9000),
+                              np.round(rng.uniform(-0.5, 2.0, 9000), 2)]).astype(np.float32)
+    junk = np.array([[np.nan, 2.5, 0], [0, 2.5, np.nan], [1e30, 2.5, 0], [0.0, 2.0 + 19 * 0.125, 0.5]], np.float32)
+    pts = np.concatenate([spread[:4000], huge, junk, spread[4000:]])
+    tomogram_case(pts, grid, True, "huge cell")
+    tomogram_case(pts, grid, False, "huge cell")
+
+
+def case_multirobot():
+    sc = scenes.multistorey_scene(33, 4.3, 3.1, 60_000, n_floors=2)
+    rs = [robot(), robot(d_min=0.7, theta_s=0.3), robot(d_inf=0.5, d_sm=0.7)]
+    eval_case(sc.points, sc.grid, rs, "multi-robot")
+
+
+def case_fallback_eval():
+    """Robots that take the tiled kernel (patch radius 2, radius > 8)."""
+    sc = scenes.multistorey_scene(32, 4.7, 3.9, 60_000, n_floors=2)
+    eval_case(sc.points, sc.grid, [robot(patch_radius=2, theta_p=0.45)], "patch radius 2")
+    eval_case(sc.points, sc.grid, [robot(d_inf=1.2, d_sm=0.5)], "radius > 8")
+
+
+def case_crop():
+    sc = scenes.multistorey_scene(21, 31.7, 23.3, 500_000, n_floors=6)
+    tomogram_case(sc.points, sc.grid, True, "crop")
+    tomogram_case(sc.points, sc.grid, False, "crop")
+
+
+def case_dense():
+    sc = scenes.multistorey_scene(22, 13.3, 9.1, 600_000, n_floors=3)
+    tomogram_case(sc.points, sc.grid, True, "dense")
+    tomogram_case(sc.points, sc.grid, False, "dense")
+
+
+def case_multirobot_large():
+    sc = scenes.multistorey_scene(33, 8.3, 6.1, 300_000, n_floors=2)
+    rs = [robot(), robot(d_min=0.7, theta_s=0.3), robot(d_inf=0.5, d_sm=0.7)]
+    eval_case(sc.points, sc.grid, rs, "multi-robot 83x61")
+
+
+def case_many_chunks():
+    """More than 64 binning workgroups (several groups of the column scan)."""
+    rng = np.random.default_rng(8)
+    grid = dict(x0=0.0, y0=0.0, res=0.1, nx=300, ny=40, slice_dz=0.3)
+    n = 1_300_000
+    pts = np.column_stack([rng.uniform(-0.5, 30.5, n), rng.uniform(-0.2, 4.2, n),
+                           rng.uniform(0.0, 3.0, n)]).astype(np.float32)
+    tomogram_case(pts, grid, True, "1.3M points")
+
+
+# ----------------------------------------------------------------- batches
+
+def make_batch(seed, n_items, side_hi=160, pts_hi=120_000, extra_empty=True):
+    items = scenes.submap_batch(seed, n_items, side_lo=20, side_hi=side_hi, pts_lo=2_000, pts_hi=pts_hi)
+    if extra_empty:
+        junk = scenes.Scene(np.array([[-50.0, -50.0, 1.0]], np.float32),
+                            dict(x0=0.0, y0=0.0, res=0.1, nx=30, ny=20, slice_dz=0.3))
+        none = scenes.Scene(np.zeros((0, 3), np.float32), dict(x0=0.0, y0=0.0, res=0.1, nx=7, ny=9, slice_dz=0.3))
+        items = items[:2] + [junk] + items[2:] + [none]
+    pts, specs, off = [], [], 0
+    for sc in items:
+        specs.append(dict(xyz_offset=off, n_points=len(sc.points), grid=sc.grid))
+        pts.append(sc.points)
+        off += len(sc.points)
+    return items, np.ascontiguousarray(np.concatenate(pts)), specs
+
+
+def batch_run(pts, specs, robots, ids):
+    n_items = len(specs)
+    items = (abi.pct_item * n_items)()
+    for it, sp in zip(items, specs):
+        it.xyz_offset, it.n_points = sp["xyz_offset"], sp["n_points"]
+        it.grid = grid_s(sp["grid"])
+    xb = Buf.of(pts)
+    ws = Buf(L.pct_batch_workspace_bytes(items, n_items, len(robots), int(ids)))
+    tc, ts = C.c_int64(), C.c_int64()
+    check("extent_batched", L.pct_tomogram_extent_batched(P(xb), len(pts), items, n_items, C.byref(tc), C.byref(ts),
+                                                          P(ws), ws.nbytes, None))
+    ws = Buf(L.pct_batch_workspace_bytes(items, n_items, len(robots), int(ids)))
+    cells, slices = max(1, tc.value), max(1, ts.value)
+    G, Cc = Buf(4 * cells), Buf(4 * cells)
+    aG, aC = (Buf(4 * cells), Buf(4 * cells)) if ids else (None, None)
+    check("build_batched", L.pct_build_tomogram_batched(P(xb), len(pts), items, n_items, P(G), P(Cc), P(aG), P(aC), 0,
+                                                        P(ws), ws.nbytes, None))
+    rs = (abi.pct_robot * len(robots))(*[robot_s(r) for r in robots])
+    cost = Buf(4 * cells * len(robots))
+    kp = Buf(slices * len(robots))
+    check("eval_batched", L.pct_eval_traversability_batched(P(G), P(Cc), items, n_items, rs, len(robots), P(cost),
+                                                            P(kp), 0, P(ws), ws.nbytes, None))
+    out = dict(G=G.get(cells, np.float32), C=Cc.get(cells, np.float32),
+               cost=cost.get((len(robots), cells), np.float32), keep=kp.get((len(robots), slices), np.uint8))
+    if ids:
+        out["aG"], out["aC"] = aG.get(cells, np.int32), aC.get(cells, np.int32)
+    return items, out
+
+
+def check_batch(items_sc, pts, specs, robots, ids, n_oracle=3, step=1):
+    items, out = batch_run(pts, specs, robots, ids)
+    checked = 0
+    for i in range(0, len(specs), step):
+        it, sp = items[i], specs[i]
+        sub = pts[sp["xyz_offset"]:sp["xyz_offset"] + sp["n_points"]]
+        tm = oracle.tomogram(sub, sp["grid"])
+        assert it.extent.n_used == tm["n_used"] and it.extent.n_slices == len(tm["h"]), i
+        N = it.extent.n_slices
+        if N == 0:
+            continue
+        nx, ny = sp["grid"]["nx"], sp["grid"]["ny"]
+        sl = slice(it.out_offset, it.out_offset + N * nx * ny)
+        np.testing.assert_array_equal(bits(out["G"][sl]), bits(tm["ground"].ravel()))
+        np.testing.assert_array_equal(bits(out["C"][sl]), bits(tm["ceil"].ravel()))
+        if ids:
+            off = sp["xyz_offset"]
+            np.testing.assert_array_equal(out["aG"][sl], np.where(tm["arg_ground"].ravel() >= 0,
+                                                                  tm["arg_ground"].ravel() + off, -1))
+            np.testing.assert_array_equal(out["aC"][sl], np.where(tm["arg_ceil"].ravel() >= 0,
+                                                                  tm["arg_ceil"].ravel() + off, -1))
+        if checked < n_oracle:
+            for r, rb in enumerate(robots):
+                lo, hi, _ = oracle.envelope(tm["ground"], tm["ceil"], sp["grid"]["res"], rb)
+                c = out["cost"][r, sl].reshape(N, ny, nx).astype(np.float64)
+                assert np.all(c >= lo - TOL) and np.all(c <= hi + TOL), (i, r)
+                kp = out["keep"][r, it.keep_offset:it.keep_offset + N]
+                assert oracle.simplify_check(tm["ground"], lo, hi, rb["c_barrier"], TOL, kp) == -1, (i, r)
+        checked += 1
+    say(f"batch of {len(specs)} items, {len(pts)} points, {len(robots)} robots, ids={ids}: "
+        f"{checked} items checked")
+
+
+def case_batch():
+    items, pts, specs = make_batch(61, 6, side_hi=60, pts_hi=30_000)
+    check_batch(items, pts, specs, [robot(), robot(d_min=0.7, theta_s=0.3)], True)
+
+
+def case_batch_mixed_radius():
+    """Robots with different inflation radii: per-job launches."""
+    items, pts, specs = make_batch(62, 3, side_hi=50, pts_hi=20_000, extra_empty=False)
+    check_batch(items, pts, specs, [robot(), robot(d_inf=0.5, d_sm=0.7)], False)
+
+
+def case_config1_build():
+    """The 20 M-point 2000 x 2000 map, tomogram with ids (slow: minutes)."""
+    sc = scenes.config1_scene()
+    tomogram_case(sc.points, sc.grid, True, "config1")
+
+
+# ------------------------------------------------------- trajectory costs
+
+def sample_fwd(cost, G, grid, e, rb, w_z, wpb, slb, T, W):
+    g = grid_s(grid)
+    r = robot_s(rb)
+    f = Buf(4 * T)
+    check("sample_fwd", L.pct_sample_cost_fwd(P(cost), P(G), C.byref(g), C.byref(e), C.byref(r), w_z, P(wpb), P(slb),
+                                              T, W, P(f), None))
+    return f.get(T, np.float32)
+
+
+def traj_bwd(G, Cc, cost, aG, aC, grid, e, rb, w_z, wpb, slb, T, W, gfb, n_points, gz, flags):
+    g = grid_s(grid)
+    r = robot_s(rb)
+    gwp = Buf(12 * T * W)
+    check("traj_bwd", L.pct_trajectory_cost_bwd(P(G), P(Cc), P(cost), P(aG), P(aC), C.byref(g), C.byref(e),
+                                                 C.byref(r), w_z, P(wpb), P(slb), T, W, P(gfb), n_points, P(gwp),
+                                                 P(gz), flags, None))
+    return gwp.get((T, W, 3), np.float32)
+
+
+def close(a, ref, mask=None, rel=1e-3):
+    a, ref = np.asarray(a, np.float64), np.asarray(ref, np.float64)
+    bad = np.abs(a - ref) > rel * np.maximum(1.0, np.abs(ref))
+    if mask is not None:
+        bad &= mask
+    assert not bad.any(), f"{bad.sum()} entries differ; worst {np.max(np.abs(a - ref)[bad])}"
+
+
+def case_traj_value_grad():
+    """Several profiles in one on-demand launch = the per-profile path
+    (cost map, sampling, fused adjoint) bit for bit for f and dL/dwp, and
+    the oracle within the gradient tolerance."""
+    w_z = 1.0
+    sc = scenes.multistorey_scene(51, 5.3, 4.1, 160_000, n_floors=2)
+    grid = sc.grid
+    pts = np.ascontiguousarray(sc.points, np.float32)
+    n = len(pts)
+    xb = Buf.of(pts)
+    e = extent(xb, n, grid)
+    G, Cc, aG, aC = build(xb, n, grid, e, True)
+    shape = (e.n_slices, grid["ny"], grid["nx"])
+    tm = oracle.tomogram(pts, grid)
+    profiles = [oracle.robot_from_physical(p, grid["res"]) for p in scenes.robot_profiles(4, 3)]
+    T, W = 6, 70
+    wps, sls = [], []
+    for i, r in enumerate(profiles):
+        cT = oracle.evaluate(tm["ground"], tm["ceil"], grid["res"], r)
+        lo, hi, _ = oracle.envelope(tm["ground"], tm["ceil"], grid["res"], r)
+        mask = (cT < r["c_barrier"]) & (lo == hi)
+        wp, sl = scenes.random_walks(20 + i, mask, tm["ground"], grid, T, W, r["d_ref"])
+        wps.append(wp)
+        sls.append(sl)
+    wp_all = np.ascontiguousarray(np.stack(wps), np.float32)
+    sl_all = np.ascontiguousarray(np.stack(sls), np.int32)
+    gf_all = np.ascontiguousarray(np.linspace(-1.0, 1.5, len(profiles) * T).reshape(len(profiles), T), np.float32)
+    # per-profile path: c^T map, sampling, fused adjoint accumulated over profiles
+    gz1 = Buf(4 * n)
+    f1, gwp1 = [], []
+    for i, r in enumerate(profiles):
+        cost, _ = evaluate(G, Cc, grid, e, [r], keep=False)
+        wpb, slb, gfb = Buf.of(wp_all[i]), Buf.of(sl_all[i]), Buf.of(gf_all[i])
+        f1.append(sample_fwd(cost, G, grid, e, r, w_z, wpb, slb, T, W))
+        gwp1.append(traj_bwd(G, Cc, cost, aG, aC, grid, e, r, w_z, wpb, slb, T, W, gfb, n, gz1,
+                             abi.PCT_ACCUMULATE if i else 0))
+    # one launch for all profiles
+    rs = (abi.pct_robot * len(profiles))(*[robot_s(r) for r in profiles])
+    ws = Buf(L.pct_trajectory_multi_workspace_bytes(len(profiles)))
+    wpb, slb, gfb = Buf.of(wp_all), Buf.of(sl_all), Buf.of(gf_all)
+    f2, gwp2, gz2 = Buf(4 * len(profiles) * T), Buf(12 * wp_all[..., 0].size), Buf(4 * n)
+    gG2, gC2 = Buf(4 * int(np.prod(shape))), Buf(4 * int(np.prod(shape)))
+    g = grid_s(grid)
+    check("multi", L.pct_trajectory_cost_multi(P(G), P(Cc), P(aG), P(aC), C.byref(g), C.byref(e), rs, len(profiles),
+                                               w_z, P(wpb), P(slb), T, W, P(gfb), P(f2), P(gwp2), P(gG2), P(gC2), n,
+                                               P(gz2), 0, P(ws), ws.nbytes, None))
+    f2 = f2.get((len(profiles), T), np.float32)
+    gwp2 = gwp2.get(wp_all.shape, np.float32)
+    np.testing.assert_array_equal(bits(f2), bits(np.stack(f1)))
+    np.testing.assert_array_equal(bits(gwp2), bits(np.stack(gwp1)))
+    a, b = gz2.get(n, np.float32), gz1.get(n, np.float32)
+    np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-5)
+    # values only: the same f, gradients untouched
+    f3 = Buf(4 * len(profiles) * T)
+    check("multi value", L.pct_trajectory_cost_multi(P(G), P(Cc), None, None, C.byref(g), C.byref(e), rs,
+                                                     len(profiles), w_z, P(wpb), P(slb), T, W, None, P(f3), None,
+                                                     None, None, 0, None, abi.PCT_DESCRIPTORS_RESIDENT, P(ws),
+                                                     ws.nbytes, None))
+    np.testing.assert_array_equal(bits(f3.get((len(profiles), T), np.float32)), bits(f2))
+    # the oracle: FP64 values and gradients summed over the profiles
+    rz = np.zeros(n)
+    rG_all = np.zeros(shape)
+    rC_all = np.zeros(shape)
+    uz = np.zeros(n, bool)
+    for i, r in enumerate(profiles):
+        cT = oracle.evaluate(tm["ground"], tm["ceil"], grid["res"], r)
+        fr = oracle.sample_fwd(cT, tm["ground"], grid, w_z, r["d_ref"], wp_all[i], sl_all[i])
+        assert np.all(np.abs(f2[i] - fr) <= 2e-5 * W + 1e-6 * np.abs(fr))
+        g64 = gf_all[i].astype(np.float64)
+        rgwp, rgc, rgg = oracle.sample_bwd(cT, tm["ground"], grid, w_z, r["d_ref"], wp_all[i], sl_all[i], g64)
+        close(gwp2[i], rgwp)
+        rG, rC, unc = oracle.eval_bwd(tm["ground"], tm["ceil"], grid["res"], r, rgc)
+        rG_all += rG + rgg
+        rC_all += rC
+        rz += oracle.route(rG + rgg, rC, tm["arg_ground"], tm["arg_ceil"], n)
+        for arr in (tm["arg_ground"], tm["arg_ceil"]):
+            m = (arr >= 0) & unc
+            uz[arr[m]] = True
+    assert np.count_nonzero(rz) > 20
+    close(gz2.get(n, np.float32), rz, ~uz)
+    close(gG2.get(shape, np.float32), rG_all)
+    close(gC2.get(shape, np.float32), rC_all)
+    say(f"multi-profile value+grad: {len(profiles)} profiles x {T} x {W}: equals the per-profile path, "
+        "oracle within tolerance")
+
+
+CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}
+
+if __name__ == "__main__":
+    oracle.lib()
+    names = sys.argv[1:] or list(CASES)
+    for name in names:
+        say(f"case {name}")
+        CASES[name]()
+    say("all passed")

@@ -1,0 +1,168 @@
+// CPU stand-in for the parts of the HIP runtime and device intrinsics that
+// libpct's kernel sources use, so that the same sources can be compiled by
+// the host compiler (with AddressSanitizer) and executed on the CPU.
+//
+// Execution model: the blocks of a launch run one after another on one OS
+// thread; the threads of a block run as cooperative fibers that switch only
+// at __syncthreads() and at cross-lane operations (__shfl, __shfl_xor,
+// __ballot, DPP moves, readfirstlane).  A cross-lane operation completes
+// when every live lane of the 64-lane wavefront has reached it; a barrier
+// completes when every live thread of the block has reached it.  A block
+// whose live threads are all waiting without either condition holding is
+// reported as a divergent synchronisation and the process aborts.
+//
+// Memory: device pointers are host pointers.  Dynamic LDS is a fresh heap
+// allocation of exactly the launch's byte count, static LDS arrays are
+// function-local statics (one block runs at a time), so AddressSanitizer
+// reports out-of-bounds accesses to either, and to global buffers.
+#pragma once
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <tuple>
+#include <type_traits>
+#include <utility>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+
+struct dim3 {
+    unsigned x, y, z;
+    constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct emu_uint3 {
+    unsigned x, y, z;
+};
+extern emu_uint3 threadIdx, blockIdx, blockDim, gridDim;
+
+typedef enum hipError_t {
+    hipSuccess = 0,
+    hipErrorInvalidValue = 1,
+    hipErrorInvalidConfiguration = 9,
+    hipErrorLaunchFailure = 719,
+} hipError_t;
+typedef struct emu_stream* hipStream_t;
+enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
+enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind kind, hipStream_t s);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipGetLastError();
+const char* hipGetErrorString(hipError_t e);
+hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute attr, int value);
+
+namespace emu {
+
+enum WaveOp { OP_SHFL = 1, OP_SHFL_XOR, OP_BALLOT, OP_DPP, OP_READFIRSTLANE };
+
+// Suspends the calling lane until every live lane of its wavefront has
+// reached a cross-lane operation of the same kind, then returns this lane's
+// result.  `arg` is the source lane / xor mask / DPP control, `old` the DPP
+// fallback value.
+uint64_t wave_op(int op, uint64_t value, int arg, uint64_t old);
+void syncthreads();
+void* dyn_smem();
+unsigned lane_id();
+
+bool begin_launch(const char* name, const void* fn, dim3 grid, dim3 block, size_t smem);
+void run_blocks(void (*thunk)(void*), void* ctx);
+
+template <class T>
+uint64_t to_bits(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lane values only");
+    uint64_t b = 0;
+    memcpy(&b, &v, sizeof(T));
+    return b;
+}
+template <class T>
+T from_bits(uint64_t b) {
+    T v;
+    memcpy(&v, &b, sizeof(T));
+    return v;
+}
+
+template <class F>
+void thunk(void* p) {
+    (*static_cast<F*>(p))();
+}
+
+template <class... P, class... A>
+void launch(const char* name, void (*k)(P...), dim3 grid, dim3 block, size_t smem, hipStream_t, A&&... a) {
+    static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+    if (!begin_launch(name, (const void*)k, grid, block, smem)) return;
+    std::tuple<std::decay_t<P>...> args(static_cast<std::decay_t<P>>(a)...);
+    auto body = [&]() { std::apply(k, args); };
+    run_blocks(&thunk<decltype(body)>, &body);
+}
+
+}  // namespace emu
+
+#define hipLaunchKernelGGL(k, grid, block, smem, stream, ...) \
+    ::emu::launch(#k, k, dim3(grid), dim3(block), (size_t)(smem), stream, ##__VA_ARGS__)
+
+#define __syncthreads() ::emu::syncthreads()
+
+template <class T>
+inline T __shfl(T v, int src, int width = 64) {
+    (void)width;
+    return emu::from_bits<T>(emu::wave_op(emu::OP_SHFL, emu::to_bits(v), src, 0));
+}
+template <class T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+    (void)width;
+    return emu::from_bits<T>(emu::wave_op(emu::OP_SHFL_XOR, emu::to_bits(v), mask, 0));
+}
+inline unsigned long long __ballot(int pred) { return emu::wave_op(emu::OP_BALLOT, pred ? 1u : 0u, 0, 0); }
+inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    if (row_mask != 0xf || bank_mask != 0xf || bound_ctrl) __builtin_trap();
+    return emu::from_bits<int>(emu::wave_op(emu::OP_DPP, emu::to_bits(src), ctrl, emu::to_bits(old)));
+}
+inline int emu_readfirstlane(int v) { return emu::from_bits<int>(emu::wave_op(emu::OP_READFIRSTLANE, emu::to_bits(v), 0, 0)); }
+#define __builtin_amdgcn_update_dpp emu_update_dpp
+#define __builtin_amdgcn_readfirstlane emu_readfirstlane
+
+// Fibers switch only at the operations above, so read-modify-write needs no
+// further protection.
+template <class T>
+inline T atomicAdd(T* p, T v) {
+    T o = *p;
+    *p = o + v;
+    return o;
+}
+template <class T>
+inline T atomicMax(T* p, T v) {
+    T o = *p;
+    *p = o > v ? o : v;
+    return o;
+}
+template <class T>
+inline T atomicMin(T* p, T v) {
+    T o = *p;
+    *p = o < v ? o : v;
+    return o;
+}
+template <class T>
+inline T atomicOr(T* p, T v) {
+    T o = *p;
+    *p = o | v;
+    return o;
+}
+
+template <class T, class U>
+inline typename std::common_type<T, U>::type min(T a, U b) {
+    typedef typename std::common_type<T, U>::type C;
+    return (C)a < (C)b ? (C)a : (C)b;
+}
+template <class T, class U>
+inline typename std::common_type<T, U>::type max(T a, U b) {
+    typedef typename std::common_type<T, U>::type C;
+    return (C)a > (C)b ? (C)a : (C)b;
+}

@@ -151,3 +151,34 @@ def test_workspace_sizes(P):
     assert 12 * 20_000_000 <= b <= 15 * 20_000_000   # records + per-workgroup tile counts
     assert L.pct_eval_workspace_bytes(C.byref(g), C.byref(e), 1) > 0
     assert L.pct_extent_workspace_bytes(1000) > 0
+
+
+def test_library_resolves_all_symbols_at_load(P):
+    """Loading with immediate binding catches an entry point that refers to
+    an undefined internal function."""
+    C.CDLL(P.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
+
+
+def test_item_struct_layout(P):
+    """pct_item as laid out by a C compiler on this ABI: 96 bytes, extent at 48."""
+    assert C.sizeof(P.pct_item) == 96
+    assert P.pct_item.extent.offset == 48 and P.pct_item.out_offset.offset == 80
+    assert C.sizeof(P.pct_extent) == 32 and C.sizeof(P.pct_grid) == 24 and C.sizeof(P.pct_robot) == 48
+
+
+def test_batch_rejects_before_launch(P):
+    L = P.lib()
+    items = (P.pct_item * 2)()
+    for it in items:
+        it.grid = P.pct_grid(0.0, 0.0, 0.1, 10, 10, 0.3)
+        it.n_points = 5
+    items[1].xyz_offset = 8
+    tc, ts = C.c_int64(), C.c_int64()
+    # item 1 reaches past the 10 points given
+    assert L.pct_tomogram_extent_batched(C.c_void_p(0x1000), 10, items, 2, C.byref(tc), C.byref(ts),
+                                         C.c_void_p(0x1000), 1 << 20, None) == P.PCT_ERR_ARG
+    items[1].grid.res = 0.0
+    items[1].xyz_offset = 5
+    assert L.pct_tomogram_extent_batched(C.c_void_p(0x1000), 10, items, 2, C.byref(tc), C.byref(ts),
+                                         C.c_void_p(0x1000), 1 << 20, None) == P.PCT_ERR_ARG
+    assert b"item 1" in L.pct_last_error()
