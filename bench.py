@@ -77,6 +77,101 @@ def cpu_baseline(sc, window_cells=400):
                        f"in {dt:.2f} s")
 
 
+def bench_profiles(P, torch, sc, xyz, dev, steps, warmup, n_profiles=64, n_walks=1024):
+    """Batched fwd+bwd against the plain path: n_profiles robot profiles on
+    the map, each followed by the trajectory-cost forward and backward of
+    the first n_walks of the 4096 x 256 random walks (values, waypoint
+    gradients, point-height gradients).  Plain: per profile the cost map,
+    the sampling forward and the fused backward (the same kernels, one
+    profile at a time).  Batched: one launch for all profiles with c^T
+    evaluated at the sampled corners only, replayed from a graph."""
+    import numpy as np
+
+    import scenes
+    g = sc.grid
+    ext = P.pct_tomogram_extent(xyz, g)
+    G, Cc, aG, aC = P.pct_build_tomogram(xyz, g, ext, with_ids=True)
+    n = xyz.shape[0]
+    Gh = G.cpu().numpy()
+    rb0 = P.robot_from_physical(sc.robot, g["res"])
+    log("random walks for the profile batch")
+    wp0, sl0 = scenes.random_walks(2, np.isfinite(Gh), Gh, g, 4096, 256, rb0.as_dict()["d_ref"])
+    del Gh
+    wp0, sl0 = wp0[:n_walks], sl0[:n_walks]
+    rbs = [P.robot_from_physical(p, g["res"]) for p in scenes.robot_profiles(4, n_profiles)]
+    wp = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(wp0, (n_profiles,) + wp0.shape))).to(dev)
+    sl = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(sl0, (n_profiles,) + sl0.shape))).to(dev)
+    gf = torch.ones((n_profiles, n_walks), device=dev)
+    f1 = torch.empty((n_profiles, n_walks), device=dev)
+    gwp1 = torch.empty_like(wp)
+    gz1 = torch.empty(n, device=dev)
+
+    def plain():
+        for i, rb in enumerate(rbs):
+            cost, _ = P.pct_eval_traversability(G, Cc, g, ext, [rb], keep=False)
+            cost = cost[0]
+            f1[i] = P.pct_sample_cost_fwd(cost, G, g, ext, rb, 1.0, wp[i], sl[i])
+            P.pct_trajectory_cost_bwd(G, Cc, cost, aG, aC, g, ext, rb, 1.0, wp[i], sl[i], gf[i], n, gwp=gwp1[i],
+                                      gz=gz1, flags=P.PCT_ACCUMULATE if i else 0)
+
+    f2 = torch.empty((n_profiles, n_walks), device=dev)
+    gwp2 = torch.empty_like(wp)
+    gz2 = torch.empty(n, device=dev)
+    ws = torch.empty(P.lib().pct_trajectory_multi_workspace_bytes(n_profiles), dtype=torch.uint8, device=dev)
+    out = (f2, gwp2, None, None, gz2)
+
+    def batched(flags=0):
+        P.pct_trajectory_cost_multi(G, Cc, aG, aC, g, ext, rbs, 1.0, wp, sl, gf, n_points=n, flags=flags,
+                                    workspace=ws, out=out)
+
+    s = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(s)
+        for _ in range(reps):
+            fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    log("profile batch: plain path")
+    for _ in range(max(1, warmup)):
+        plain()
+    ms_plain = timed(plain, steps)
+    log("profile batch: batched path, graph-captured")
+    batched()                                   # uploads the profile table
+    torch.cuda.synchronize()
+    cs = torch.cuda.Stream(device=dev)
+    cs.wait_stream(torch.cuda.current_stream(dev))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cs):
+        batched(P.PCT_DESCRIPTORS_RESIDENT)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=cs):
+            batched(P.PCT_DESCRIPTORS_RESIDENT)
+    torch.cuda.synchronize()
+    for _ in range(max(1, warmup)):
+        graph.replay()
+    ms_batched = timed(graph.replay, steps)
+    torch.cuda.synchronize()
+    same_f = bool(torch.equal(f1.view(torch.int32), f2.view(torch.int32)))
+    same_gwp = bool(torch.equal(gwp1.view(torch.int32), gwp2.view(torch.int32)))
+    dz = float((gz1 - gz2).abs().max().item())
+    zs = float(gz1.abs().max().item())
+    wps = n_profiles * n_walks * wp.shape[2]
+    return {"workload": f"{n_profiles} robot profiles (min interval 0.4-0.8 m, slope 20-40 deg, step 0.1-0.3 m) "
+                        f"on the 20M-point map, each with {n_walks} walks x {int(wp.shape[2])} waypoints, "
+                        "trajectory-cost forward + backward (waypoint and point-height gradients)",
+            "plain": "per profile: cost map, sampling forward, fused backward",
+            "batched": "one launch for all profiles, c^T evaluated at the sampled bilinear corners only, "
+                       "graph replay",
+            "plain_ms": ms_plain, "batched_ms": ms_batched, "ratio": ms_plain / ms_batched,
+            "waypoints_per_s": wps / (ms_batched * 1e-3),
+            "identical_f": same_f, "identical_gwp": same_gwp, "gz_max_abs_diff": dz, "gz_max_abs": zs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=2000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain profile measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
@@ -183,6 +279,9 @@ def main():
                      "traffic": traffic, "alg_bytes_per_launch": eval_bytes},
         "wall_s_timed": wall,
     }
+    if not args.no_batched:
+        del g, c, cost, keep
+        out["batched_vs_plain"] = bench_profiles(P, torch, sc, xyz, dev, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a window)")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_window)

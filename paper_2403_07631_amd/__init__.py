@@ -247,18 +247,19 @@ def pct_route_grad_to_points(gground, gceil, arg_ground, arg_ceil, grid, extent,
 
 
 def pct_trajectory_cost_bwd(ground, ceil, cost, arg_ground, arg_ceil, grid, extent, robot, w_z, wp, slices, gf,
-                            n_points):
-    """(gwp [T, W, 3], gz [n_points]) in one pass (no dense gradient grids)."""
+                            n_points, gwp=None, gz=None, flags=0):
+    """(gwp [T, W, 3], gz [n_points]) in one pass (no dense gradient grids).
+    gwp/gz may be passed in; with ``flags=PCT_ACCUMULATE`` gz is added to."""
     wp, slices = _wp(wp, slices)
     g, rb = grid_struct(grid), robot_struct(robot)
     T, W = slices.shape
-    gwp = torch.empty_like(wp)
-    gz = torch.empty(n_points, dtype=torch.float32, device=wp.device)
+    gwp = torch.empty_like(wp) if gwp is None else gwp
+    gz = torch.empty(n_points, dtype=torch.float32, device=wp.device) if gz is None else gz
     _check("pct_trajectory_cost_bwd",
            lib().pct_trajectory_cost_bwd(_ptr(ground), _ptr(ceil), _ptr(cost), _ptr(arg_ground), _ptr(arg_ceil),
                                          C.byref(g), C.byref(extent), C.byref(rb), float(w_z), _ptr(wp),
-                                         _ptr(slices), T, W, _ptr(gf.contiguous()), n_points, _ptr(gwp), _ptr(gz), 0,
-                                         _stream(wp.device)))
+                                         _ptr(slices), T, W, _ptr(gf.contiguous()), n_points, _ptr(gwp), _ptr(gz),
+                                         int(flags), _stream(wp.device)))
     return gwp, gz
 
 

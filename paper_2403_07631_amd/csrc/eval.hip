@@ -179,16 +179,24 @@ __device__ __forceinline__ float maxnn(float a, float b) {
 
 // One wavefront's strip: work index w of a map with parameters p and strip
 // geometry sg (ground/ceil/cost already point at the map's first slice).
+//
+// The rows a lane keeps live (4 ground rows, 3 flag rows, 2R+1 c^init rows,
+// kPrefetch raw rows of each input) sit in rings of S slots indexed by the
+// step number modulo S; the row loop is unrolled S times so that every slot
+// index is a compile-time constant and no row is ever moved between
+// registers.  Step t handles output row y = Y0 - 2 HX + t.
 template <int R>
 __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                 const EvalParams& p, float* __restrict__ cost, const StripGeom& sg,
                                                 int w) {
     constexpr int HX = R + 2;            // halo columns: inflation R, patch 1, stencil 1
     constexpr int OUTW = 64 - 2 * HX;
+    constexpr int S0 = 2 * R + 1 > 4 ? 2 * R + 1 : 4;
+    constexpr int S = S0 > kPrefetch ? S0 : kPrefetch;   // ring length
     const int sx = w % sg.n_sx;
-    const int t = w / sg.n_sx;
-    const int sy = t % sg.n_sy;
-    const int k = t / sg.n_sy;
+    const int t0 = w / sg.n_sx;
+    const int sy = t0 % sg.n_sy;
+    const int k = t0 / sg.n_sy;
     const int lane = threadIdx.x & 63;
     const int nx = p.nx, ny = p.ny;
     const int x = sx * OUTW - HX + lane;
@@ -200,98 +208,97 @@ __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground
     const float* ck = ceil + (long long)k * p.plane;
     float* ok = cost + (long long)k * p.plane;
 
-    // Loads use clamped addresses; the raw value of row r is fetched one
-    // step ahead and masked (outside the grid: no ground) when consumed, so
-    // the load latency overlaps a whole step and the loop has no branches.
+    // Loads use clamped addresses; the raw value of a row is fetched
+    // kPrefetch steps ahead and masked (outside the grid: no ground) when
+    // consumed, so the load latency overlaps several steps.
     auto addr = [&](int row) { return (unsigned)min(max(row, 0), ny - 1) * (unsigned)nx + xc; };
 
-    float gR[4];          // ground rows y+R-1 .. y+R+2
-    int fR[3];            // gentle flags rows y+R-1 .. y+R+1
-    float cR[2 * R + 1];  // c^init rows y-R .. y+R
+    float gS[S];   // ground row y+HX-j at slot (t-j) mod S ... (rows y+R-1 .. y+R+2 live)
+    int fS[S];     // gentle flags, row y+R+1 written at slot t mod S
+    float cS[S];   // c^init, row y+R written at slot t mod S
+    float gRaw[S], cRaw[S];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) gR[i] = -INFINITY;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) fR[i] = 0;
-#pragma unroll
-    for (int i = 0; i < 2 * R + 1; ++i) cR[i] = 0.0f;
-
-    // raw rows fetched kPrefetch steps ahead (memory-level parallelism)
-    int y = Y0 - 2 * HX;
-    float gRaw[kPrefetch], cRaw[kPrefetch];
+    for (int i = 0; i < S; ++i) {
+        gS[i] = -INFINITY;
+        fS[i] = 0;
+        cS[i] = 0.0f;
+    }
+    const int ys = Y0 - 2 * HX;   // row of step 0
 #pragma unroll
     for (int d = 0; d < kPrefetch; ++d) {
-        gRaw[d] = gk[addr(y + HX + d)];
-        cRaw[d] = ck[addr(y + R + d)];
+        gRaw[d % S] = gk[addr(ys + HX + d)];
+        cRaw[d % S] = ck[addr(ys + R + d)];
     }
-    for (; y < Y1; ++y) {
-        const int rg = y + HX, rc = y + R;
-        const float gIn = (xin & (rg >= 0) & (rg < ny)) ? gRaw[0] : -INFINITY;
-        const float cIn = cRaw[0];
-        const bool crow = xin & (rc >= 0) & (rc < ny);
+    const int n_steps = Y1 - ys;
+    for (int tb = 0; tb < n_steps; tb += S) {
 #pragma unroll
-        for (int d = 0; d + 1 < kPrefetch; ++d) {
-            gRaw[d] = gRaw[d + 1];
-            cRaw[d] = cRaw[d + 1];
-        }
-        gRaw[kPrefetch - 1] = gk[addr(rg + kPrefetch)];
-        cRaw[kPrefetch - 1] = ck[addr(rc + kPrefetch)];
+        for (int ph = 0; ph < S; ++ph) {
+            const int t = tb + ph;
+            if (t < n_steps) {
+                const int y = ys + t;
+                const int rg = y + HX, rc = y + R;
+                // step t consumes raw slot ph and refills it kPrefetch rows ahead
+                const float gIn = (xin & (rg >= 0) & (rg < ny)) ? gRaw[ph] : -INFINITY;
+                const float cIn = cRaw[ph];
+                const bool crow = xin & (rc >= 0) & (rc < ny);
+                gRaw[(ph + kPrefetch) % S] = gk[addr(rg + kPrefetch)];
+                cRaw[(ph + kPrefetch) % S] = ck[addr(rc + kPrefetch)];
+                // ground ring: row y+R+2 (newest) at slot ph, row y+R+2-j at slot ph-j
+                gS[ph] = gIn;
+                const float g3 = gS[ph], g2 = gS[(ph + S - 1) % S], g1 = gS[(ph + S - 2) % S],
+                            g0 = gS[(ph + S - 3) % S];   // rows y+R+2, y+R+1, y+R, y+R-1
 
-#pragma unroll
-        for (int i = 0; i < 3; ++i) gR[i] = gR[i + 1];
-        gR[3] = gIn;
+                // gentle flag of row y+R+1
+                {
+                    const float Gc = g2, Gd = g1, Gu = g3;
+                    const float Gl = from_prev(Gc), Gr = from_next(Gc);
+                    const bool ok5 = isfinite(Gc) & isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
+                    const float s2 = sumsq(Gr - Gl, Gu - Gd);
+                    fS[ph] = (ok5 & (s2 < p.Ts2)) ? 1 : 0;
+                }
+                const int f2 = fS[ph], f1 = fS[(ph + S - 1) % S], f0 = fS[(ph + S - 2) % S];  // rows y+R+1, y+R, y+R-1
 
-        // gentle flag of row y+R+1
-        {
-            const float Gc = gR[2], Gd = gR[1], Gu = gR[3];
-            const float Gl = from_prev(Gc), Gr = from_next(Gc);
-            const bool ok5 = isfinite(Gc) & isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
-            const float s2 = sumsq(Gr - Gl, Gu - Gd);
-            const int f = (ok5 & (s2 < p.Ts2)) ? 1 : 0;
-            fR[0] = fR[1];
-            fR[1] = fR[2];
-            fR[2] = f;
-        }
+                // c^init of row y+R, Eqs. (1)-(5), computed without branches
+                {
+                    const float G = g1, Gd = g0, Gu = g2;
+                    const float Gl = from_prev(G), Gr = from_next(G);
+                    const int colsum = f0 + f1 + f2;
+                    const int cnt = colsum + from_prev_i(colsum) + from_next_i(colsum) - f1;
+                    const float dI = cIn - G;
+                    const float cI = dI < p.d_min ? p.cB : fmaxf(0.0f, p.alpha_d * (p.d_ref - dI));
+                    const bool v4 = isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
+                    const float dx = Gr - Gl, dy = Gu - Gd;
+                    const float s2 = sumsq(dx, dy);
+                    const float c_gentle = p.As * s2;
+                    const float c_edge = p.Ab * maxnn(dx * dx, dy * dy);
+                    const float c_step = cnt > p.kp ? c_edge : p.cB;
+                    float cG = s2 < p.Ts2 ? c_gentle : c_step;
+                    const bool passable = v4 & !(maxnn(fabsf(dx), fabsf(dy)) > p.Tb);
+                    cG = passable ? cG : p.cB;
+                    float ci = isfinite(G) ? fminf(p.cB, cI + cG) : p.cB;
+                    cS[ph] = crow ? ci : 0.0f;
+                }
 
-        // c^init of row y+R, Eqs. (1)-(5), computed without branches
-        {
-            const float G = gR[1], Gd = gR[0], Gu = gR[2];
-            const float Gl = from_prev(G), Gr = from_next(G);
-            const int colsum = fR[0] + fR[1] + fR[2];
-            const int cnt = colsum + from_prev_i(colsum) + from_next_i(colsum) - fR[1];
-            const float dI = cIn - G;
-            const float cI = dI < p.d_min ? p.cB : fmaxf(0.0f, p.alpha_d * (p.d_ref - dI));
-            const bool v4 = isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
-            const float dx = Gr - Gl, dy = Gu - Gd;
-            const float s2 = sumsq(dx, dy);
-            const float c_gentle = p.As * s2;
-            const float c_edge = p.Ab * maxnn(dx * dx, dy * dy);
-            const float c_step = cnt > p.kp ? c_edge : p.cB;
-            float cG = s2 < p.Ts2 ? c_gentle : c_step;
-            const bool passable = v4 & !(maxnn(fabsf(dx), fabsf(dy)) > p.Tb);
-            cG = passable ? cG : p.cB;
-            float ci = isfinite(G) ? fminf(p.cB, cI + cG) : p.cB;
-            ci = crow ? ci : 0.0f;
+                // inflation of row y: c^init rows y-R .. y+R are slots ph-2R .. ph
+                // (column pass from registers, row pass across lanes; all
+                // operands are >= 0)
+                float P[R + 1];
+                P[0] = cS[(ph + S - R) % S];
 #pragma unroll
-            for (int i = 0; i < 2 * R; ++i) cR[i] = cR[i + 1];
-            cR[2 * R] = ci;
+                for (int jj = 1; jj <= R; ++jj)
+                    P[jj] = maxnn(cS[(ph + S - R - jj) % S], cS[(ph + S - R + jj) % S]);
+                float v = 0.0f;
+#pragma unroll
+                for (int a = 0; a <= R; ++a) {
+                    float h = 0.0f;
+#pragma unroll
+                    for (int jj = 0; jj <= R; ++jj) h = maxnn(h, p.K[a][jj] * P[jj]);
+                    if (a == 0) v = h;
+                    else v = maxnn(v, maxnn(__shfl(h, lane - a, 64), __shfl(h, lane + a, 64)));
+                }
+                if (y >= Y0 && xout) ok[(unsigned)y * (unsigned)nx + (unsigned)x] = v;
+            }
         }
-
-        // inflation of row y: column pass from the register rows, row pass
-        // across lanes (all operands are >= 0)
-        float P[R + 1];
-        P[0] = cR[R];
-#pragma unroll
-        for (int j = 1; j <= R; ++j) P[j] = maxnn(cR[R - j], cR[R + j]);
-        float v = 0.0f;
-#pragma unroll
-        for (int a = 0; a <= R; ++a) {
-            float h = 0.0f;
-#pragma unroll
-            for (int j = 0; j <= R; ++j) h = maxnn(h, p.K[a][j] * P[j]);
-            if (a == 0) v = h;
-            else v = maxnn(v, maxnn(__shfl(h, lane - a, 64), __shfl(h, lane + a, 64)));
-        }
-        if (y >= Y0 && xout) ok[(unsigned)y * (unsigned)nx + (unsigned)x] = v;
     }
 }
 
@@ -306,7 +313,7 @@ __device__ __forceinline__ int xcd_wave_index() {
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                        const EvalParams p, float* __restrict__ cost, const StripGeom sg) {
-    const int w = xcd_wave_index();
+    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_index());   // uniform: row logic stays scalar
     if (w >= sg.n_work) return;
     eval_strip_wave<R>(ground, ceil, p, cost, sg, w);
 }
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restr
                                                             const float* __restrict__ ceil,
                                                             const EvalJob* __restrict__ jobs, int n_jobs, int n_work,
                                                             float* __restrict__ cost) {
-    const int w = xcd_wave_index();
+    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_index());
     if (w >= n_work) return;
     const int j = __builtin_amdgcn_readfirstlane(find_job_work(jobs, n_jobs, w));
     const EvalJob& jb = jobs[j];

@@ -410,8 +410,9 @@ def case_traj_value_grad():
     gwp2 = gwp2.get(wp_all.shape, np.float32)
     np.testing.assert_array_equal(bits(f2), bits(np.stack(f1)))
     np.testing.assert_array_equal(bits(gwp2), bits(np.stack(gwp1)))
+    # float atomics add in a different order: a few ulps of the largest partial sums
     a, b = gz2.get(n, np.float32), gz1.get(n, np.float32)
-    np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(a, b, rtol=1e-5, atol=2e-5 * max(1.0, float(np.abs(b).max())))
     # values only: the same f, gradients untouched
     f3 = Buf(4 * len(profiles) * T)
     check("multi value", L.pct_trajectory_cost_multi(P(G), P(Cc), None, None, C.byref(g), C.byref(e), rs,
