@@ -488,13 +488,35 @@ pct_status make_items(const pct_item* h, int n_items, int64_t n_total, bool need
 
 }  // namespace
 
+// Batch workspace layout (one size query serves all three batched calls):
+//   [0, A)            the construction's item table (kept for PCT_DESCRIPTORS_RESIDENT)
+//   [A, F)            transient: the extent's table and partials, or the
+//                     construction's records and counters
+//   [end - E, end)    the evaluation's job table and slice-test scratch
+// A = item table bytes, F = max(A + extent bytes, construction bytes with
+// ids), E = evaluation bytes for the call's robots.  The three regions never
+// overlap, so resident tables survive the other calls.
+struct BatchLayout {
+    size_t A, F, E;
+};
+
+static BatchLayout batch_layout(const pct_item* h_items, const std::vector<BuildItemDev>& it, int n_items, int n_robots) {
+    BatchLayout L{};
+    L.A = align_up(sizeof(BuildItemDev) * (size_t)n_items);
+    L.F = align_up(std::max(L.A + batch_extent_ws_bytes(it.data(), n_items), batch_build_ws_bytes(it.data(), n_items, true)));
+    L.E = align_up(batch_eval_ws_bytes(h_items, n_items, std::max(1, n_robots)));
+    return L;
+}
+
 size_t pct_batch_workspace_bytes(const pct_item* h_items, int32_t n_items, int32_t n_robots, int32_t with_ids) {
+    (void)with_ids;   // sized for point ids either way, so one workspace serves both
     std::vector<BuildItemDev> it;
     int64_t tot = 0;
-    for (int i = 0; i < n_items; ++i) tot = std::max<int64_t>(tot, h_items[i].xyz_offset + h_items[i].n_points);
+    for (int i = 0; h_items && i < n_items; ++i)
+        tot = std::max<int64_t>(tot, h_items[i].xyz_offset + h_items[i].n_points);
     if (make_items(h_items, n_items, tot, false, &it) != PCT_OK) return 0;
-    size_t b = std::max(batch_extent_ws_bytes(it.data(), n_items), batch_build_ws_bytes(it.data(), n_items, with_ids != 0));
-    return std::max(b, batch_eval_ws_bytes(h_items, n_items, std::max(1, (int)n_robots)));
+    const BatchLayout L = batch_layout(h_items, it, n_items, n_robots);
+    return L.F + L.E;
 }
 
 pct_status pct_tomogram_extent_batched(const float* d_xyz, int64_t n_total, pct_item* h_items, int32_t n_items,
@@ -505,10 +527,11 @@ pct_status pct_tomogram_extent_batched(const float* d_xyz, int64_t n_total, pct_
     pct_status st = make_items(h_items, n_items, n_total, false, &it);
     if (st != PCT_OK) return st;
     if (n_total > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
-    const size_t need = batch_extent_ws_bytes(it.data(), n_items);
+    const size_t A = align_up(sizeof(BuildItemDev) * (size_t)n_items);
+    const size_t need = A + batch_extent_ws_bytes(it.data(), n_items);
     if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "batch extent workspace too small: %zu < %zu", ws_bytes, need);
     std::vector<ExtentDev> ex(n_items);
-    st = launch_extent_batched(d_xyz, it.data(), n_items, d_ws, ex.data(), 1, (hipStream_t)stream);
+    st = launch_extent_batched(d_xyz, it.data(), n_items, (char*)d_ws + A, ex.data(), 1, (hipStream_t)stream);
     if (st != PCT_OK) return st;
     int64_t cells = 0, slices = 0;
     for (int i = 0; i < n_items; ++i) {
@@ -569,8 +592,13 @@ pct_status pct_eval_traversability_batched(const float* d_ground, const float* d
         }
     }
     if (!d_ground || !d_ceil || !d_cost) return fail(PCT_ERR_ARG, "device pointers are null");
-    return launch_eval_batched(d_ground, d_ceil, h_items, n_items, h_robots, n_robots, d_cost, d_keep, d_ws, ws_bytes,
-                               !(flags & PCT_DESCRIPTORS_RESIDENT), (hipStream_t)stream);
+    const BatchLayout L = batch_layout(h_items, it, n_items, n_robots);
+    if (!d_ws || ws_bytes < L.F + L.E)
+        return fail(PCT_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", ws_bytes, L.F + L.E);
+    const size_t eval_off = (ws_bytes - L.E) / 256 * 256;   // the last E bytes, 256-aligned
+    return launch_eval_batched(d_ground, d_ceil, h_items, n_items, h_robots, n_robots, d_cost, d_keep,
+                               (char*)d_ws + eval_off, ws_bytes - eval_off, !(flags & PCT_DESCRIPTORS_RESIDENT),
+                               (hipStream_t)stream);
 }
 
 size_t pct_trajectory_multi_workspace_bytes(int32_t n_profiles) {

@@ -15,8 +15,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kBinPPT = 16;           // points per thread in the binning kernels
-constexpr int kReduceCapIds = 6144;   // LDS record capacity of the tile reduce (with ids)
-constexpr int kReduceCap = 8192;      // ... without ids
+constexpr int kReduceCapIds = 4096;   // LDS record capacity of the tile reduce (with ids)
+constexpr int kReduceCap = 6144;      // ... without ids
 
 __device__ __forceinline__ float wave_min(float v) {
     for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
@@ -127,21 +127,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(unsigned* __restrict__ p, i
         p[i] = v;
 }
 
-// Per-tile point counts with global atomics (used when the tile count
-// exceeds the LDS-privatised path).
-__global__ __launch_bounds__(kBlock) void k_tile_count(const float* __restrict__ xyz, int64_t n, GridDev g,
-                                                       unsigned* __restrict__ gcount) {
-    const int64_t base = (int64_t)blockIdx.x * kBlock * kBinPPT;
-#pragma unroll 4
-    for (int j = 0; j < kBinPPT; ++j) {
-        int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
-        int tile;
-        unsigned cell;
-        float z;
-        if (i < n && bin_point(xyz, i, g, tile, cell, z)) atomicAdd(&gcount[tile], 1u);
-    }
-}
-
 // Exclusive scan of the tile counts (one workgroup): off[0..ntiles], and
 // the scatter cursors start at the offsets.
 __global__ __launch_bounds__(1024) void k_scan_tiles(const unsigned* __restrict__ cnt, int ntiles,
@@ -168,90 +153,224 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const unsigned* __restrict_
     if (threadIdx.x == 1023) off[ntiles] = s_part[1023];
 }
 
-// Scatter of packed records (height, cell-in-tile[, point id]) into tile
-// order with a global atomic cursor per tile (used when the tile count
-// exceeds the LDS-privatised path).  The order inside a tile is not fixed;
-// the tile reduce does not depend on it.
-template <bool IDS>
-__global__ __launch_bounds__(kBlock) void k_tile_scatter(const float* __restrict__ xyz, int64_t n, GridDev g,
-                                                         unsigned* __restrict__ cursor, float* __restrict__ rz,
-                                                         unsigned* __restrict__ rmeta, int* __restrict__ rid) {
-    const int64_t base = (int64_t)blockIdx.x * kBlock * kBinPPT;
-    for (int j = 0; j < kBinPPT; ++j) {
-        const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
-        int tile;
-        unsigned cell;
-        float z;
-        if (i >= n || !bin_point(xyz, i, g, tile, cell, z)) continue;
-        const unsigned pos = atomicAdd(&cursor[tile], 1u);
-        rz[pos] = z;
-        rmeta[pos] = cell;
-        if (IDS) rid[pos] = (int)i;
-    }
+// Two-level binning into construction tiles (a stable-free counting sort).
+// Level 1 sorts points into super-tiles, runs of G consecutive tile ids;
+// level 2 sorts each super-tile's records into its tiles.  With at most
+// 128 buckets per level, each workgroup appends on the order of a hundred
+// records per bucket, so the scattered writes of a workgroup fill whole
+// cache lines instead of touching thousands of lines with a few bytes each.
+// Every level: a per-workgroup LDS histogram written as one column of a
+// bucket-major count matrix, an exclusive scan along each bucket's row
+// (one wavefront per bucket), bucket offsets, then a scatter through LDS
+// cursors.  Positions depend only on the counts, not on timing; the order
+// of records inside one workgroup's run of a bucket is left to the LDS
+// atomics, which the tile reduce does not depend on.
+constexpr int kBinBlock = 512;
+constexpr int64_t kBinChunk = 16384;    // points (level 1) or records (level 2) per workgroup
+constexpr int kSuperTarget = 128;       // buckets per level
+constexpr int kMaxSuperG = 8192;        // tiles per super-tile (LDS counters of level 2)
+
+struct BinPlan {
+    int G, S1, CT;     // tiles per super-tile, super-tiles, cells per tile
+    int nb1;           // level-1 workgroups
+    int nb2;           // level-2 workgroups (upper bound; surplus ones exit)
+    bool two_level;
+};
+
+BinPlan make_bin_plan(int64_t n, const GridDev& g) {
+    BinPlan b{};
+    b.CT = kBuildTileW * g.th;
+    int64_t G = (g.ntiles + kSuperTarget - 1) / kSuperTarget;
+    if (G < 1) G = 1;
+    if (G > kMaxSuperG) G = kMaxSuperG;
+    b.G = (int)G;
+    b.S1 = (int)((g.ntiles + G - 1) / G);
+    b.two_level = b.G > 1;
+    b.nb1 = (int)std::max<int64_t>(1, (n + kBinChunk - 1) / kBinChunk);
+    b.nb2 = b.two_level ? b.nb1 + b.S1 : 0;
+    return b;
 }
 
-// Blocked binning (the tile count fits in LDS): radix-sort style, no
-// global atomics.  Workgroup b counts its chunk of points per tile in LDS
-// and writes the whole count row; a column scan turns the rows into
-// per-(tile, workgroup) offsets; the scatter then places each point with an
-// LDS atomic on its workgroup's cursor for the tile.
-constexpr int kBinBlock = 512;
-
-__global__ __launch_bounds__(kBinBlock) void k_block_hist(const float* __restrict__ xyz, int64_t n, GridDev g,
-                                                          int64_t chunk, unsigned* __restrict__ cnt) {
+// Level-1 histogram: column b of cnt1 [S1][nb1].
+__global__ __launch_bounds__(kBinBlock) void k_bin1_hist(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                         int G, int S1, int nb1, unsigned* __restrict__ cnt1) {
     extern __shared__ unsigned s_cnt[];
-    for (int t = threadIdx.x; t < g.ntiles; t += kBinBlock) s_cnt[t] = 0;
+    for (int t = threadIdx.x; t < S1; t += kBinBlock) s_cnt[t] = 0;
     __syncthreads();
-    const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    const int64_t b0 = (int64_t)blockIdx.x * kBinChunk, b1 = min(n, b0 + kBinChunk);
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kBinBlock) {
         int tile;
         unsigned cell;
         float z;
-        if (bin_point(xyz, i, g, tile, cell, z)) atomicAdd(&s_cnt[tile], 1u);
+        if (bin_point(xyz, i, g, tile, cell, z)) atomicAdd(&s_cnt[tile / G], 1u);
     }
     __syncthreads();
-    unsigned* row = cnt + (int64_t)blockIdx.x * g.ntiles;
-    for (int t = threadIdx.x; t < g.ntiles; t += kBinBlock) row[t] = s_cnt[t];
+    for (int t = threadIdx.x; t < S1; t += kBinBlock) cnt1[(int64_t)t * nb1 + blockIdx.x] = s_cnt[t];
 }
 
-// Per tile, exclusive scan of the counts down the workgroup rows; the
-// column total goes to total[t].
-__global__ __launch_bounds__(kBlock) void k_scan_cols(unsigned* __restrict__ cnt, int nb, int ntiles,
-                                                      unsigned* __restrict__ total) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= ntiles) return;
-    unsigned s = 0;
-    for (int b = 0; b < nb; ++b) {
-        const unsigned v = cnt[(int64_t)b * ntiles + t];
-        cnt[(int64_t)b * ntiles + t] = s;
-        s += v;
+// Exclusive scan of row[0..len) in place by one wavefront; returns the total
+// (in every lane).
+__device__ unsigned wave_scan_row(unsigned* __restrict__ row, int len) {
+    const int lane = threadIdx.x & 63;
+    unsigned carry = 0;
+    for (int base = 0; base < len; base += 64) {
+        const unsigned v = base + lane < len ? row[base + lane] : 0u;
+        unsigned incl = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned u = __shfl(incl, lane - d, 64);
+            if (lane >= d) incl += u;
+        }
+        if (base + lane < len) row[base + lane] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
     }
-    total[t] = s;
+    return carry;
 }
 
-template <bool IDS>
-__global__ __launch_bounds__(kBinBlock) void k_block_scatter(const float* __restrict__ xyz, int64_t n, GridDev g,
-                                                             int64_t chunk, const unsigned* __restrict__ cnt,
-                                                             const unsigned* __restrict__ off, float* __restrict__ rz,
-                                                             unsigned* __restrict__ rmeta, int* __restrict__ rid) {
+// Level-1 rows: bucket s scans its row of cnt1; the total goes to tot1[s].
+__global__ __launch_bounds__(kBlock) void k_bin1_rows(unsigned* __restrict__ cnt1, int nb1, int S1,
+                                                      unsigned* __restrict__ tot1) {
+    const int s = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x / 64);
+    if (s >= S1) return;
+    const unsigned t = wave_scan_row(cnt1 + (int64_t)s * nb1, nb1);
+    if ((threadIdx.x & 63) == 0) tot1[s] = t;
+}
+
+// One workgroup: super-tile offsets off1[0..S1] and the level-2 workgroup
+// bases cbase[0..S1] (each super-tile gets ceil(tot1 / kBinChunk) of them).
+__global__ __launch_bounds__(1024) void k_bin1_offsets(const unsigned* __restrict__ tot1, int S1,
+                                                       unsigned* __restrict__ off1, unsigned* __restrict__ cbase) {
+    __shared__ unsigned s_a[1024], s_b[1024];
+    const int per = (S1 + 1023) / 1024;
+    const int b = threadIdx.x * per, e = min(b + per, S1);
+    unsigned sa = 0, sb = 0;
+    for (int i = b; i < e; ++i) {
+        sa += tot1[i];
+        sb += (unsigned)((tot1[i] + kBinChunk - 1) / kBinChunk);
+    }
+    s_a[threadIdx.x] = sa;
+    s_b[threadIdx.x] = sb;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const unsigned va = threadIdx.x >= (unsigned)d ? s_a[threadIdx.x - d] : 0u;
+        const unsigned vb = threadIdx.x >= (unsigned)d ? s_b[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s_a[threadIdx.x] += va;
+        s_b[threadIdx.x] += vb;
+        __syncthreads();
+    }
+    unsigned ra = s_a[threadIdx.x] - sa, rb = s_b[threadIdx.x] - sb;
+    for (int i = b; i < e; ++i) {
+        off1[i] = ra;
+        cbase[i] = rb;
+        ra += tot1[i];
+        rb += (unsigned)((tot1[i] + kBinChunk - 1) / kBinChunk);
+    }
+    if (threadIdx.x == 1023) {
+        off1[S1] = s_a[1023];
+        cbase[S1] = s_b[1023];
+    }
+}
+
+// Level-1 scatter.  FINAL (one tile per super-tile): records go straight to
+// the tile arrays as (height, cell-in-tile[, id]); otherwise to the level-1
+// arrays with key = tile-in-super-tile * CT + cell.
+template <bool IDS, bool FINAL>
+__global__ __launch_bounds__(kBinBlock) void k_bin1_scatter(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                            int G, int S1, int CT, int nb1,
+                                                            const unsigned* __restrict__ cnt1,
+                                                            const unsigned* __restrict__ off1, float* __restrict__ oz,
+                                                            unsigned* __restrict__ okey, int* __restrict__ oid) {
     extern __shared__ unsigned s_cur[];
-    const unsigned* row = cnt + (int64_t)blockIdx.x * g.ntiles;
-    for (int t = threadIdx.x; t < g.ntiles; t += kBinBlock) s_cur[t] = off[t] + row[t];
+    for (int t = threadIdx.x; t < S1; t += kBinBlock) s_cur[t] = off1[t] + cnt1[(int64_t)t * nb1 + blockIdx.x];
     __syncthreads();
-    const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    const int64_t b0 = (int64_t)blockIdx.x * kBinChunk, b1 = min(n, b0 + kBinChunk);
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kBinBlock) {
         int tile;
         unsigned cell;
         float z;
         if (!bin_point(xyz, i, g, tile, cell, z)) continue;
-        const unsigned pos = atomicAdd(&s_cur[tile], 1u);
-        rz[pos] = z;
-        rmeta[pos] = cell;
-        if (IDS) rid[pos] = (int)i;
+        const int st = tile / G;
+        const unsigned pos = atomicAdd(&s_cur[st], 1u);
+        oz[pos] = z;
+        okey[pos] = FINAL ? cell : (unsigned)(tile - st * G) * (unsigned)CT + cell;
+        if (IDS) oid[pos] = (int)i;
+    }
+}
+
+// Level-2 workgroup q covers records [off1[s] + j kBinChunk, ...) of
+// super-tile s, with cbase[s] <= q = cbase[s] + j < cbase[s+1].
+__device__ __forceinline__ int bin2_super(const unsigned* __restrict__ cbase, int S1, unsigned q) {
+    int lo = 0, hi = S1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (cbase[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Level-2 histogram: column q of cnt2 [G][nb2].
+__global__ __launch_bounds__(kBinBlock) void k_bin2_hist(const unsigned* __restrict__ key1,
+                                                         const unsigned* __restrict__ off1,
+                                                         const unsigned* __restrict__ cbase, int S1, int G, int CT,
+                                                         int nb2, unsigned* __restrict__ cnt2) {
+    extern __shared__ unsigned s_cnt[];
+    const unsigned q = blockIdx.x;
+    if (q >= cbase[S1]) return;   // surplus workgroup (uniform)
+    const int st = bin2_super(cbase, S1, q);
+    const unsigned r0 = off1[st] + (q - cbase[st]) * (unsigned)kBinChunk;
+    const unsigned r1 = min(off1[st + 1], r0 + (unsigned)kBinChunk);
+    for (int t = threadIdx.x; t < G; t += kBinBlock) s_cnt[t] = 0;
+    __syncthreads();
+    for (unsigned r = r0 + threadIdx.x; r < r1; r += kBinBlock) atomicAdd(&s_cnt[key1[r] / (unsigned)CT], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < G; t += kBinBlock) cnt2[(int64_t)t * nb2 + q] = s_cnt[t];
+}
+
+// Level-2 rows: tile t = st G + l scans its workgroups' counts (the
+// columns cbase[st] .. cbase[st+1] of row l of cnt2); the total goes to
+// tot[t].
+__global__ __launch_bounds__(kBlock) void k_bin2_rows(unsigned* __restrict__ cnt2, const unsigned* __restrict__ cbase,
+                                                      int G, int ntiles, int nb2, unsigned* __restrict__ tot) {
+    const int t = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x / 64);
+    if (t >= ntiles) return;
+    const int st = t / G, l = t - st * G;
+    const unsigned c0 = cbase[st], c1 = cbase[st + 1];
+    const unsigned total = wave_scan_row(cnt2 + (int64_t)l * nb2 + c0, (int)(c1 - c0));
+    if ((threadIdx.x & 63) == 0) tot[t] = total;
+}
+
+// Level-2 scatter into the tile arrays: (height, cell-in-tile[, id]).
+template <bool IDS>
+__global__ __launch_bounds__(kBinBlock) void k_bin2_scatter(const float* __restrict__ z1,
+                                                            const unsigned* __restrict__ key1,
+                                                            const int* __restrict__ id1,
+                                                            const unsigned* __restrict__ off1,
+                                                            const unsigned* __restrict__ cbase, int S1, int G, int CT,
+                                                            int nb2, const unsigned* __restrict__ cnt2,
+                                                            const unsigned* __restrict__ off, float* __restrict__ rz,
+                                                            unsigned* __restrict__ rmeta, int* __restrict__ rid) {
+    extern __shared__ unsigned s_cur[];
+    const unsigned q = blockIdx.x;
+    if (q >= cbase[S1]) return;
+    const int st = bin2_super(cbase, S1, q);
+    const unsigned r0 = off1[st] + (q - cbase[st]) * (unsigned)kBinChunk;
+    const unsigned r1 = min(off1[st + 1], r0 + (unsigned)kBinChunk);
+    const int tbase = st * G;
+    for (int t = threadIdx.x; t < G; t += kBinBlock) s_cur[t] = off[tbase + t] + cnt2[(int64_t)t * nb2 + q];
+    __syncthreads();
+    for (unsigned r = r0 + threadIdx.x; r < r1; r += kBinBlock) {
+        const unsigned key = key1[r];
+        const unsigned l = key / (unsigned)CT;
+        const unsigned pos = atomicAdd(&s_cur[l], 1u);
+        rz[pos] = z1[r];
+        rmeta[pos] = key - l * (unsigned)CT;
+        if (IDS) rid[pos] = id1[r];
     }
 }
 
 // ------------------------------------------------------------------ reduce
+constexpr int kReduceBlock = 512;   // one cell per thread for the 512-cell tiles
 __device__ __forceinline__ bool rec_less(float za, int ia, float zb, int ib, bool ids) {
     return za < zb || (ids && za == zb && ia < ib);
 }
@@ -300,14 +419,14 @@ __device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __r
                           const unsigned* __restrict__ rmeta, const int* __restrict__ rid, int ix, int iy,
                           const GridDev& g, float zmin, float ds, int N, float* __restrict__ ground,
                           float* __restrict__ ceil, int* __restrict__ ag, int* __restrict__ ac) {
-    __shared__ float s_gz[kBlock], s_cz[kBlock];
-    __shared__ int s_gi[kBlock], s_ci[kBlock];
+    __shared__ float s_gz[kReduceBlock], s_cz[kReduceBlock];
+    __shared__ int s_gi[kReduceBlock], s_ci[kReduceBlock];
     const int64_t plane = (int64_t)g.nx * g.ny;
     for (int k = 0; k < N; ++k) {
         const float hk = plane_height(zmin, ds, k);
         float gz = -INFINITY, cz = INFINITY;
         int gi = 0x7fffffff, ci = 0x7fffffff;
-        for (unsigned r = r0 + threadIdx.x; r < r1; r += kBlock) {
+        for (unsigned r = r0 + threadIdx.x; r < r1; r += kReduceBlock) {
             if (rmeta[r] != c) continue;
             float z = rz[r];
             int id = IDS ? rid[r] : 0;
@@ -320,7 +439,7 @@ __device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __r
         s_gz[threadIdx.x] = gz; s_gi[threadIdx.x] = gi;
         s_cz[threadIdx.x] = cz; s_ci[threadIdx.x] = ci;
         __syncthreads();
-        for (int s = kBlock / 2; s > 0; s >>= 1) {
+        for (int s = kReduceBlock / 2; s > 0; s >>= 1) {
             if ((int)threadIdx.x < s) {
                 float z2 = s_gz[threadIdx.x + s];
                 int i2 = s_gi[threadIdx.x + s];
@@ -366,20 +485,20 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
     const int tx = tl % g.ntx, ty = tl / g.ntx;
     const unsigned r0 = off[tg], r1 = off[tg + 1];
 
-    for (int c = threadIdx.x; c < cells; c += kBlock) s_cnt[c] = 0;
+    for (int c = threadIdx.x; c < cells; c += kReduceBlock) s_cnt[c] = 0;
     __syncthreads();
-    for (unsigned r = r0 + threadIdx.x; r < r1; r += kBlock) atomicAdd(&s_cnt[rmeta[r]], 1u);
+    for (unsigned r = r0 + threadIdx.x; r < r1; r += kReduceBlock) atomicAdd(&s_cnt[rmeta[r]], 1u);
     __syncthreads();
     // exclusive scan of the per-cell counts; thread i owns a contiguous run
     {
-        __shared__ unsigned s_part[kBlock];
-        const int per = (cells + kBlock - 1) / kBlock;
+        __shared__ unsigned s_part[kReduceBlock];
+        const int per = (cells + kReduceBlock - 1) / kReduceBlock;
         const int b = threadIdx.x * per, e = min(b + per, cells);
         unsigned sum = 0;
         for (int i = b; i < e; ++i) sum += s_cnt[i];
         s_part[threadIdx.x] = sum;
         __syncthreads();
-        for (int d = 1; d < kBlock; d <<= 1) {
+        for (int d = 1; d < kReduceBlock; d <<= 1) {
             unsigned v = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0u;
             __syncthreads();
             s_part[threadIdx.x] += v;
@@ -390,7 +509,7 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
             s_start[i] = run;
             run += s_cnt[i];
         }
-        if (threadIdx.x == kBlock - 1) s_start[cells] = s_part[kBlock - 1];
+        if (threadIdx.x == kReduceBlock - 1) s_start[cells] = s_part[kReduceBlock - 1];
     }
     __syncthreads();
 
@@ -415,9 +534,9 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
             const int iy = ty * g.th + c_lo / kBuildTileW;
             huge_cell<IDS>((unsigned)c_lo, r0, r1, rz, rmeta, rid, ix, iy, g, zmin, ds, N, ground, ceil, ag, ac);
         } else {
-            for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) s_cnt[c] = 0;
+            for (int c = c_lo + threadIdx.x; c < c_hi; c += kReduceBlock) s_cnt[c] = 0;
             __syncthreads();
-            for (unsigned r = r0 + threadIdx.x; r < r1; r += kBlock) {
+            for (unsigned r = r0 + threadIdx.x; r < r1; r += kReduceBlock) {
                 unsigned c = rmeta[r];
                 if ((int)c < c_lo || (int)c >= c_hi) continue;
                 unsigned pos = s_start[c] - g0 + atomicAdd(&s_cnt[c], 1u);
@@ -425,7 +544,7 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
                 if (IDS) s_id[pos] = rid[r];
             }
             __syncthreads();
-            for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) {
+            for (int c = c_lo + threadIdx.x; c < c_hi; c += kReduceBlock) {
                 const int ix = tx * kBuildTileW + (c % kBuildTileW);
                 const int iy = ty * g.th + c / kBuildTileW;
                 if (ix >= g.nx || iy >= g.ny) continue;
@@ -440,7 +559,7 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
 }
 
 template <bool IDS>
-__global__ __launch_bounds__(kBlock) void k_tile_reduce(const unsigned* __restrict__ off,
+__global__ __launch_bounds__(kReduceBlock) void k_tile_reduce(const unsigned* __restrict__ off,
                                                         const float* __restrict__ rz,
                                                         const unsigned* __restrict__ rmeta,
                                                         const int* __restrict__ rid, GridDev g, float zmin,
@@ -456,10 +575,14 @@ inline size_t reduce_lds_bytes(const GridDev& g, bool ids) {
 }
 
 struct BuildWs {
-    unsigned *count, *off, *cursor, *bcount;
-    int64_t chunk;
-    int nb;
-    float* rz;
+    BinPlan bp;
+    unsigned *cnt1, *tot1, *off1, *cbase;   // level 1
+    unsigned *cnt2;                          // level 2
+    unsigned *count, *off, *cursor;          // tiles
+    float* z1;                               // level-1 records
+    unsigned* key1;
+    int* id1;
+    float* rz;                               // tile records
     unsigned* rmeta;
     int* rid;
     size_t bytes;
@@ -474,13 +597,18 @@ BuildWs carve_build_ws(void* base, int64_t n, const GridDev& g, bool ids) {
         o += align_up(bytes);
         return r;
     };
-    // chunk of the blocked binning: at least 16384 points per workgroup,
-    // doubled until the per-workgroup count matrix has <= 2^26 entries
-    w.chunk = 16384;
-    while (((n + w.chunk - 1) / w.chunk) * (int64_t)g.ntiles > (int64_t(1) << 26)) w.chunk *= 2;
-    w.nb = (int)std::max<int64_t>(1, (n + w.chunk - 1) / w.chunk);
-    const bool blocked = g.ntiles <= kMaxLdsTiles;
-    w.bcount = blocked ? (unsigned*)take(sizeof(unsigned) * (size_t)w.nb * g.ntiles) : nullptr;
+    w.bp = make_bin_plan(n, g);
+    const BinPlan& b = w.bp;
+    w.cnt1 = (unsigned*)take(sizeof(unsigned) * (size_t)b.S1 * b.nb1);
+    w.tot1 = (unsigned*)take(sizeof(unsigned) * (size_t)(b.S1 + 1));
+    w.off1 = (unsigned*)take(sizeof(unsigned) * (size_t)(b.S1 + 1));
+    w.cbase = (unsigned*)take(sizeof(unsigned) * (size_t)(b.S1 + 1));
+    if (b.two_level) {
+        w.cnt2 = (unsigned*)take(sizeof(unsigned) * (size_t)b.G * b.nb2);
+        w.z1 = (float*)take(sizeof(float) * (size_t)n);
+        w.key1 = (unsigned*)take(sizeof(unsigned) * (size_t)n);
+        w.id1 = ids ? (int*)take(sizeof(int) * (size_t)n) : nullptr;
+    }
     w.count = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
     w.off = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
     w.cursor = (unsigned*)take(sizeof(unsigned) * (g.ntiles + 1));
@@ -662,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_bscatter(const float* __restrict__ x
 }
 
 template <bool IDS>
-__global__ __launch_bounds__(kBlock) void k_breduce(const unsigned* __restrict__ off, const float* __restrict__ rz,
+__global__ __launch_bounds__(kReduceBlock) void k_breduce(const unsigned* __restrict__ off, const float* __restrict__ rz,
                                                     const unsigned* __restrict__ rmeta, const int* __restrict__ rid,
                                                     const BuildItemDev* __restrict__ items, int n_items,
                                                     float* __restrict__ ground, float* __restrict__ ceil,
@@ -738,60 +866,65 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
     const bool ids = ag != nullptr;
     BuildWs w = carve_build_ws(ws, n, g, ids);
     if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "build workspace too small: %zu < %zu", ws_bytes, w.bytes);
-    const bool lds = g.ntiles <= kMaxLdsTiles;
-    if (lds) {
-        // blocked binning: per-workgroup counts, column scan, tile scan, scatter
-        if (n > 0) {
-            hipLaunchKernelGGL(k_block_hist, dim3(w.nb), dim3(kBinBlock), sizeof(unsigned) * g.ntiles, s, xyz, n, g,
-                               w.chunk, w.bcount);
+    const BinPlan& b = w.bp;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(std::min(1024, g.ntiles / kBlock + 1)), dim3(kBlock), 0, s, w.count,
+                           (int64_t)g.ntiles + 1, 0u);
+        PCT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
+        PCT_LAUNCH_CHECK();
+    } else {
+        // level 1: points -> super-tiles (the tiles themselves when G = 1)
+        const size_t l1 = sizeof(unsigned) * (size_t)b.S1;
+        hipLaunchKernelGGL(k_bin1_hist, dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G, b.S1, b.nb1, w.cnt1);
+        PCT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_bin1_rows, dim3((b.S1 + 3) / 4), dim3(kBlock), 0, s, w.cnt1, b.nb1, b.S1, w.tot1);
+        PCT_LAUNCH_CHECK();
+        if (!b.two_level) {
+            hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.tot1, g.ntiles, w.off, w.cursor);
             PCT_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_scan_cols, dim3((g.ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, w.bcount, w.nb,
-                               g.ntiles, w.count);
+            if (ids)
+                hipLaunchKernelGGL((k_bin1_scatter<true, true>), dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G,
+                                   b.S1, b.CT, b.nb1, w.cnt1, w.off, w.rz, w.rmeta, w.rid);
+            else
+                hipLaunchKernelGGL((k_bin1_scatter<false, true>), dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G,
+                                   b.S1, b.CT, b.nb1, w.cnt1, w.off, w.rz, w.rmeta, w.rid);
             PCT_LAUNCH_CHECK();
         } else {
-            hipLaunchKernelGGL(k_fill_u32, dim3(std::min(1024, g.ntiles / kBlock + 1)), dim3(kBlock), 0, s, w.count,
-                               (int64_t)g.ntiles + 1, 0u);
+            hipLaunchKernelGGL(k_bin1_offsets, dim3(1), dim3(1024), 0, s, w.tot1, b.S1, w.off1, w.cbase);
             PCT_LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
-        PCT_LAUNCH_CHECK();
-        if (n > 0) {
             if (ids)
-                hipLaunchKernelGGL(k_block_scatter<true>, dim3(w.nb), dim3(kBinBlock), sizeof(unsigned) * g.ntiles, s,
-                                   xyz, n, g, w.chunk, w.bcount, w.off, w.rz, w.rmeta, w.rid);
+                hipLaunchKernelGGL((k_bin1_scatter<true, false>), dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G,
+                                   b.S1, b.CT, b.nb1, w.cnt1, w.off1, w.z1, w.key1, w.id1);
             else
-                hipLaunchKernelGGL(k_block_scatter<false>, dim3(w.nb), dim3(kBinBlock), sizeof(unsigned) * g.ntiles, s,
-                                   xyz, n, g, w.chunk, w.bcount, w.off, w.rz, w.rmeta, w.rid);
+                hipLaunchKernelGGL((k_bin1_scatter<false, false>), dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G,
+                                   b.S1, b.CT, b.nb1, w.cnt1, w.off1, w.z1, w.key1, w.id1);
             PCT_LAUNCH_CHECK();
-        }
-    } else {
-        // more tiles than LDS holds: global atomics on the tile counters
-        const int fill_blocks = std::min(1024, (g.ntiles + kBlock) / kBlock + 1);
-        hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(kBlock), 0, s, w.count, (int64_t)g.ntiles + 1, 0u);
-        PCT_LAUNCH_CHECK();
-        const int64_t chunks = (n + (int64_t)kBlock * kBinPPT - 1) / ((int64_t)kBlock * kBinPPT);
-        if (chunks > 0) {
-            hipLaunchKernelGGL(k_tile_count, dim3((unsigned)chunks), dim3(kBlock), 0, s, xyz, n, g, w.count);
+            // level 2: each super-tile's records -> its tiles
+            const size_t l2 = sizeof(unsigned) * (size_t)b.G;
+            hipLaunchKernelGGL(k_bin2_hist, dim3(b.nb2), dim3(kBinBlock), l2, s, w.key1, w.off1, w.cbase, b.S1, b.G,
+                               b.CT, b.nb2, w.cnt2);
             PCT_LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
-        PCT_LAUNCH_CHECK();
-        if (chunks > 0) {
+            hipLaunchKernelGGL(k_bin2_rows, dim3((g.ntiles + 3) / 4), dim3(kBlock), 0, s, w.cnt2, w.cbase, b.G,
+                               g.ntiles, b.nb2, w.count);
+            PCT_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
+            PCT_LAUNCH_CHECK();
             if (ids)
-                hipLaunchKernelGGL(k_tile_scatter<true>, dim3((unsigned)chunks), dim3(kBlock), 0, s, xyz, n, g,
-                                   w.cursor, w.rz, w.rmeta, w.rid);
+                hipLaunchKernelGGL(k_bin2_scatter<true>, dim3(b.nb2), dim3(kBinBlock), l2, s, w.z1, w.key1, w.id1,
+                                   w.off1, w.cbase, b.S1, b.G, b.CT, b.nb2, w.cnt2, w.off, w.rz, w.rmeta, w.rid);
             else
-                hipLaunchKernelGGL(k_tile_scatter<false>, dim3((unsigned)chunks), dim3(kBlock), 0, s, xyz, n, g,
-                                   w.cursor, w.rz, w.rmeta, w.rid);
+                hipLaunchKernelGGL(k_bin2_scatter<false>, dim3(b.nb2), dim3(kBinBlock), l2, s, w.z1, w.key1, w.id1,
+                                   w.off1, w.cbase, b.S1, b.G, b.CT, b.nb2, w.cnt2, w.off, w.rz, w.rmeta, w.rid);
             PCT_LAUNCH_CHECK();
         }
     }
     const size_t rl = reduce_lds_bytes(g, ids);
     if (ids)
-        hipLaunchKernelGGL(k_tile_reduce<true>, dim3(g.ntiles), dim3(kBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
+        hipLaunchKernelGGL(k_tile_reduce<true>, dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
                            zmin, ds, N, ground, ceil, ag, ac);
     else
-        hipLaunchKernelGGL(k_tile_reduce<false>, dim3(g.ntiles), dim3(kBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
+        hipLaunchKernelGGL(k_tile_reduce<false>, dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
                            zmin, ds, N, ground, ceil, ag, ac);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
@@ -894,10 +1027,10 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
     }
     if (w.total_tiles > 0) {
         if (ids)
-            hipLaunchKernelGGL(k_breduce<true>, dim3(w.total_tiles), dim3(kBlock), max_reduce_lds, s, w.off, w.rz, w.rmeta,
+            hipLaunchKernelGGL(k_breduce<true>, dim3(w.total_tiles), dim3(kReduceBlock), max_reduce_lds, s, w.off, w.rz, w.rmeta,
                                w.rid, w.items, n_items, ground, ceil, ag, ac);
         else
-            hipLaunchKernelGGL(k_breduce<false>, dim3(w.total_tiles), dim3(kBlock), max_reduce_lds, s, w.off, w.rz,
+            hipLaunchKernelGGL(k_breduce<false>, dim3(w.total_tiles), dim3(kReduceBlock), max_reduce_lds, s, w.off, w.rz,
                                w.rmeta, w.rid, w.items, n_items, ground, ceil, ag, ac);
         PCT_LAUNCH_CHECK();
     }

@@ -47,9 +47,39 @@ def digest():
     return h.hexdigest()
 
 
+def _balanced(text, i):
+    """Index just past the parenthesis that closes the one at text[i]."""
+    depth = 0
+    for j in range(i, len(text)):
+        if text[j] == "(":
+            depth += 1
+        elif text[j] == ")":
+            depth -= 1
+            if depth == 0:
+                return j + 1
+    raise ValueError("unbalanced parentheses")
+
+
 def rewrite(src):
-    text = open(src).read()
-    return DYN_SHARED.sub(lambda m: f"{m.group(1)}* {m.group(2)} = ({m.group(1)}*)::emu::dyn_smem();", text)
+    """Dynamic LDS declarations become pointers to the launch's LDS buffer;
+    every kernel with __launch_bounds__(B) checks at entry that the launch
+    has at most B threads per workgroup."""
+    text = DYN_SHARED.sub(lambda m: f"{m.group(1)}* {m.group(2)} = ({m.group(1)}*)::emu::dyn_smem();",
+                          open(src).read())
+    out, pos = [], 0
+    key = "__launch_bounds__("
+    while True:
+        i = text.find(key, pos)
+        if i < 0:
+            out.append(text[pos:])
+            break
+        e = _balanced(text, i + len(key) - 1)
+        expr = text[i + len(key):e - 1]
+        body = text.find("{", e)
+        out.append(text[pos:body + 1])
+        out.append(f" ::emu::check_launch_bound((int)({expr}), __func__);")
+        pos = body + 1
+    return "".join(out)
 
 
 def build(force=False):

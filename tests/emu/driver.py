@@ -235,6 +235,19 @@ def case_many_chunks():
     tomogram_case(pts, grid, True, "1.3M points")
 
 
+def case_two_level():
+    """Enough tiles for two binning levels with several level-2 workgroups
+    per super-tile, a ragged last super-tile and an empty band."""
+    rng = np.random.default_rng(9)
+    grid = dict(x0=0.0, y0=0.0, res=0.1, nx=1000, ny=606, slice_dz=0.3)
+    n = 1_800_000
+    x = rng.uniform(-1.0, 101.0, n)
+    y = rng.uniform(0.0, 60.6, n)
+    keep = ~((y > 20.0) & (y < 26.0))          # a band of tiles with no points
+    pts = np.column_stack([x[keep], y[keep], rng.uniform(0.0, 4.0, keep.sum())]).astype(np.float32)
+    tomogram_case(pts, grid, True, "two-level binning")
+
+
 # ----------------------------------------------------------------- batches
 
 def make_batch(seed, n_items, side_hi=160, pts_hi=120_000, extra_empty=True):
@@ -317,6 +330,41 @@ def check_batch(items_sc, pts, specs, robots, ids, n_oracle=3, step=1):
 def case_batch():
     items, pts, specs = make_batch(61, 6, side_hi=60, pts_hi=30_000)
     check_batch(items, pts, specs, [robot(), robot(d_min=0.7, theta_s=0.3)], True)
+
+
+def case_batch_resident():
+    """Eager extent, build and evaluation, then build and evaluation again
+    with PCT_DESCRIPTORS_RESIDENT on the same workspace (the sequence a
+    graph capture uses): the same outputs."""
+    items_sc, pts, specs = make_batch(63, 5, side_hi=60, pts_hi=30_000, extra_empty=False)
+    robots = [robot()]
+    n_items = len(specs)
+    items = (abi.pct_item * n_items)()
+    for it, sp in zip(items, specs):
+        it.xyz_offset, it.n_points = sp["xyz_offset"], sp["n_points"]
+        it.grid = grid_s(sp["grid"])
+    xb = Buf.of(pts)
+    tc, ts = C.c_int64(), C.c_int64()
+    ws = Buf(L.pct_batch_workspace_bytes(items, n_items, 1, 0))
+    check("extent_batched", L.pct_tomogram_extent_batched(P(xb), len(pts), items, n_items, C.byref(tc), C.byref(ts),
+                                                          P(ws), ws.nbytes, None))
+    ws = Buf(L.pct_batch_workspace_bytes(items, n_items, 1, 0))
+    cells, slices = tc.value, ts.value
+    rs = (abi.pct_robot * 1)(robot_s(robots[0]))
+    outs = []
+    for flags in (0, abi.PCT_DESCRIPTORS_RESIDENT, abi.PCT_DESCRIPTORS_RESIDENT):
+        G, Cc = Buf(4 * cells), Buf(4 * cells)
+        cost, kp = Buf(4 * cells), Buf(slices)
+        check("build_batched", L.pct_build_tomogram_batched(P(xb), len(pts), items, n_items, P(G), P(Cc), None, None,
+                                                            flags, P(ws), ws.nbytes, None))
+        check("eval_batched", L.pct_eval_traversability_batched(P(G), P(Cc), items, n_items, rs, 1, P(cost), P(kp),
+                                                                flags, P(ws), ws.nbytes, None))
+        outs.append([G.get(cells, np.float32), Cc.get(cells, np.float32), cost.get(cells, np.float32),
+                     kp.get(slices, np.uint8)])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            np.testing.assert_array_equal(bits(a), bits(b))
+    say(f"batch with resident descriptors: {n_items} items, 2 replays equal the eager run")
 
 
 def case_batch_mixed_radius():

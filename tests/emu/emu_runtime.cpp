@@ -270,6 +270,15 @@ void syncthreads() {
 
 void* dyn_smem() { return S.smem; }
 
+void check_launch_bound(int bound, const char* fn) {
+    const unsigned nt = blockDim.x * blockDim.y * blockDim.z;
+    if ((long long)nt > bound) {
+        fprintf(stderr, "[emu] %s launched with %u threads per workgroup, above its launch bound %d\n", fn, nt, bound);
+        fflush(stderr);
+        abort();
+    }
+}
+
 unsigned lane_id() { return (unsigned)S.cur & 63u; }
 
 bool begin_launch(const char* name, const void* fn, dim3 grid, dim3 block, size_t smem) {

@@ -73,6 +73,9 @@ void* dyn_smem();
 unsigned lane_id();
 
 bool begin_launch(const char* name, const void* fn, dim3 grid, dim3 block, size_t smem);
+// Aborts when the running launch has more threads per workgroup than the
+// kernel's __launch_bounds__ (the hardware would not run such a launch).
+void check_launch_bound(int bound, const char* fn);
 void run_blocks(void (*thunk)(void*), void* ctx);
 
 template <class T>

@@ -44,8 +44,8 @@ def run_cases(cases, order="fwd", timeout=900):
 @pytest.mark.parametrize("cases,order", [
     (["tiny", "edges", "config0", "multirobot", "fallback_eval"], "rev"),
     (["crop", "dense", "multirobot_large"], "rand"),
-    (["many_chunks"], "fwd"),
-    (["batch", "batch_mixed_radius"], "rand"),
+    (["many_chunks", "two_level"], "fwd"),
+    (["batch", "batch_resident", "batch_mixed_radius"], "rand"),
     (["traj_value_grad"], "fwd"),
 ])
 def test_kernels_on_cpu(emu_lib, cases, order):

@@ -15,13 +15,6 @@ import scenes
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
-# A GPU run that included the tests marked with this ended in a GPU memory
-# fault whose cause has not been found: the same kernels built for the CPU
-# with AddressSanitizer run these cases cleanly and bit-exactly against the
-# oracle (tests/test_emu.py).  Until a cause is shown they stay off the GPU.
-OFF_GPU = pytest.mark.skip(reason="kept off the GPU after an unexplained GPU memory fault in a run that included it; "
-                                  "the same case runs on the CPU build of the kernels in tests/test_emu.py")
-
 
 def say(msg):
     print(f"[gpu] {msg}", file=sys.stderr, flush=True)
@@ -81,7 +74,6 @@ def crop_scene(seed=21, lx=31.7, ly=23.3, n=500_000):
 # --------------------------------------------------------------- construction
 
 
-@OFF_GPU
 def test_tiny_golden(P, oracle_lib):
     from conftest import load_golden
     g = load_golden("tiny_tomogram.json")
@@ -94,7 +86,6 @@ def test_tiny_golden(P, oracle_lib):
 
 
 
-@OFF_GPU
 @pytest.mark.parametrize("name", ["config0", "crop", "dense"])
 @pytest.mark.parametrize("ids", [True, False])
 def test_build_parity(P, oracle_lib, name, ids):
@@ -107,7 +98,6 @@ def test_build_parity(P, oracle_lib, name, ids):
     check_tomogram(P, oracle_lib, sc.points, sc.grid, ids)
 
 
-@OFF_GPU
 def test_build_edge_cases(P, oracle_lib):
     rng = np.random.default_rng(5)
     grid = dict(x0=-1.0, y0=2.0, res=0.125, nx=130, ny=19, slice_dz=0.25)
@@ -134,7 +124,6 @@ def test_build_edge_cases(P, oracle_lib):
     check_tomogram(P, oracle_lib, e, grid)
 
 
-@OFF_GPU
 def test_build_deterministic(P):
     sc = crop_scene(seed=23, n=300_000)
     say("determinism")
@@ -213,7 +202,6 @@ def test_eval_analytic_scenes(P, oracle_lib):
         check_eval(P, oracle_lib, sc.points, sc.grid, [robot()], name)
 
 
-@OFF_GPU
 def test_eval_many_robots_match_single(P, oracle_lib):
     sc = scenes.multistorey_scene(33, 8.3, 6.1, 300_000, n_floors=2)
     rs = [robot(), robot(d_min=0.7, theta_s=0.3), robot(d_inf=0.5, d_sm=0.7)]
@@ -228,7 +216,6 @@ def test_eval_many_robots_match_single(P, oracle_lib):
 # --------------------------------------------------------------- full size
 
 
-@OFF_GPU
 def test_full_size_config1_windows(P, oracle_lib):
     """The 20 M-point map at its full size, in the benchmark's launch
     configuration: the tomogram and the costs are compared exactly on
