@@ -14,7 +14,6 @@ namespace pct {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kBinPPT = 16;           // points per thread in the binning kernels
 constexpr int kReduceCapIds = 4096;   // LDS record capacity of the tile reduce (with ids)
 constexpr int kReduceCap = 6144;      // ... without ids
 
@@ -166,15 +165,18 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const unsigned* __restrict_
 // of records inside one workgroup's run of a bucket is left to the LDS
 // atomics, which the tile reduce does not depend on.
 constexpr int kBinBlock = 512;
-constexpr int64_t kBinChunk = 16384;    // points (level 1) or records (level 2) per workgroup
+constexpr int64_t kBinChunk = 4096;     // points (level 1) or records (level 2) per workgroup
+constexpr int kBinPPT = (int)kBinChunk / kBinBlock;   // per thread
 constexpr int kSuperTarget = 128;       // buckets per level
 constexpr int kMaxSuperG = 8192;        // tiles per super-tile (LDS counters of level 2)
+constexpr int kMaxStaged = 1024;        // buckets of a scatter that stages its chunk in LDS
 
 struct BinPlan {
     int G, S1, CT;     // tiles per super-tile, super-tiles, cells per tile
     int nb1;           // level-1 workgroups
     int nb2;           // level-2 workgroups (upper bound; surplus ones exit)
     bool two_level;
+    bool staged1, staged2;   // scatters staged in LDS (bucket counts within kMaxStaged)
 };
 
 BinPlan make_bin_plan(int64_t n, const GridDev& g) {
@@ -188,6 +190,8 @@ BinPlan make_bin_plan(int64_t n, const GridDev& g) {
     b.two_level = b.G > 1;
     b.nb1 = (int)std::max<int64_t>(1, (n + kBinChunk - 1) / kBinChunk);
     b.nb2 = b.two_level ? b.nb1 + b.S1 : 0;
+    b.staged1 = b.S1 <= kMaxStaged;
+    b.staged2 = b.G <= kMaxStaged;
     return b;
 }
 
@@ -297,6 +301,113 @@ __global__ __launch_bounds__(kBinBlock) void k_bin1_scatter(const float* __restr
     }
 }
 
+// Exclusive scan of cnt[0..B) into start[0..B] by the first wavefront.
+__device__ __forceinline__ void wave_scan_lds(const unsigned* __restrict__ cnt, unsigned* __restrict__ start, int B) {
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    unsigned carry = 0;
+    for (int base = 0; base < B; base += 64) {
+        const unsigned v = base + lane < B ? cnt[base + lane] : 0u;
+        unsigned incl = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned u = __shfl(incl, lane - d, 64);
+            if (lane >= d) incl += u;
+        }
+        if (base + lane < B) start[base + lane] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) start[B] = carry;
+}
+
+// The bucket of sorted position p: the last b with start[b] <= p.
+__device__ __forceinline__ int bucket_of(const unsigned* __restrict__ start, int B, unsigned p) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (start[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Staged scatter (both levels): the workgroup's records are first sorted by
+// bucket in LDS, then written so that consecutive threads write consecutive
+// addresses of a bucket's run.  LDS: 3 B + 1 counters, then the chunk's
+// heights, keys (and ids).
+inline size_t staged_lds_bytes(int B, bool ids) {
+    return sizeof(unsigned) * (3 * (size_t)B + 1) + (size_t)kBinChunk * (ids ? 12 : 8);
+}
+
+template <bool IDS>
+__device__ __forceinline__ void staged_write(unsigned* s_mem, int B, const float (&z)[kBinPPT],
+                                             const unsigned (&key)[kBinPPT], const int (&id)[kBinPPT],
+                                             const int (&bk)[kBinPPT], const unsigned (&rank)[kBinPPT],
+                                             float* __restrict__ oz, unsigned* __restrict__ okey,
+                                             int* __restrict__ oid) {
+    unsigned* s_cnt = s_mem;
+    unsigned* s_start = s_cnt + B;          // B + 1
+    unsigned* s_gb = s_start + B + 1;       // global start of this workgroup's run of each bucket
+    float* s_z = (float*)(s_gb + B);
+    unsigned* s_key = (unsigned*)(s_z + kBinChunk);
+    int* s_id = (int*)(s_key + kBinChunk);
+    wave_scan_lds(s_cnt, s_start, B);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBinPPT; ++j) {
+        if (bk[j] < 0) continue;
+        const unsigned p = s_start[bk[j]] + rank[j];
+        s_z[p] = z[j];
+        s_key[p] = key[j];
+        if (IDS) s_id[p] = id[j];
+    }
+    __syncthreads();
+    const unsigned total = s_start[B];
+    for (unsigned p = threadIdx.x; p < total; p += kBinBlock) {
+        const int b = bucket_of(s_start, B, p);
+        const unsigned pos = s_gb[b] + (p - s_start[b]);
+        oz[pos] = s_z[p];
+        okey[pos] = s_key[p];
+        if (IDS) oid[pos] = s_id[p];
+    }
+}
+
+template <bool IDS, bool FINAL>
+__global__ __launch_bounds__(kBinBlock) void k_bin1_scatter_staged(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                                   int G, int S1, int CT, int nb1,
+                                                                   const unsigned* __restrict__ cnt1,
+                                                                   const unsigned* __restrict__ off1,
+                                                                   float* __restrict__ oz, unsigned* __restrict__ okey,
+                                                                   int* __restrict__ oid) {
+    extern __shared__ unsigned s_mem[];
+    unsigned* s_cnt = s_mem;
+    unsigned* s_gb = s_cnt + 2 * S1 + 1;
+    for (int t = threadIdx.x; t < S1; t += kBinBlock) {
+        s_cnt[t] = 0;
+        s_gb[t] = off1[t] + cnt1[(int64_t)t * nb1 + blockIdx.x];
+    }
+    __syncthreads();
+    float z[kBinPPT];
+    unsigned key[kBinPPT], rank[kBinPPT];
+    int id[kBinPPT], bk[kBinPPT];
+    const int64_t b0 = (int64_t)blockIdx.x * kBinChunk;
+#pragma unroll
+    for (int j = 0; j < kBinPPT; ++j) {
+        const int64_t i = b0 + (int64_t)j * kBinBlock + threadIdx.x;
+        int tile;
+        unsigned cell;
+        bk[j] = -1;
+        id[j] = (int)i;
+        if (i < n && bin_point(xyz, i, g, tile, cell, z[j])) {
+            const int st = tile / G;
+            bk[j] = st;
+            key[j] = FINAL ? cell : (unsigned)(tile - st * G) * (unsigned)CT + cell;
+            rank[j] = atomicAdd(&s_cnt[st], 1u);
+        }
+    }
+    __syncthreads();
+    staged_write<IDS>(s_mem, S1, z, key, id, bk, rank, oz, okey, oid);
+}
+
 // Level-2 workgroup q covers records [off1[s] + j kBinChunk, ...) of
 // super-tile s, with cbase[s] <= q = cbase[s] + j < cbase[s+1].
 __device__ __forceinline__ int bin2_super(const unsigned* __restrict__ cbase, int S1, unsigned q) {
@@ -367,6 +478,52 @@ __global__ __launch_bounds__(kBinBlock) void k_bin2_scatter(const float* __restr
         rmeta[pos] = key - l * (unsigned)CT;
         if (IDS) rid[pos] = id1[r];
     }
+}
+
+template <bool IDS>
+__global__ __launch_bounds__(kBinBlock) void k_bin2_scatter_staged(const float* __restrict__ z1,
+                                                                   const unsigned* __restrict__ key1,
+                                                                   const int* __restrict__ id1,
+                                                                   const unsigned* __restrict__ off1,
+                                                                   const unsigned* __restrict__ cbase, int S1, int G,
+                                                                   int CT, int nb2, const unsigned* __restrict__ cnt2,
+                                                                   const unsigned* __restrict__ off,
+                                                                   float* __restrict__ rz, unsigned* __restrict__ rmeta,
+                                                                   int* __restrict__ rid) {
+    extern __shared__ unsigned s_mem[];
+    const unsigned q = blockIdx.x;
+    if (q >= cbase[S1]) return;   // surplus workgroup (uniform)
+    const int st = bin2_super(cbase, S1, q);
+    const unsigned r0 = off1[st] + (q - cbase[st]) * (unsigned)kBinChunk;
+    const unsigned r1 = min(off1[st + 1], r0 + (unsigned)kBinChunk);
+    const int tbase = st * G;
+    unsigned* s_cnt = s_mem;
+    unsigned* s_gb = s_cnt + 2 * G + 1;
+    for (int t = threadIdx.x; t < G; t += kBinBlock) {
+        s_cnt[t] = 0;
+        s_gb[t] = off[tbase + t] + cnt2[(int64_t)t * nb2 + q];
+    }
+    __syncthreads();
+    float z[kBinPPT];
+    unsigned key[kBinPPT], rank[kBinPPT];
+    int id[kBinPPT], bk[kBinPPT];
+#pragma unroll
+    for (int j = 0; j < kBinPPT; ++j) {
+        const unsigned r = r0 + (unsigned)(j * kBinBlock) + threadIdx.x;
+        bk[j] = -1;
+        id[j] = 0;
+        if (r < r1) {
+            const unsigned k = key1[r];
+            const unsigned l = k / (unsigned)CT;
+            z[j] = z1[r];
+            key[j] = k - l * (unsigned)CT;
+            if (IDS) id[j] = id1[r];
+            bk[j] = (int)l;
+            rank[j] = atomicAdd(&s_cnt[l], 1u);
+        }
+    }
+    __syncthreads();
+    staged_write<IDS>(s_mem, G, z, key, id, bk, rank, rz, rmeta, rid);
 }
 
 // ------------------------------------------------------------------ reduce
@@ -883,7 +1040,14 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
         if (!b.two_level) {
             hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.tot1, g.ntiles, w.off, w.cursor);
             PCT_LAUNCH_CHECK();
-            if (ids)
+            const size_t ls = staged_lds_bytes(b.S1, ids);
+            if (b.staged1 && ids)
+                hipLaunchKernelGGL((k_bin1_scatter_staged<true, true>), dim3(b.nb1), dim3(kBinBlock), ls, s, xyz, n, g,
+                                   b.G, b.S1, b.CT, b.nb1, w.cnt1, w.off, w.rz, w.rmeta, w.rid);
+            else if (b.staged1)
+                hipLaunchKernelGGL((k_bin1_scatter_staged<false, true>), dim3(b.nb1), dim3(kBinBlock), ls, s, xyz, n, g,
+                                   b.G, b.S1, b.CT, b.nb1, w.cnt1, w.off, w.rz, w.rmeta, w.rid);
+            else if (ids)
                 hipLaunchKernelGGL((k_bin1_scatter<true, true>), dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G,
                                    b.S1, b.CT, b.nb1, w.cnt1, w.off, w.rz, w.rmeta, w.rid);
             else
@@ -893,7 +1057,14 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
         } else {
             hipLaunchKernelGGL(k_bin1_offsets, dim3(1), dim3(1024), 0, s, w.tot1, b.S1, w.off1, w.cbase);
             PCT_LAUNCH_CHECK();
-            if (ids)
+            const size_t ls = staged_lds_bytes(b.S1, ids);
+            if (b.staged1 && ids)
+                hipLaunchKernelGGL((k_bin1_scatter_staged<true, false>), dim3(b.nb1), dim3(kBinBlock), ls, s, xyz, n,
+                                   g, b.G, b.S1, b.CT, b.nb1, w.cnt1, w.off1, w.z1, w.key1, w.id1);
+            else if (b.staged1)
+                hipLaunchKernelGGL((k_bin1_scatter_staged<false, false>), dim3(b.nb1), dim3(kBinBlock), ls, s, xyz, n,
+                                   g, b.G, b.S1, b.CT, b.nb1, w.cnt1, w.off1, w.z1, w.key1, w.id1);
+            else if (ids)
                 hipLaunchKernelGGL((k_bin1_scatter<true, false>), dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G,
                                    b.S1, b.CT, b.nb1, w.cnt1, w.off1, w.z1, w.key1, w.id1);
             else
@@ -910,7 +1081,14 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
             PCT_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.count, g.ntiles, w.off, w.cursor);
             PCT_LAUNCH_CHECK();
-            if (ids)
+            const size_t ls2 = staged_lds_bytes(b.G, ids);
+            if (b.staged2 && ids)
+                hipLaunchKernelGGL(k_bin2_scatter_staged<true>, dim3(b.nb2), dim3(kBinBlock), ls2, s, w.z1, w.key1,
+                                   w.id1, w.off1, w.cbase, b.S1, b.G, b.CT, b.nb2, w.cnt2, w.off, w.rz, w.rmeta, w.rid);
+            else if (b.staged2)
+                hipLaunchKernelGGL(k_bin2_scatter_staged<false>, dim3(b.nb2), dim3(kBinBlock), ls2, s, w.z1, w.key1,
+                                   w.id1, w.off1, w.cbase, b.S1, b.G, b.CT, b.nb2, w.cnt2, w.off, w.rz, w.rmeta, w.rid);
+            else if (ids)
                 hipLaunchKernelGGL(k_bin2_scatter<true>, dim3(b.nb2), dim3(kBinBlock), l2, s, w.z1, w.key1, w.id1,
                                    w.off1, w.cbase, b.S1, b.G, b.CT, b.nb2, w.cnt2, w.off, w.rz, w.rmeta, w.rid);
             else
