@@ -20,6 +20,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue rate without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def eval_ops_per_cell(R):
+    """Algorithmic FP32/integer operations per cell-slice of the evaluation:
+    Eqs. (1)-(5) with the patch count and validity tests (40), and Eq. (6)
+    in the folded row decomposition of radius R: R column maxima, (R+1)^2
+    products and maxima, 3R row-pass maxima."""
+    return 40 + 4 * R + 2 * (R + 1) ** 2
 METRIC = "points/s tomogram + cells/s traversability (HBM GB/s %peak); batched fwd+bwd vs plain"
 
 
@@ -180,6 +190,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain profile measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
@@ -250,7 +262,18 @@ def main():
     build_bytes = 12 * n + 8 * cells        # read xyz; write e^G, e^C
     eval_gbs = eval_bytes / (ms_eval_kernel * 1e-3) / 1e9
     build_gbs = build_bytes / (ms_build * 1e-3) / 1e9
-    traffic = load_traffic("k_eval", eval_bytes)
+    R = P.pct_kernel_radius(rb, grid["res"])
+    eval_ops = eval_ops_per_cell(R) * cells
+    eval_tops = eval_ops / (ms_eval_kernel * 1e-3) / 1e12
+    traffic = load_traffic("k_eval_strip", eval_bytes)
+    if args.copy_calibration:
+        log("copy calibration: 3 x 1 GiB device copy")
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     out = {
         "metric": METRIC,
         "value": n / (ms_step * 1e-3),
@@ -274,9 +297,12 @@ def main():
                       "extent_and_sync": max(0.0, ms_step - ms_build - ms_eval_full)},
         "build_points_per_s": n / (ms_build * 1e-3),
         "build_alg_gbs": build_gbs,
-        "roofline": {"kernel": "k_eval", "bound": "hbm", "achieved": eval_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": eval_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": eval_bytes},
+        "roofline": {"kernel": "k_eval_strip", "bound": "alu", "achieved": eval_tops, "peak": VALU_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": eval_tops / VALU_PEAK_TOPS, "traffic": traffic,
+                     "alg_ops_per_launch": eval_ops, "ops_per_cell_slice": eval_ops_per_cell(R),
+                     "kernel_ms": ms_eval_kernel,
+                     "hbm": {"alg_bytes_per_launch": eval_bytes, "achieved_gbs": eval_gbs,
+                             "peak_gbs": HBM_PEAK_GBS, "frac": eval_gbs / HBM_PEAK_GBS}},
         "wall_s_timed": wall,
     }
     if not args.no_batched:
