@@ -75,6 +75,13 @@ def rewrite(src):
             break
         e = _balanced(text, i + len(key) - 1)
         expr = text[i + len(key):e - 1]
+        depth = 0
+        for k, ch in enumerate(expr):    # the first argument: threads per workgroup
+            depth += ch == "("
+            depth -= ch == ")"
+            if ch == "," and depth == 0:
+                expr = expr[:k]
+                break
         body = text.find("{", e)
         out.append(text[pos:body + 1])
         out.append(f" ::emu::check_launch_bound((int)({expr}), __func__);")
