@@ -157,6 +157,57 @@ __device__ WinMax window_max(const float* __restrict__ gk, const float* __restri
     return o;
 }
 
+// window_max for the four bilinear corners of a waypoint at once: corners
+// (cx[c], cy[c]) lie in a 2 x 2 block, so their windows share most cells.
+// The union of the windows is walked once in row-major order, computing
+// each cell's c^init once; every cell updates the corners whose window holds
+// it.  Row-major order over the union is row-major order over each corner's
+// window, so each corner gets the same first maximum as window_max.
+__device__ void window_max4(const float* __restrict__ gk, const float* __restrict__ ck, const int (&cx)[4],
+                            const int (&cy)[4], const EvalParams& p, WinMax (&o)[4]) {
+    const int nx = p.nx, ny = p.ny, R = p.R;
+    int xlo = cx[0], xhi = cx[0], ylo = cy[0], yhi = cy[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        xlo = min(xlo, cx[c]);
+        xhi = max(xhi, cx[c]);
+        ylo = min(ylo, cy[c]);
+        yhi = max(yhi, cy[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        o[c] = WinMax{};
+        o[c].v = -INFINITY;
+    }
+    for (int qy = max(0, ylo - R); qy <= min(ny - 1, yhi + R); ++qy) {
+        for (int qx = max(0, xlo - R); qx <= min(nx - 1, xhi + R); ++qx) {
+            bool need = false;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int m = abs(qx - cx[c]), n = abs(qy - cy[c]);
+                need |= m <= R && n <= R && p.K[m][n] > 0.0f;
+            }
+            if (!need) continue;
+            const Cinit q = cinit_at(gk, ck, qx, qy, p);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int m = abs(qx - cx[c]), n = abs(qy - cy[c]);
+                if (m > R || n > R) continue;
+                const float kw = p.K[m][n];
+                if (kw <= 0.0f) continue;
+                const float v = kw * q.ci;
+                if (v > o[c].v) {
+                    o[c].v = v;
+                    o[c].k = kw;
+                    o[c].qx = qx;
+                    o[c].qy = qy;
+                    o[c].q = q;
+                }
+            }
+        }
+    }
+}
+
 // Eq. (1)-(5) adjoint at the maximising cell of a window, for gradient gq
 // of its c^init.
 __device__ void cinit_adjoint(const Cinit& q, long long iq, int nx, float gq, const EvalParams& p, const Sink& s) {
@@ -474,10 +525,14 @@ __global__ __launch_bounds__(kBlock) void k_traj_value_grad(const float* __restr
             const float* ck = ceil + base;
             const long long cs[4] = {b.c00, b.c10, b.c01, b.c11};
             WinMax wm[4];
+            int cx[4], cy[4];
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const long long local = cs[c] - base;
-                wm[c] = window_max(gk, ck, (int)(local % a.nx), (int)(local / a.nx), p);
+                cx[c] = (int)(local % a.nx);
+                cy[c] = (int)(local / a.nx);
             }
+            window_max4(gk, ck, cx, cy, p, wm);
             const float w00 = (1.0f - b.fu) * (1.0f - b.fv), w10 = b.fu * (1.0f - b.fv);
             const float w01 = (1.0f - b.fu) * b.fv, w11 = b.fu * b.fv;
             const float ws[4] = {w00, w10, w01, w11};
