@@ -185,7 +185,13 @@ __device__ __forceinline__ float maxnn(float a, float b) {
 // step number modulo S; the row loop is unrolled S times so that every slot
 // index is a compile-time constant and no row is ever moved between
 // registers.  Step t handles output row y = Y0 - 2 HX + t.
-template <int R>
+// Tap weights known at compile time: weight exactly 1 where a^2 + j^2 <= Q1
+// and exactly 0 where a^2 + j^2 >= Q0 (Q1 < 0 and Q0 = kNoZeroTaps: none
+// known).  1 * c = c and 0 * c = 0 exactly for the finite c^init >= 0, so
+// skipping those multiplies leaves every maximum unchanged.
+constexpr int kNoZeroTaps = 1 << 20;
+
+template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
 __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                 const EvalParams& p, float* __restrict__ cost, const StripGeom& sg,
                                                 int w) {
@@ -292,7 +298,11 @@ __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground
                 for (int a = 0; a <= R; ++a) {
                     float h = 0.0f;
 #pragma unroll
-                    for (int jj = 0; jj <= R; ++jj) h = maxnn(h, p.K[a][jj] * P[jj]);
+                    for (int jj = 0; jj <= R; ++jj) {
+                        const int q = a * a + jj * jj;
+                        if (q <= Q1) h = maxnn(h, P[jj]);                      // weight 1
+                        else if (q < Q0) h = maxnn(h, p.K[a][jj] * P[jj]);     // weight in (0, 1)
+                    }
                     if (a == 0) v = h;
                     else v = maxnn(v, maxnn(__shfl(h, lane - a, 64), __shfl(h, lane + a, 64)));
                 }
@@ -310,12 +320,12 @@ __device__ __forceinline__ int xcd_wave_index() {
     return wb * (kBlock / 64) + (int)(threadIdx.x / 64);
 }
 
-template <int R>
+template <int R, int Q1, int Q0>
 __global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                        const EvalParams p, float* __restrict__ cost, const StripGeom sg) {
     const int w = __builtin_amdgcn_readfirstlane(xcd_wave_index());   // uniform: row logic stays scalar
     if (w >= sg.n_work) return;
-    eval_strip_wave<R>(ground, ceil, p, cost, sg, w);
+    eval_strip_wave<R, Q1, Q0>(ground, ceil, p, cost, sg, w);
 }
 
 // A batch: jobs are (map, robot) pairs with their own parameters, strip
@@ -340,7 +350,7 @@ __device__ __forceinline__ int find_job_work(const EvalJob* __restrict__ jobs, i
     return lo;
 }
 
-template <int R>
+template <int R, int Q1, int Q0>
 __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restrict__ ground,
                                                             const float* __restrict__ ceil,
                                                             const EvalJob* __restrict__ jobs, int n_jobs, int n_work,
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restr
     if (w >= n_work) return;
     const int j = __builtin_amdgcn_readfirstlane(find_job_work(jobs, n_jobs, w));
     const EvalJob& jb = jobs[j];
-    eval_strip_wave<R>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w - jb.work_base);
+    eval_strip_wave<R, Q1, Q0>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w - jb.work_base);
 }
 
 StripGeom strip_geom(const EvalParams& p) {
@@ -364,13 +374,13 @@ StripGeom strip_geom(const EvalParams& p) {
     return g;
 }
 
-template <int R>
+template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
 pct_status launch_eval_strip(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s) {
     const StripGeom sg = strip_geom(p);
     const int waves_per_block = kBlock / 64;
     int blocks = (sg.n_work + waves_per_block - 1) / waves_per_block;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_eval_strip<R>, dim3(blocks), dim3(kBlock), 0, s, ground, ceil, p, cost, sg);
+    hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0>), dim3(blocks), dim3(kBlock), 0, s, ground, ceil, p, cost, sg);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -551,8 +561,33 @@ size_t eval_ws_bytes(int N, int) {
     return align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * W);
 }
 
+// The compiled tap-weight patterns: for radius R >= 2, weight exactly 1 for
+// a^2 + j^2 <= (R-2)^2 and exactly 0 for a^2 + j^2 >= (R+1)^2 (an inflation
+// radius of R-2 cells with a 3-cell margin, as a 0.1 m grid with a 0.4 m
+// smoothing distance gives).  True when p's weights follow it exactly.
+static bool weights_follow_pattern(const EvalParams& p) {
+    const int R = p.R;
+    if (R < 2 || R > 8) return false;
+    const int q1 = (R - 2) * (R - 2), q0 = (R + 1) * (R + 1);
+    for (int a = 0; a <= R; ++a)
+        for (int j = 0; j <= R; ++j) {
+            const int q = a * a + j * j;
+            if (q <= q1 && p.K[a][j] != 1.0f) return false;
+            if (q >= q0 && p.K[a][j] != 0.0f) return false;
+        }
+    return true;
+}
+
 pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s) {
     if (p.rp == 1 && p.R <= 8) {
+        if (weights_follow_pattern(p)) {
+            switch (p.R) {
+#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s);
+                PCT_P(2) PCT_P(3) PCT_P(4) PCT_P(5) PCT_P(6) PCT_P(7) PCT_P(8)
+#undef PCT_P
+                default: break;
+            }
+        }
         switch (p.R) {
 #define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s);
             PCT_S(0) PCT_S(1) PCT_S(2) PCT_S(3) PCT_S(4) PCT_S(5) PCT_S(6) PCT_S(7) PCT_S(8)
@@ -597,6 +632,7 @@ struct JobPlan {
     size_t scratch = 0;      // bytes of slice-test scratch
     int R = -1;
     bool strip = true;       // every job can use the strip kernel with one R
+    bool pattern = true;     // ... and every job's weights follow the compiled pattern
 };
 
 pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots, int n_robots, JobPlan* jp) {
@@ -625,18 +661,19 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
             jp->n_work += jb.sg.n_work;
             if (jp->R < 0) jp->R = jb.p.R;
             if (jb.p.R != jp->R || jb.p.rp != 1 || jb.p.R > 8) jp->strip = false;
+            if (!weights_follow_pattern(jb.p)) jp->pattern = false;
             jp->jobs.push_back(jb);
         }
     return PCT_OK;
 }
 
-template <int R>
+template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
 pct_status launch_jobs_r(const float* ground, const float* ceil, const EvalJob* d_jobs, int n_jobs, int n_work,
                          float* cost, hipStream_t s) {
     int blocks = (n_work + kBlock / 64 - 1) / (kBlock / 64);
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_eval_strip_jobs<R>, dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_jobs, n_jobs, n_work,
-                       cost);
+    hipLaunchKernelGGL((k_eval_strip_jobs<R, Q1, Q0>), dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_jobs, n_jobs,
+                       n_work, cost);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -675,7 +712,12 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
     }
     if (jp.strip) {
         switch (jp.R) {
-#define PCT_J(r) case r: st = launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s); break;
+#define PCT_J(r)                                                                                       \
+    case r:                                                                                            \
+        st = (jp.pattern && r >= 2)                                                                    \
+                 ? launch_jobs_r<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s) \
+                 : launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s);                 \
+        break;
             PCT_J(0) PCT_J(1) PCT_J(2) PCT_J(3) PCT_J(4) PCT_J(5) PCT_J(6) PCT_J(7) PCT_J(8)
 #undef PCT_J
             default: return fail(PCT_ERR_CAPACITY, "inflation radius %d", jp.R);
