@@ -436,45 +436,72 @@ __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, u
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) maxp0[i] = -1;
 }
 
-// Slice-test flags of one cell (all lanes of a wavefront must call it
-// together; lanes without a cell pass active = false).
-__device__ __forceinline__ void simp_flags_cell(const float* __restrict__ ground, const float* __restrict__ cost,
-                                                long long plane, int N, float cB, int W, int* __restrict__ maxp0,
-                                                unsigned* __restrict__ urun, long long cell, bool active) {
+// Slice-test flags of kSimpCells consecutive cells per lane, cells cell0 ..
+// cell0 + nact - 1 (all lanes of a wavefront must call it together; lanes
+// without cells pass nact = 0).  Several cells per lane divide the
+// wavefront reductions and atomics per cell.
+constexpr int kSimpCells = 4;
+
+__device__ __forceinline__ void simp_flags_cells(const float* __restrict__ ground, const float* __restrict__ cost,
+                                                 long long plane, int N, float cB, int W, int* __restrict__ maxp0,
+                                                 unsigned* __restrict__ urun, long long cell0, int nact) {
+    constexpr int CPT = kSimpCells;
     const int lane = threadIdx.x & 63;
-    float ek = active ? ground[cell] : -INFINITY;
-    float ck = active ? cost[cell] : cB;
-    float eprev = -INFINITY;
-    int p0 = 0;
+    float ek[CPT], ck[CPT], eprev[CPT];
+    int p0[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const bool act = c < nact;
+        ek[c] = act ? ground[cell0 + c] : -INFINITY;
+        ck[c] = act ? cost[cell0 + c] : cB;
+        eprev[c] = -INFINITY;
+        p0[c] = 0;
+    }
     for (int k = 0; k < N; ++k) {
-        float ek1 = -INFINITY, ck1 = cB;
-        if (k + 1 < N && active) {
-            ek1 = ground[(long long)(k + 1) * plane + cell];
-            ck1 = cost[(long long)(k + 1) * plane + cell];
+        float ek1[CPT], ck1[CPT];
+        const long long nb = (long long)(k + 1) * plane + cell0;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const bool ld = k + 1 < N && c < nact;
+            ek1[c] = ld ? ground[nb + c] : -INFINITY;
+            ck1[c] = ld ? cost[nb + c] : cB;
         }
-        if (k > 0 && ek != eprev) p0 = k;
-        const bool trav = active && ck < cB;
-        const bool upper = (k == N - 1) || (ek1 > ek) || (ck < ck1);
-        const bool A = trav && upper;
-        const int m = wave_max_i(A ? p0 : -1);
+        int mloc = -1, pminloc = 0x7fffffff;
+        bool runA[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            if (k > 0 && ek[c] != eprev[c]) p0[c] = k;
+            const bool trav = c < nact && ck[c] < cB;
+            const bool upper = (k == N - 1) || (ek1[c] > ek[c]) || (ck[c] < ck1[c]);
+            const bool A = trav && upper;
+            if (A) mloc = max(mloc, p0[c]);
+            runA[c] = A && p0[c] < k;
+            if (runA[c]) pminloc = min(pminloc, p0[c]);
+        }
+        const int m = wave_max_i(mloc);
         if (lane == 0 && m >= 0) atomicMax(&maxp0[k], m);
-        const bool runA = A && p0 < k;
-        if (__ballot(runA)) {
-            const int pmin = wave_min_i(runA ? p0 : 0x7fffffff);
+        if (__ballot(pminloc != 0x7fffffff)) {
+            const int pmin = wave_min_i(pminloc);
             for (int w = pmin / 32; w <= (k - 1) / 32; ++w) {
                 unsigned bits = 0;
                 const int pb = max(pmin, w * 32), pe = min(k, w * 32 + 32);
                 for (int pp = pb; pp < pe; ++pp) {
-                    const float cp = active ? cost[(long long)pp * plane + cell] : 0.0f;
-                    if (runA && pp >= p0 && cp > ck) bits |= 1u << (pp - w * 32);
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        if (runA[c] && pp >= p0[c] && cost[(long long)pp * plane + cell0 + c] > ck[c])
+                            bits |= 1u << (pp - w * 32);
+                    }
                 }
                 bits = wave_or(bits);
                 if (lane == 0 && bits) atomicOr(&urun[(long long)k * W + w], bits);
             }
         }
-        eprev = ek;
-        ek = ek1;
-        ck = ck1;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            eprev[c] = ek[c];
+            ek[c] = ek1[c];
+            ck[c] = ck1[c];
+        }
     }
 }
 
@@ -482,8 +509,10 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__
                                                        const int nx, const int ny, const int N, const float cB,
                                                        const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun) {
     const long long plane = (long long)nx * ny;
-    const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
-    simp_flags_cell(ground, cost, plane, N, cB, W, maxp0, urun, cell < plane ? cell : 0, cell < plane);
+    const long long cell0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * kSimpCells;
+    const long long left = plane - cell0;
+    const int nact = left <= 0 ? 0 : (left < kSimpCells ? (int)left : kSimpCells);
+    simp_flags_cells(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact);
 }
 
 __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
@@ -531,16 +560,20 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restr
                                                             const float* __restrict__ cost,
                                                             const EvalJob* __restrict__ jobs, int n_jobs,
                                                             char* __restrict__ ws) {
-    const long long g = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const int j = __builtin_amdgcn_readfirstlane(find_job_cell(jobs, n_jobs, g - (threadIdx.x & 63)));
+    // global padded cell of this lane's first cell; a wavefront's 64 x kSimpCells
+    // cells never span two jobs (job ranges are padded to that)
+    const long long g = ((long long)blockIdx.x * kBlock + threadIdx.x) * kSimpCells;
+    const int j = __builtin_amdgcn_readfirstlane(
+        find_job_cell(jobs, n_jobs, g - (long long)(threadIdx.x & 63) * kSimpCells));
     const EvalJob& jb = jobs[j];
-    const long long cell = g - jb.cell_base;
-    const bool active = cell >= 0 && cell < jb.p.plane;
+    const long long cell0 = g - jb.cell_base;
+    const long long left = jb.p.plane - cell0;
+    const int nact = (cell0 < 0 || left <= 0) ? 0 : (left < kSimpCells ? (int)left : kSimpCells);
     const int N = jb.p.N, W = (N + 31) / 32;
     int* maxp0 = (int*)(ws + jb.ws_off);
     unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    simp_flags_cell(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
-                    active ? cell : 0, active);
+    simp_flags_cells(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
+                     nact > 0 ? cell0 : 0, nact);
 }
 
 __global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, const char* __restrict__ ws,
@@ -612,7 +645,7 @@ pct_status launch_simplify(const float* ground, const float* cost, const EvalPar
     hipLaunchKernelGGL(k_simp_init, dim3(std::max(1, std::min(1024, (p.N * W + kBlock - 1) / kBlock))), dim3(kBlock), 0, s,
                        maxp0, urun, p.N, W);
     PCT_LAUNCH_CHECK();
-    const long long blocks = (p.plane + kBlock - 1) / kBlock;
+    const long long blocks = (p.plane + (long long)kBlock * kSimpCells - 1) / ((long long)kBlock * kSimpCells);
     hipLaunchKernelGGL(k_simp_flags, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny, p.N, p.cB, W,
                        maxp0, urun);
     PCT_LAUNCH_CHECK();
@@ -656,7 +689,7 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
             jb.cell_base = jp->cells;
             jb.ws_off = (long long)jp->scratch;
             jb.work_base = jp->n_work;
-            jp->cells += (jb.p.plane + 63) / 64 * 64;
+            jp->cells += (jb.p.plane + 64 * kSimpCells - 1) / (64 * kSimpCells) * (64 * kSimpCells);
             jp->scratch += align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * ((N + 31) / 32));
             jp->n_work += jb.sg.n_work;
             if (jp->R < 0) jp->R = jb.p.R;
@@ -733,7 +766,9 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
     if (keep) {
         hipLaunchKernelGGL(k_simp_init_jobs, dim3(n_jobs), dim3(kBlock), 0, s, d_jobs, scratch);
         PCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_simp_flags_jobs, dim3((unsigned)((jp.cells + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL(k_simp_flags_jobs, dim3((unsigned)((jp.cells + (long long)kBlock * kSimpCells - 1) /
+                                                             ((long long)kBlock * kSimpCells))),
+                           dim3(kBlock), 0, s,
                            ground, cost, d_jobs, n_jobs, scratch);
         PCT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_keep_chain_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, s, d_jobs, n_jobs, scratch, keep);
