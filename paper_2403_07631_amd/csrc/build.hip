@@ -560,11 +560,12 @@ __device__ void sweep_cell(float* zs, int* is, int n, int ix, int iy, const Grid
             ++j;
             znext = j < n ? zs[j] : INFINITY;
         }
-        ground[o] = j > 0 ? zs[j - 1] : -INFINITY;
-        ceil[o] = znext;
+        // streaming stores: the grids are far larger than the caches
+        __builtin_nontemporal_store(j > 0 ? zs[j - 1] : -INFINITY, &ground[o]);
+        __builtin_nontemporal_store(znext, &ceil[o]);
         if (IDS) {
-            ag[o] = j > 0 ? is[rs] : -1;
-            ac[o] = j < n ? is[j] : -1;
+            __builtin_nontemporal_store(j > 0 ? is[rs] : -1, &ag[o]);
+            __builtin_nontemporal_store(j < n ? is[j] : -1, &ac[o]);
         }
     }
 }
