@@ -320,6 +320,11 @@ def main():
     ws_b = torch.empty(P.lib().pct_build_workspace_bytes(xyz.shape[0], ctypes.byref(P.grid_struct(grid)),
                                                           ctypes.byref(ext0)), dtype=torch.uint8, device=dev)
 
+    g0, c0, _, _ = P.pct_build_tomogram(xyz, grid, ext0, workspace=ws_b)
+    log("autotuning the evaluation's strip height")
+    tuned_rows, tune_ms = P.pct_autotune_traversability(g0, c0, grid, ext0, rb)
+    del g0, c0
+
     def step():
         ext = P.pct_tomogram_extent(xyz, grid)
         g, c, _, _ = P.pct_build_tomogram(xyz, grid, ext, workspace=ws_b)
@@ -408,6 +413,7 @@ def main():
                      "hbm": {"alg_bytes_per_launch": eval_bytes, "achieved_gbs": eval_gbs,
                              "peak_gbs": HBM_PEAK_GBS, "frac": eval_gbs / HBM_PEAK_GBS}},
         "wall_s_timed": wall,
+        "autotune": {"strip_rows": tuned_rows, "candidates_ms": {str(k): v for k, v in tune_ms.items()}},
     }
     if not args.no_batched:
         del g, c, cost, keep

@@ -176,6 +176,24 @@ pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, c
                                    const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
                                    float* d_cost, uint8_t* d_keep, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Autotuner for pct_eval_traversability.  Times the evaluation of this
+ * map shape for each candidate strip height (the rows of one slice that
+ * one wavefront walks: 32, 64, ... up to the first at or above ny, at most
+ * 1024) and records the fastest; later evaluations in this process of a
+ * map with the same nx, ny, slice count and kernel radius use it.
+ * Synchronous.  d_cost: float32 [N][ny][nx] scratch, overwritten.
+ * h_rows/h_ms: host arrays of n_max entries for the candidates and their
+ * times in ms (nullable); *h_count = the number of candidates;
+ * *h_best_rows = the chosen height, 0 when this robot's evaluation does not
+ * use strips (patch radius above 1 or inflation radius above 8). */
+pct_status pct_autotune_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                       const pct_extent* extent, const pct_robot* h_robot, float* d_cost,
+                                       int32_t* h_best_rows, int32_t* h_rows, float* h_ms, int32_t n_max,
+                                       int32_t* h_count, void* stream);
+
+/* Forgets every height the autotuner recorded (defaults apply again). */
+pct_status pct_autotune_reset(void);
+
 /* ---------------------------------------------------------------------- */
 /* Trajectory cost sampling (Sec. III-E) and adjoints                     */
 

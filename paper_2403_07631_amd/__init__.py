@@ -186,6 +186,28 @@ def pct_eval_traversability(ground, ceil, grid, extent: pct_extent, robots, keep
     return cost, kp
 
 
+def pct_autotune_traversability(ground, ceil, grid, extent, robot, scratch=None):
+    """Tune the evaluation's strip height for this map shape (synchronous).
+    Returns (best_rows, {rows: ms}); best_rows is 0 when the robot's
+    evaluation does not use strips."""
+    g, rb = grid_struct(grid), robot_struct(robot)
+    N = extent.n_slices
+    cost = scratch if scratch is not None else torch.empty((max(N, 1), g.ny, g.nx), dtype=torch.float32,
+                                                           device=ground.device)
+    best, count = C.c_int32(), C.c_int32()
+    rows = (C.c_int32 * 8)()
+    ms = (C.c_float * 8)()
+    _check("pct_autotune_traversability",
+           lib().pct_autotune_traversability(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(rb),
+                                             _ptr(cost), C.byref(best), rows, ms, 8, C.byref(count),
+                                             _stream(ground.device)))
+    return int(best.value), {int(rows[i]): float(ms[i]) for i in range(count.value)}
+
+
+def pct_autotune_reset():
+    _check("pct_autotune_reset", lib().pct_autotune_reset())
+
+
 # --------------------------------------------------------------------- trajectory cost
 
 def _wp(wp, slices):

@@ -309,6 +309,42 @@ pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, c
     return PCT_OK;
 }
 
+pct_status pct_autotune_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                       const pct_extent* extent, const pct_robot* h_robot, float* d_cost,
+                                       int32_t* h_best_rows, int32_t* h_rows, float* h_ms, int32_t n_max,
+                                       int32_t* h_count, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (!h_robot) return fail(PCT_ERR_ARG, "h_robot is null");
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    if (!h_best_rows || !h_count) return fail(PCT_ERR_ARG, "h_best_rows and h_count are required");
+    if (n_max < 0) return fail(PCT_ERR_ARG, "n_max must be >= 0");
+    *h_best_rows = 0;
+    *h_count = 0;
+    const int N = extent->n_slices;
+    if (N == 0) return PCT_OK;
+    if (!d_ground || !d_ceil || !d_cost) return fail(PCT_ERR_ARG, "device pointers are null");
+    EvalParams p;
+    st = make_eval_params(*h_robot, *grid, N, &p);
+    if (st != PCT_OK) return st;
+    int best = 0, count = 0;
+    st = autotune_eval(d_ground, d_ceil, p, d_cost, (hipStream_t)stream, &best, h_rows, h_ms, n_max, &count);
+    if (st != PCT_OK) return st;
+    *h_best_rows = best;
+    *h_count = count;
+    return PCT_OK;
+}
+
+pct_status pct_autotune_reset(void) {
+    clear_error();
+    autotune_reset();
+    return PCT_OK;
+}
+
 namespace {
 
 pct_status check_sampling(const pct_grid* grid, const pct_extent* extent, const pct_robot* robot, int32_t T, int32_t W,

@@ -9,6 +9,8 @@
 //   c^T(x, y) = max_a max(V_a(x-a, y), V_a(x+a, y))             (row pass)
 // Each product K * c is the same FP32 multiply as in the direct 2-D window
 // and max is exact, so the result equals the direct FP32 window max.
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "pct_internal.h"
@@ -362,21 +364,45 @@ __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restr
     eval_strip_wave<R, Q1, Q0>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w - jb.work_base);
 }
 
-StripGeom strip_geom(const EvalParams& p) {
+// Strip heights chosen by the autotuner, per map shape and kernel radius.
+struct TuneKey {
+    int nx, ny, N, R;
+    bool operator<(const TuneKey& o) const {
+        return nx != o.nx ? nx < o.nx : ny != o.ny ? ny < o.ny : N != o.N ? N < o.N : R < o.R;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_rows;
+
+int tuned_rows(const EvalParams& p) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_rows.find(TuneKey{p.nx, p.ny, p.N, p.R});
+    return it == g_tune_rows.end() ? 0 : it->second;
+}
+
+// rows = 0: the tuned height if one is recorded, else the default (256,
+// halved while the strips give fewer than 16384 wavefronts, down to 32).
+StripGeom strip_geom(const EvalParams& p, int rows = 0) {
     const int outw = 64 - 2 * (p.R + 2);
     StripGeom g{};
     g.n_sx = (p.nx + outw - 1) / outw;
-    g.rows = kStripRows;
-    auto work = [&](int rows) { return (long long)p.N * g.n_sx * ((p.ny + rows - 1) / rows); };
-    while (g.rows > 32 && work(g.rows) < 16384) g.rows /= 2;
+    auto work = [&](int r) { return (long long)p.N * g.n_sx * ((p.ny + r - 1) / r); };
+    if (rows <= 0) rows = tuned_rows(p);
+    if (rows > 0) {
+        g.rows = rows;
+    } else {
+        g.rows = kStripRows;
+        while (g.rows > 32 && work(g.rows) < 16384) g.rows /= 2;
+    }
     g.n_sy = (p.ny + g.rows - 1) / g.rows;
     g.n_work = (int)work(g.rows);
     return g;
 }
 
 template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
-pct_status launch_eval_strip(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s) {
-    const StripGeom sg = strip_geom(p);
+pct_status launch_eval_strip(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                             int rows = 0) {
+    const StripGeom sg = strip_geom(p, rows);
     const int waves_per_block = kBlock / 64;
     int blocks = (sg.n_work + waves_per_block - 1) / waves_per_block;
     blocks = (blocks + 7) / 8 * 8;
@@ -611,18 +637,19 @@ static bool weights_follow_pattern(const EvalParams& p) {
     return true;
 }
 
-pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s) {
+pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                       int rows) {
     if (p.rp == 1 && p.R <= 8) {
         if (weights_follow_pattern(p)) {
             switch (p.R) {
-#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s);
+#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s, rows);
                 PCT_P(2) PCT_P(3) PCT_P(4) PCT_P(5) PCT_P(6) PCT_P(7) PCT_P(8)
 #undef PCT_P
                 default: break;
             }
         }
         switch (p.R) {
-#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s);
+#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s, rows);
             PCT_S(0) PCT_S(1) PCT_S(2) PCT_S(3) PCT_S(4) PCT_S(5) PCT_S(6) PCT_S(7) PCT_S(8)
 #undef PCT_S
             default: break;
@@ -635,6 +662,59 @@ pct_status launch_eval(const float* ground, const float* ceil, const EvalParams&
 #undef PCT_R
         default: return fail(PCT_ERR_CAPACITY, "inflation radius %d exceeds %d", p.R, PCT_MAX_KERNEL_RADIUS);
     }
+}
+
+// Times the strip evaluation of this map shape for each candidate strip
+// height and records the fastest in the tuning table (synchronous).
+pct_status autotune_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                         int* best_rows, int* cand_rows, float* cand_ms, int n_max, int* n_cand) {
+    *best_rows = 0;
+    *n_cand = 0;
+    if (!(p.rp == 1 && p.R <= 8)) return PCT_OK;   // the tiled kernel has no strip height
+    int rows[8], nc = 0;
+    for (int r = 32; r <= 1024 && nc < 8; r *= 2) {
+        rows[nc++] = r;
+        if (r >= p.ny) break;
+    }
+    hipEvent_t e0, e1;
+    PCT_HIP(hipEventCreate(&e0));
+    PCT_HIP(hipEventCreate(&e1));
+    float best = INFINITY;
+    pct_status st = PCT_OK;
+    for (int i = 0; i < nc && st == PCT_OK; ++i) {
+        st = launch_eval(ground, ceil, p, cost, s, rows[i]);   // warm-up
+        if (st != PCT_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PCT_ERR_DEVICE, "hipEventRecord failed"); break; }
+        for (int rep = 0; rep < 3 && st == PCT_OK; ++rep) st = launch_eval(ground, ceil, p, cost, s, rows[i]);
+        if (st != PCT_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(PCT_ERR_DEVICE, "timing the candidates failed");
+            break;
+        }
+        ms /= 3.0f;
+        if (i < n_max) {
+            if (cand_rows) cand_rows[i] = rows[i];
+            if (cand_ms) cand_ms[i] = ms;
+        }
+        if (ms < best) {
+            best = ms;
+            *best_rows = rows[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PCT_OK) return st;
+    *n_cand = nc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_rows[TuneKey{p.nx, p.ny, p.N, p.R}] = *best_rows;
+    return PCT_OK;
+}
+
+void autotune_reset() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_rows.clear();
 }
 
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep, void* ws,

@@ -119,8 +119,11 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
                         hipStream_t s);
 
 size_t eval_ws_bytes(int N, int n_robots);
-pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost,
-                       hipStream_t s);
+pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                       int rows = 0);
+pct_status autotune_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                         int* best_rows, int* cand_rows, float* cand_ms, int n_max, int* n_cand);
+void autotune_reset();
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
                            void* ws, hipStream_t s);
 

@@ -248,6 +248,31 @@ def case_two_level():
     tomogram_case(pts, grid, True, "two-level binning")
 
 
+def case_autotune():
+    """The autotuner tries every strip height; evaluations after tuning are
+    bit-identical to those before."""
+    sc = scenes.multistorey_scene(34, 4.9, 3.3, 60_000, n_floors=2)
+    pts = np.ascontiguousarray(sc.points, np.float32)
+    xb = Buf.of(pts)
+    e = extent(xb, len(pts), sc.grid)
+    G, Cc, _, _ = build(xb, len(pts), sc.grid, e, False)
+    r = robot()
+    before = evaluate(G, Cc, sc.grid, e, [r])[0].get(e.n_slices * sc.grid["nx"] * sc.grid["ny"], np.float32)
+    g = grid_s(sc.grid)
+    rb = robot_s(r)
+    scratch = Buf(4 * e.n_slices * sc.grid["nx"] * sc.grid["ny"])
+    best, count = C.c_int32(), C.c_int32()
+    rows, ms = (C.c_int32 * 8)(), (C.c_float * 8)()
+    check("autotune", L.pct_autotune_traversability(P(G), P(Cc), C.byref(g), C.byref(e), C.byref(rb), P(scratch),
+                                                    C.byref(best), rows, ms, 8, C.byref(count), None))
+    cands = [rows[i] for i in range(count.value)]
+    assert count.value >= 2 and best.value in cands, (best.value, cands)
+    after = evaluate(G, Cc, sc.grid, e, [r])[0].get(e.n_slices * sc.grid["nx"] * sc.grid["ny"], np.float32)
+    np.testing.assert_array_equal(bits(after), bits(before))
+    check("reset", L.pct_autotune_reset())
+    say(f"autotune: candidates {cands}, chose {best.value}; evaluation unchanged")
+
+
 # ----------------------------------------------------------------- batches
 
 def make_batch(seed, n_items, side_hi=160, pts_hi=120_000, extra_empty=True):

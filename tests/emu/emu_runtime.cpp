@@ -7,6 +7,7 @@
 #include <sys/mman.h>
 #include <ucontext.h>
 
+#include <chrono>
 #include <map>
 #include <vector>
 
@@ -353,6 +354,29 @@ hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute attr, int value) 
     if (attr != hipFuncAttributeMaxDynamicSharedMemorySize || value < 0 || (size_t)value > emu::kMaxLds)
         return hipErrorInvalidValue;
     emu::g_lds_limit[f] = (size_t)value;
+    return hipSuccess;
+}
+
+// Events: launches run to completion when issued, so an event records the
+// host clock at the time it is recorded.
+struct emu_event {
+    std::chrono::steady_clock::time_point t;
+};
+hipError_t hipEventCreate(hipEvent_t* e) {
+    *e = new emu_event{std::chrono::steady_clock::now()};
+    return hipSuccess;
+}
+hipError_t hipEventDestroy(hipEvent_t e) {
+    delete e;
+    return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
+    e->t = std::chrono::steady_clock::now();
+    return hipSuccess;
+}
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+    *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();
     return hipSuccess;
 }
 

@@ -58,6 +58,12 @@ hipError_t hipStreamSynchronize(hipStream_t s);
 hipError_t hipGetLastError();
 const char* hipGetErrorString(hipError_t e);
 hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute attr, int value);
+typedef struct emu_event* hipEvent_t;
+hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventDestroy(hipEvent_t e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 
 namespace emu {
 

@@ -46,7 +46,7 @@ def run_cases(cases, order="fwd", timeout=900):
     (["crop", "dense", "multirobot_large"], "rand"),
     (["many_chunks", "two_level"], "fwd"),
     (["batch", "batch_resident", "batch_mixed_radius"], "rand"),
-    (["traj_value_grad"], "fwd"),
+    (["traj_value_grad", "autotune"], "fwd"),
 ])
 def test_kernels_on_cpu(emu_lib, cases, order):
     run_cases(cases, order)

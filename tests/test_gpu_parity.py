@@ -213,6 +213,25 @@ def test_eval_many_robots_match_single(P, oracle_lib):
         np.testing.assert_array_equal(keep[i], k1[0])
 
 
+def test_autotune_keeps_results(P):
+    """Tuning the strip height changes no value of the evaluation."""
+    import torch
+    sc = crop_scene(seed=24, n=300_000)
+    xyz = torch.from_numpy(sc.points).cuda()
+    ext = P.pct_tomogram_extent(xyz, sc.grid)
+    g, c, _, _ = P.pct_build_tomogram(xyz, sc.grid, ext)
+    rb = P.robot_struct(robot())
+    say("autotune")
+    before, kb = P.pct_eval_traversability(g, c, sc.grid, ext, [rb])
+    best, cands = P.pct_autotune_traversability(g, c, sc.grid, ext, rb)
+    after, ka = P.pct_eval_traversability(g, c, sc.grid, ext, [rb])
+    torch.cuda.synchronize()
+    P.pct_autotune_reset()
+    assert best in cands and len(cands) >= 3
+    np.testing.assert_array_equal(bits(after.cpu().numpy()), bits(before.cpu().numpy()))
+    np.testing.assert_array_equal(ka.cpu().numpy(), kb.cpu().numpy())
+
+
 # --------------------------------------------------------------- full size
 
 
