@@ -103,7 +103,8 @@ pct_status pct_robot_from_physical(float min_interval, float nominal_height, flo
 pct_status pct_validate_grid(const pct_grid* grid);
 
 /* Host only.  Checks a robot at resolution res: finite parameters,
- * c_barrier > 0, d_sm > res (the margin of Eq. (6) must be wider than a
+ * c_barrier > 0, theta_b, theta_s > 0 with theta_b * 2 res finite in
+ * single precision, d_sm > res (the margin of Eq. (6) must be wider than a
  * cell), 1 <= patch_radius <= 4, kernel radius <= 16. */
 pct_status pct_validate_robot(const pct_robot* robot, float res);
 

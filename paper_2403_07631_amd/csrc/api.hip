@@ -70,6 +70,9 @@ pct_status check_robot(const pct_robot* r, float res) {
         if (!finite_f(x)) return fail(PCT_ERR_ARG, "robot parameters must be finite");
     if (!(r->c_barrier > 0.0f)) return fail(PCT_ERR_ARG, "c_barrier must be > 0");
     if (!(r->theta_b > 0.0f) || !(r->theta_s > 0.0f)) return fail(PCT_ERR_ARG, "theta_b and theta_s must be > 0");
+    // the step threshold theta_b * 2r is compared in single precision
+    if (!finite_f((float)((double)r->theta_b * 2.0 * (double)res)))
+        return fail(PCT_ERR_ARG, "theta_b * 2 res overflows single precision");
     if (r->theta_p < 0.0f) return fail(PCT_ERR_ARG, "theta_p must be >= 0");
     if (r->alpha_d < 0.0f || r->alpha_b < 0.0f || r->alpha_s < 0.0f) return fail(PCT_ERR_ARG, "scaling factors must be >= 0");
     if (r->d_inf < 0.0f) return fail(PCT_ERR_ARG, "d_inf must be >= 0");

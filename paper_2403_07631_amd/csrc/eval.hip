@@ -149,14 +149,16 @@ __global__ __launch_bounds__(kBlock) void k_eval(const float* __restrict__ groun
 // Per element the arithmetic is the same sequence of FP32 operations as in
 // the tiled kernel above, so both give identical bits.
 
+// bound_ctrl: the edge lane (no source lane) reads 0, so no old value has
+// to be copied into the destination first.
 __device__ __forceinline__ float from_prev(float v) {   // lane i receives lane i-1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_next(float v) {   // lane i receives lane i+1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
-__device__ __forceinline__ int from_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int from_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int from_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int from_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
 
 #ifndef PCT_EVAL_PREFETCH
 #define PCT_EVAL_PREFETCH 4
@@ -256,13 +258,18 @@ __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground
                 const float g3 = gS[ph], g2 = gS[(ph + S - 1) % S], g1 = gS[(ph + S - 2) % S],
                             g0 = gS[(ph + S - 3) % S];   // rows y+R+2, y+R+1, y+R, y+R-1
 
+                // Ground values are finite or -inf.  A difference of two
+                // such values is finite only when both are finite (else it
+                // is +-inf or NaN), so a test that fails on inf and NaN
+                // (s2 < Ts2, max|d| <= Tb with Tb finite) already carries
+                // the finiteness of the four stencil neighbours.
+
                 // gentle flag of row y+R+1
                 {
                     const float Gc = g2, Gd = g1, Gu = g3;
                     const float Gl = from_prev(Gc), Gr = from_next(Gc);
-                    const bool ok5 = isfinite(Gc) & isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
                     const float s2 = sumsq(Gr - Gl, Gu - Gd);
-                    fS[ph] = (ok5 & (s2 < p.Ts2)) ? 1 : 0;
+                    fS[ph] = (isfinite(Gc) & (s2 < p.Ts2)) ? 1 : 0;
                 }
                 const int f2 = fS[ph], f1 = fS[(ph + S - 1) % S], f0 = fS[(ph + S - 2) % S];  // rows y+R+1, y+R, y+R-1
 
@@ -274,14 +281,14 @@ __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground
                     const int cnt = colsum + from_prev_i(colsum) + from_next_i(colsum) - f1;
                     const float dI = cIn - G;
                     const float cI = dI < p.d_min ? p.cB : fmaxf(0.0f, p.alpha_d * (p.d_ref - dI));
-                    const bool v4 = isfinite(Gl) & isfinite(Gr) & isfinite(Gd) & isfinite(Gu);
                     const float dx = Gr - Gl, dy = Gu - Gd;
                     const float s2 = sumsq(dx, dy);
                     const float c_gentle = p.As * s2;
                     const float c_edge = p.Ab * maxnn(dx * dx, dy * dy);
                     const float c_step = cnt > p.kp ? c_edge : p.cB;
                     float cG = s2 < p.Ts2 ? c_gentle : c_step;
-                    const bool passable = v4 & !(maxnn(fabsf(dx), fabsf(dy)) > p.Tb);
+                    // |dx|, |dy| >= 0 or NaN (positive, so above +inf in maxnn's order)
+                    const bool passable = maxnn(fabsf(dx), fabsf(dy)) <= p.Tb;
                     cG = passable ? cG : p.cB;
                     float ci = isfinite(G) ? fminf(p.cB, cI + cG) : p.cB;
                     cS[ph] = crow ? ci : 0.0f;

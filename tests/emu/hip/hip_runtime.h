@@ -130,9 +130,11 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
     return emu::from_bits<T>(emu::wave_op(emu::OP_SHFL_XOR, emu::to_bits(v), mask, 0));
 }
 inline unsigned long long __ballot(int pred) { return emu::wave_op(emu::OP_BALLOT, pred ? 1u : 0u, 0, 0); }
+// Lanes whose source lane is outside the wavefront or inactive get `old`,
+// or 0 with bound_ctrl.
 inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
-    if (row_mask != 0xf || bank_mask != 0xf || bound_ctrl) __builtin_trap();
-    return emu::from_bits<int>(emu::wave_op(emu::OP_DPP, emu::to_bits(src), ctrl, emu::to_bits(old)));
+    if (row_mask != 0xf || bank_mask != 0xf) __builtin_trap();
+    return emu::from_bits<int>(emu::wave_op(emu::OP_DPP, emu::to_bits(src), ctrl, emu::to_bits(bound_ctrl ? 0 : old)));
 }
 inline int emu_readfirstlane(int v) { return emu::from_bits<int>(emu::wave_op(emu::OP_READFIRSTLANE, emu::to_bits(v), 0, 0)); }
 #define __builtin_amdgcn_update_dpp emu_update_dpp

@@ -72,6 +72,12 @@ def test_robot_validation(P):
         with pytest.raises(P.PctError) as e:
             P.pct_validate_robot(rr, 0.1)
         assert e.value.status == code, bad
+    # the step threshold theta_b * 2 res must stay finite in single precision
+    rr = dict(r, d_inf=0.0, d_sm=5.0)
+    P.pct_validate_robot(dict(rr, theta_b=1e37), 4.0)
+    with pytest.raises(P.PctError) as e:
+        P.pct_validate_robot(dict(rr, theta_b=3e38), 4.0)
+    assert e.value.status == P.PCT_ERR_ARG
 
 
 @pytest.mark.parametrize("d_inf,d_sm,res", [(0.3, 0.4, 0.1), (0.2, 0.4, 0.1), (0.0, 0.15, 0.1),
