@@ -337,6 +337,51 @@ pct_status pct_trajectory_cost_multi(const float* d_ground, const float* d_ceil,
                                      float* d_f, float* d_gwp, float* d_gground, float* d_gceil, int64_t n_points,
                                      float* d_gz, int32_t flags, void* d_ws, size_t ws_bytes, void* stream);
 
+/* ---- path search through the slices (Sec. III-D) ----
+ * The graph of the section: nodes are the cells of n_layers chosen slices
+ * (normally those the slice test keeps, in increasing order); a node links
+ * to its eight planar neighbours on its layer.  Moving onto node v costs
+ * c^N(v) + step length (1 or sqrt 2, in cells), where c^N is the least c^T
+ * over v and the adjacent layers whose ground elevation at the cell is equal
+ * (the same point in space); nodes with c^N >= c^B cannot be entered.  A
+ * node whose adjacent layer has the same ground and a strictly lower c^T is
+ * a gateway to it (no cost), upwards and downwards.
+ * The library computes every node's least path cost from the start (the
+ * cost an A* search with the diagonal-distance heuristic ends with) and
+ * reads a least-cost path back from it.  Distances are FP64: each edge adds
+ * (double)c^N + step in one rounding each, so the result is the least
+ * rounded path sum, independent of the order of the parallel work. */
+
+/* Workspace bytes for pct_plan_distance / pct_plan_path on an nx x ny map
+ * with n_layers layers. */
+size_t pct_plan_workspace_bytes(int32_t nx, int32_t ny, int32_t n_layers);
+
+/* Distances from the start node (sx, sy, layer s_layer) to every node.
+ * d_cost, d_ground: float32 [N][ny][nx] (c^T of one robot, e^G); c^B is
+ * h_robot->c_barrier.  h_layers: host [n_layers], strictly increasing slice
+ * indices in [0, N).  d_dist: float64 [n_layers][ny][nx], overwritten
+ * (+inf: unreachable).  The workspace keeps the node costs and gateways for
+ * pct_plan_path.  Synchronous (one host read-back per round of tiles);
+ * *h_rounds (nullable) receives the round count, *h_tiles (nullable) the
+ * tiles processed.  The start may itself be a barrier node. */
+pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const pct_grid* grid,
+                             const pct_extent* extent, const pct_robot* h_robot, const int32_t* h_layers,
+                             int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double* d_dist, void* d_ws,
+                             size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream);
+
+/* A least-cost path from the start to the goal (gx, gy, layer g_layer),
+ * read back from d_dist of the preceding pct_plan_distance call with the
+ * same workspace: from the goal, the first predecessor whose distance plus
+ * the edge cost equals the node's (gateway from below, gateway from above,
+ * then the planar neighbours in row-major order of (dy, dx)), up to the
+ * start.  d_path: int32 [max_len][3] (x, y, slice index), start first.
+ * *h_len = node count, 0 if the goal is unreachable.  PCT_ERR_CAPACITY if
+ * the path has more than max_len nodes, PCT_ERR_ARG if d_dist is not a
+ * distance field of this graph.  Synchronous. */
+pct_status pct_plan_path(const double* d_dist, const pct_grid* grid, int32_t n_layers, int32_t sx, int32_t sy,
+                         int32_t s_layer, int32_t gx, int32_t gy, int32_t g_layer, int32_t* d_path, int32_t max_len,
+                         int32_t* h_len, void* d_ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

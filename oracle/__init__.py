@@ -78,6 +78,11 @@ def lib():
                                        C.c_double, u8p]
         L.o_simplify_check.restype = C.c_int
         _register_grad(L)
+        L.o_plan.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, f64p]
+        L.o_plan.restype = C.c_int64
+        L.o_plan_path.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double, f64p, C.c_int, C.c_int,
+                                  C.c_int, C.c_int, C.c_int, C.c_int, i32p, C.c_int]
+        L.o_plan_path.restype = C.c_int
         _lib = L
     return _lib
 
@@ -360,3 +365,37 @@ def eval_signature(eG, eC, res, robot):
     lib().o_eval_signature(_p(eG, C.c_float), _p(eC, C.c_float), N, nx, ny, float(np.float32(res)), C.byref(rb),
                            _p(sig, C.c_int32))
     return sig
+
+
+# ---------------------------------------------------------------------------
+# path search through the slices (Sec. III-D)
+
+def plan(cT, eG, c_barrier, start):
+    """Distances [L, ny, nx] (FP64, +inf unreachable) from ``start`` = (x, y,
+    layer) over the layers given as FP32 c^T and e^G arrays [L, ny, nx]."""
+    cT, eG = _f32(cT), _f32(eG)
+    L, ny, nx = cT.shape
+    dist = np.empty((L, ny, nx), np.float64)
+    n = lib().o_plan(_p(cT, C.c_float), _p(eG, C.c_float), L, nx, ny, float(np.float32(c_barrier)),
+                     int(start[0]), int(start[1]), int(start[2]), _p(dist, C.c_double))
+    if n < 0:
+        raise ValueError("bad start node")
+    return dist
+
+
+def plan_path(cT, eG, c_barrier, dist, start, goal, max_len=None):
+    """(x, y, layer) rows of the least-cost path from start to goal read
+    back from ``dist``; None if the goal is unreachable."""
+    cT, eG = _f32(cT), _f32(eG)
+    dist = np.ascontiguousarray(dist, np.float64)
+    L, ny, nx = cT.shape
+    max_len = max_len or L * nx * ny
+    path = np.empty((max_len, 3), np.int32)
+    n = lib().o_plan_path(_p(cT, C.c_float), _p(eG, C.c_float), L, nx, ny, float(np.float32(c_barrier)),
+                          _p(dist, C.c_double), int(start[0]), int(start[1]), int(start[2]), int(goal[0]),
+                          int(goal[1]), int(goal[2]), _p(path, C.c_int32), int(max_len))
+    if n == -2:
+        raise ValueError("path longer than max_len")
+    if n < 0:
+        raise ValueError("bad node or not a distance field")
+    return None if n == 0 else path[:n].copy()

@@ -829,3 +829,190 @@ int o_eval_signature(const float* eG, const float* eC, int N, int nx, int ny, do
     free(cells);
     return R;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III-D: path search through the tomogram slices.
+ *
+ * The search runs on L layers (the slices kept by the simplification, in
+ * increasing order), given as c^T and e^G arrays [L][ny][nx] in FP32.
+ * The graph, as the section describes it:
+ *   - a node is a cell (x, y) of a layer l; it links to its eight planar
+ *     neighbours on the same layer;
+ *   - the layers directly above and below are checked at the same cell: a
+ *     layer whose ground elevation is equal is the same point in space, and
+ *     the node cost c^N is the least c^T among the node and those layers;
+ *   - moving onto a node v costs c^N(v) plus the length of the step; a node
+ *     with c^N = c^B cannot be entered;
+ *   - if the layer above has the same ground and a strictly lower c^T, the
+ *     node is a gateway to it (moving up costs nothing: it is the same point);
+ *     the same holds downwards.
+ * Readings where the section is silent: the step length is measured in
+ * cells (1 straight, sqrt 2 diagonal, the planar Euclidean distance; the
+ * diagonal-distance heuristic uses the same unit); diagonal steps need no free
+ * orthogonal neighbours; the start node may itself be a barrier.
+ * A* with the diagonal-distance heuristic (admissible and consistent here,
+ * since every step costs at least its length) finds a least-cost path; its
+ * cost is the shortest-path distance, which this function computes for every
+ * node by Dijkstra's algorithm.  Distances are FP64 sums, each edge cost
+ * (double)c^N + step length, added to the distance of its tail; unreachable
+ * nodes get +inf. */
+
+static double o_node_cost(const float* cT, const float* eG, int L, int64_t plane, int l, int64_t c) {
+    double cn = cT[l * plane + c];
+    if (l + 1 < L && eG[(l + 1) * plane + c] == eG[l * plane + c] && cT[(l + 1) * plane + c] < cn)
+        cn = cT[(l + 1) * plane + c];
+    if (l > 0 && eG[(l - 1) * plane + c] == eG[l * plane + c] && cT[(l - 1) * plane + c] < cn)
+        cn = cT[(l - 1) * plane + c];
+    return cn;
+}
+
+/* gateway from layer l to layer m = l +- 1 at cell c */
+static int o_gateway(const float* cT, const float* eG, int L, int64_t plane, int l, int m, int64_t c) {
+    if (m < 0 || m >= L) return 0;
+    return eG[m * plane + c] == eG[l * plane + c] && cT[m * plane + c] < cT[l * plane + c];
+}
+
+typedef struct {
+    double d;
+    int64_t v;
+} o_hitem;
+
+static void o_heap_push(o_hitem* h, int64_t* n, double d, int64_t v) {
+    int64_t i = (*n)++;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d <= d) break;
+        h[i] = h[p];
+        i = p;
+    }
+    h[i].d = d;
+    h[i].v = v;
+}
+
+static o_hitem o_heap_pop(o_hitem* h, int64_t* n) {
+    o_hitem top = h[0], last = h[--(*n)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t a = 2 * i + 1;
+        if (a >= *n) break;
+        if (a + 1 < *n && h[a + 1].d < h[a].d) ++a;
+        if (h[a].d >= last.d) break;
+        h[i] = h[a];
+        i = a;
+    }
+    if (*n > 0) h[i] = last;
+    return top;
+}
+
+static const int o_dx8[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+static const int o_dy8[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+
+/* Returns the number of nodes settled, or -1 on a bad start / no memory. */
+int64_t o_plan(const float* cT, const float* eG, int L, int nx, int ny, double cB, int sx, int sy, int sl,
+               double* dist) {
+    const int64_t plane = (int64_t)nx * ny, nn = (int64_t)L * plane;
+    if (sx < 0 || sy < 0 || sl < 0 || sx >= nx || sy >= ny || sl >= L) return -1;
+    const double diag = sqrt(2.0);
+    for (int64_t v = 0; v < nn; ++v) dist[v] = INFINITY;
+    /* each node enters the heap at most once per in-edge: 10 per node */
+    o_hitem* h = (o_hitem*)malloc(sizeof(o_hitem) * (size_t)(10 * nn + 1));
+    uint8_t* done = (uint8_t*)calloc((size_t)nn, 1);
+    if (!h || !done) {
+        free(h);
+        free(done);
+        return -1;
+    }
+    int64_t n = 0, settled = 0;
+    const int64_t s = (int64_t)sl * plane + (int64_t)sy * nx + sx;
+    dist[s] = 0.0;
+    o_heap_push(h, &n, 0.0, s);
+    while (n > 0) {
+        o_hitem it = o_heap_pop(h, &n);
+        const int64_t u = it.v;
+        if (done[u]) continue;
+        done[u] = 1;
+        ++settled;
+        const int l = (int)(u / plane);
+        const int64_t c = u % plane;
+        const int x = (int)(c % nx), y = (int)(c / nx);
+        for (int e = 0; e < 8; ++e) {
+            const int x2 = x + o_dx8[e], y2 = y + o_dy8[e];
+            if (x2 < 0 || y2 < 0 || x2 >= nx || y2 >= ny) continue;
+            const int64_t c2 = (int64_t)y2 * nx + x2;
+            const double cn = o_node_cost(cT, eG, L, plane, l, c2);
+            if (!(cn < cB)) continue;
+            const double w = cn + ((o_dx8[e] != 0 && o_dy8[e] != 0) ? diag : 1.0);
+            const double nd = dist[u] + w;
+            const int64_t v = (int64_t)l * plane + c2;
+            if (nd < dist[v]) {
+                dist[v] = nd;
+                o_heap_push(h, &n, nd, v);
+            }
+        }
+        for (int m = l - 1; m <= l + 1; m += 2) {
+            if (!o_gateway(cT, eG, L, plane, l, m, c)) continue;
+            const int64_t v = (int64_t)m * plane + c;
+            const double nd = dist[u] + 0.0;
+            if (nd < dist[v]) {
+                dist[v] = nd;
+                o_heap_push(h, &n, nd, v);
+            }
+        }
+    }
+    free(h);
+    free(done);
+    return settled;
+}
+
+/* A least-cost path from the start to the goal, read back from the
+ * distances: from the goal, step to the first predecessor u (in the order:
+ * gateway from the layer below, gateway from the layer above, then the eight
+ * planar neighbours in row-major order of (dy, dx)) whose distance plus the
+ * edge cost equals the node's distance, until the start.  path receives
+ * (x, y, layer) triples from start to goal.  Returns the node count, 0 if the
+ * goal is unreachable, -1 on a bad argument, -2 if max_len is too small. */
+int o_plan_path(const float* cT, const float* eG, int L, int nx, int ny, double cB, const double* dist, int sx,
+                int sy, int sl, int gx, int gy, int gl, int32_t* path, int max_len) {
+    const int64_t plane = (int64_t)nx * ny;
+    if (sx < 0 || sy < 0 || sl < 0 || sx >= nx || sy >= ny || sl >= L) return -1;
+    if (gx < 0 || gy < 0 || gl < 0 || gx >= nx || gy >= ny || gl >= L) return -1;
+    const double diag = sqrt(2.0);
+    int64_t v = (int64_t)gl * plane + (int64_t)gy * nx + gx;
+    const int64_t s = (int64_t)sl * plane + (int64_t)sy * nx + sx;
+    if (!(dist[v] < INFINITY)) return 0;
+    int len = 0;
+    for (;;) {
+        if (len >= max_len) return -2;
+        const int l = (int)(v / plane);
+        const int64_t c = v % plane;
+        const int x = (int)(c % nx), y = (int)(c / nx);
+        path[3 * len] = x;
+        path[3 * len + 1] = y;
+        path[3 * len + 2] = l;
+        ++len;
+        if (v == s) break;
+        int64_t u = -1;
+        for (int m = l - 1; m <= l + 1 && u < 0; m += 2) {
+            if (m < 0 || m >= L) continue;
+            if (o_gateway(cT, eG, L, plane, m, l, c) && dist[(int64_t)m * plane + c] + 0.0 == dist[v])
+                u = (int64_t)m * plane + c;
+        }
+        const double cn = o_node_cost(cT, eG, L, plane, l, c);
+        for (int e = 0; e < 8 && u < 0 && cn < cB; ++e) {
+            const int x2 = x + o_dx8[e], y2 = y + o_dy8[e];
+            if (x2 < 0 || y2 < 0 || x2 >= nx || y2 >= ny) continue;
+            const int64_t u2 = (int64_t)l * plane + (int64_t)y2 * nx + x2;
+            const double w = cn + ((o_dx8[e] != 0 && o_dy8[e] != 0) ? diag : 1.0);
+            if (dist[u2] + w == dist[v]) u = u2;
+        }
+        if (u < 0) return -1; /* not a distance field of this graph */
+        v = u;
+    }
+    for (int a = 0, b = len - 1; a < b; ++a, --b)
+        for (int t = 0; t < 3; ++t) {
+            int32_t tmp = path[3 * a + t];
+            path[3 * a + t] = path[3 * b + t];
+            path[3 * b + t] = tmp;
+        }
+    return len;
+}

@@ -208,6 +208,48 @@ def pct_autotune_reset():
     _check("pct_autotune_reset", lib().pct_autotune_reset())
 
 
+# --------------------------------------------------------------------- path search
+
+def pct_plan_distance(cost, ground, grid, extent: pct_extent, robot, layers, start, workspace=None, dist=None):
+    """Least path costs from ``start`` = (x, y, layer index) over the slices
+    ``layers`` (strictly increasing slice indices) of one robot's c^T
+    [N, ny, nx] and e^G.  Returns (dist [L, ny, nx] float64, workspace,
+    {"rounds", "tiles"}); pass the workspace on to ``pct_plan_path``."""
+    g, rb = grid_struct(grid), robot_struct(robot)
+    N = extent.n_slices
+    for t in (cost, ground):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (N, g.ny, g.nx)):
+            raise ValueError("cost/ground must be contiguous CUDA float32 [N, ny, nx]")
+    lay = (C.c_int32 * len(layers))(*[int(v) for v in layers])
+    L = len(layers)
+    dev = cost.device
+    if dist is None:
+        dist = torch.empty((L, g.ny, g.nx), dtype=torch.float64, device=dev)
+    need = lib().pct_plan_workspace_bytes(g.nx, g.ny, max(L, 1))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    rounds, tiles = C.c_int32(), C.c_int64()
+    _check("pct_plan_distance",
+           lib().pct_plan_distance(_ptr(cost), _ptr(ground), C.byref(g), C.byref(extent), C.byref(rb), lay, L,
+                                   int(start[0]), int(start[1]), int(start[2]), _ptr(dist), _ptr(ws), ws.numel(),
+                                   C.byref(rounds), C.byref(tiles), _stream(dev)))
+    return dist, ws, {"rounds": int(rounds.value), "tiles": int(tiles.value)}
+
+
+def pct_plan_path(dist, grid, start, goal, workspace, max_len=None):
+    """Least-cost path as int32 [n, 3] rows (x, y, slice index), start
+    first, on the device; None if the goal is unreachable."""
+    g = grid_struct(grid)
+    L = dist.shape[0]
+    max_len = int(max_len or min(L * g.nx * g.ny, 1 << 24))
+    path = torch.empty((max_len, 3), dtype=torch.int32, device=dist.device)
+    n = C.c_int32()
+    _check("pct_plan_path",
+           lib().pct_plan_path(_ptr(dist), C.byref(g), L, int(start[0]), int(start[1]), int(start[2]), int(goal[0]),
+                               int(goal[1]), int(goal[2]), _ptr(path), max_len, C.byref(n), _ptr(workspace),
+                               workspace.numel(), _stream(dist.device)))
+    return None if n.value == 0 else path[:n.value]
+
+
 # --------------------------------------------------------------------- trajectory cost
 
 def _wp(wp, slices):

@@ -696,4 +696,74 @@ pct_status pct_trajectory_cost_multi(const float* d_ground, const float* d_ceil,
                                   d_wp_slice, n_traj, n_wp, d_gf, d_f, d_gwp, d_gground, d_gceil, d_gz, n_points, s);
 }
 
+size_t pct_plan_workspace_bytes(int32_t nx, int32_t ny, int32_t n_layers) {
+    if (nx < 1 || ny < 1 || n_layers < 1) return 0;
+    return plan_ws_bytes(nx, ny, n_layers);
+}
+
+static pct_status check_node(const pct_grid* g, int32_t n_layers, int32_t x, int32_t y, int32_t l, const char* what) {
+    if (x < 0 || y < 0 || x >= g->nx || y >= g->ny || l < 0 || l >= n_layers)
+        return fail(PCT_ERR_ARG, "%s node (%d, %d, layer %d) outside the %d x %d x %d map", what, x, y, l, g->nx,
+                    g->ny, n_layers);
+    return PCT_OK;
+}
+
+pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const pct_grid* grid,
+                             const pct_extent* extent, const pct_robot* h_robot, const int32_t* h_layers,
+                             int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double* d_dist, void* d_ws,
+                             size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    const int N = extent->n_slices;
+    if (n_layers < 1 || n_layers > N) return fail(PCT_ERR_ARG, "n_layers %d outside [1, %d]", n_layers, N);
+    if (!h_layers) return fail(PCT_ERR_ARG, "h_layers is null");
+    for (int l = 0; l < n_layers; ++l) {
+        if (h_layers[l] < 0 || h_layers[l] >= N || (l > 0 && h_layers[l] <= h_layers[l - 1]))
+            return fail(PCT_ERR_ARG, "layers must be strictly increasing slice indices in [0, %d)", N);
+    }
+    st = check_node(grid, n_layers, sx, sy, s_layer, "start");
+    if (st != PCT_OK) return st;
+    if (!d_cost || !d_ground || !d_dist) return fail(PCT_ERR_ARG, "device pointers are null");
+    const size_t need = plan_ws_bytes(grid->nx, grid->ny, n_layers);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "plan workspace too small: %zu < %zu", ws_bytes, need);
+    int rounds = 0;
+    long long tiles = 0;
+    st = launch_plan(d_cost, d_ground, grid->nx, grid->ny, h_layers, n_layers, h_robot->c_barrier, sx, sy, s_layer,
+                     d_dist, d_ws, &rounds, &tiles, (hipStream_t)stream);
+    if (h_rounds) *h_rounds = rounds;
+    if (h_tiles) *h_tiles = tiles;
+    return st;
+}
+
+pct_status pct_plan_path(const double* d_dist, const pct_grid* grid, int32_t n_layers, int32_t sx, int32_t sy,
+                         int32_t s_layer, int32_t gx, int32_t gy, int32_t g_layer, int32_t* d_path, int32_t max_len,
+                         int32_t* h_len, void* d_ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    if (n_layers < 1 || n_layers > PCT_MAX_SLICES) return fail(PCT_ERR_ARG, "n_layers %d outside [1, %d]", n_layers,
+                                                               PCT_MAX_SLICES);
+    st = check_node(grid, n_layers, sx, sy, s_layer, "start");
+    if (st != PCT_OK) return st;
+    st = check_node(grid, n_layers, gx, gy, g_layer, "goal");
+    if (st != PCT_OK) return st;
+    if (max_len < 1) return fail(PCT_ERR_ARG, "max_len must be >= 1");
+    if (!d_dist || !d_path || !h_len) return fail(PCT_ERR_ARG, "pointers are null");
+    const size_t need = plan_ws_bytes(grid->nx, grid->ny, n_layers);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "plan workspace too small: %zu < %zu", ws_bytes, need);
+    int len = 0;
+    st = launch_plan_path(d_dist, grid->nx, grid->ny, n_layers, sx, sy, s_layer, gx, gy, g_layer, d_path, max_len,
+                          d_ws, &len, (hipStream_t)stream);
+    if (st != PCT_OK) return st;
+    if (len == -2) return fail(PCT_ERR_CAPACITY, "path has more than %d nodes", max_len);
+    if (len < 0) return fail(PCT_ERR_ARG, "d_dist is not a distance field of this graph");
+    *h_len = len;
+    return PCT_OK;
+}
+
 }  // extern "C"

@@ -14,6 +14,9 @@ from .synth import (  # noqa: F401
     random_walks,
     submap_batch,
     robot_profiles,
+    plan_layers,
+    plan_serpentine,
+    plan_building,
     ROBOT_CONFIG0,
     ROBOT_TABLE1,
 )

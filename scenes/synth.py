@@ -333,3 +333,53 @@ def robot_profiles(seed: int = 4, n: int = 64):
         r["max_step"] = float(rng.uniform(0.1, 0.3))
         out.append(r)
     return out
+
+
+# --------------------------------------------------------------------------
+# inputs of the path search
+
+def plan_layers(seed: int, L: int, ny: int, nx: int, c_barrier: float = 50.0, p_block: float = 0.2,
+                p_same: float = 0.3, p_tie: float = 0.05):
+    """Random layers for the path search: float32 c^T [L, ny, nx] uniform in
+    [0, 20) with a ``p_block`` share of barrier cells, and e^G [L, ny, nx]
+    where each layer repeats the ground of the layer below on a random
+    ``p_same`` share of cells (where nodes merge and gateways can arise) and
+    lies 0.5-3 m higher elsewhere; a ``p_tie`` share of cells copies the
+    cost of the layer below (equal costs: no gateway)."""
+    rng = np.random.default_rng(seed)
+    cT = rng.uniform(0.0, 20.0, (L, ny, nx)).astype(np.float32)
+    cT[rng.random((L, ny, nx)) < p_block] = np.float32(c_barrier)
+    eG = np.zeros((L, ny, nx), np.float32)
+    eG[0] = rng.uniform(0.0, 0.2, (ny, nx)).astype(np.float32)
+    for l in range(1, L):
+        same = rng.random((ny, nx)) < p_same
+        eG[l] = np.where(same, eG[l - 1], eG[l - 1] + np.float32(rng.uniform(0.5, 3.0)))
+    tie = rng.random((L, ny, nx)) < p_tie
+    cT[1:][tie[1:]] = cT[:-1][tie[1:]]
+    return cT, eG
+
+
+def plan_serpentine(seed: int, ny: int, nx: int, pitch: int = 8, gap: int = 3, c_barrier: float = 50.0):
+    """One layer with barrier walls across the map every ``pitch`` rows,
+    each open for ``gap`` cells at alternating ends, so that a path from the
+    top to the bottom winds through every corridor; costs uniform in [0, 5)."""
+    rng = np.random.default_rng(seed)
+    cT = rng.uniform(0.0, 5.0, (1, ny, nx)).astype(np.float32)
+    for i, y in enumerate(range(pitch, ny, pitch)):
+        cT[0, y, :] = np.float32(c_barrier)
+        if i % 2 == 0:
+            cT[0, y, nx - gap:] = cT[0, y - 1, nx - gap:]
+        else:
+            cT[0, y, :gap] = cT[0, y - 1, :gap]
+    return cT, np.zeros((1, ny, nx), np.float32)
+
+
+def plan_building(seed: int = 7, side: float = 100.0, n_floors: int = 6, per_cell: float = 4.0) -> Scene:
+    """The path-search map: the six-storey building of the large map on a
+    ``side`` x ``side`` footprint, sampled densely enough (``per_cell``
+    points per 0.1 m cell and storey, plus 10 % for stairs and beams) that
+    floors and stairs are observed, so that paths exist through the slices."""
+    n_points = int(per_cell * (side / 0.1) ** 2 * n_floors * 1.1)
+    sc = multistorey_scene(seed, side, side, n_points, n_floors=n_floors)
+    sc.name = "plan-building"
+    return sc

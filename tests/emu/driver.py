@@ -520,6 +520,62 @@ def case_traj_value_grad():
         "oracle within tolerance")
 
 
+def plan_run(cT, eG, layers, start, goals, what):
+    """Distances and paths of the library against the oracle's, bit for bit."""
+    N, ny, nx = cT.shape
+    g = grid_s(dict(x0=0.0, y0=0.0, res=0.1, nx=nx, ny=ny, slice_dz=0.3))
+    e = abi.pct_extent(0.0, 1.0, N, 0, 0, 0)
+    rb = robot_s(robot())
+    cB = robot()["c_barrier"]
+    Lc = len(layers)
+    lay = (C.c_int32 * Lc)(*layers)
+    cb, gb = Buf.of(np.ascontiguousarray(cT, np.float32)), Buf.of(np.ascontiguousarray(eG, np.float32))
+    dist = Buf(8 * Lc * ny * nx)
+    ws = Buf(L.pct_plan_workspace_bytes(nx, ny, Lc))
+    rounds, tiles = C.c_int32(), C.c_int64()
+    check("plan", L.pct_plan_distance(P(cb), P(gb), C.byref(g), C.byref(e), C.byref(rb), lay, Lc, start[0], start[1],
+                                      start[2], P(dist), P(ws), ws.nbytes, C.byref(rounds), C.byref(tiles), None))
+    d = dist.get((Lc, ny, nx), np.float64)
+    ref = oracle.plan(cT[layers], eG[layers], cB, start)
+    assert np.array_equal(d.view(np.uint64), ref.view(np.uint64)), f"{what}: distances differ"
+    n_paths = 0
+    for goal in goals:
+        pb = Buf(4 * 3 * Lc * nx * ny)
+        n = C.c_int32()
+        check("path", L.pct_plan_path(P(dist), C.byref(g), Lc, start[0], start[1], start[2], goal[0], goal[1], goal[2],
+                                      P(pb), Lc * nx * ny, C.byref(n), P(ws), ws.nbytes, None))
+        rp = oracle.plan_path(cT[layers], eG[layers], cB, ref, start, goal)
+        if rp is None:
+            assert n.value == 0, f"{what}: goal {goal} should be unreachable"
+            continue
+        got = pb.get((n.value, 3), np.int32)
+        rp = rp.copy()
+        rp[:, 2] = np.asarray(layers)[rp[:, 2]]
+        assert np.array_equal(got, rp), f"{what}: path to {goal} differs"
+        n_paths += 1
+    say(f"plan {what} {Lc}x{ny}x{nx}: distances bit-exact ({int(np.isfinite(ref).sum())} reachable, "
+        f"{rounds.value} rounds, {tiles.value} tiles), {n_paths} paths identical")
+
+
+def case_plan():
+    """Path search through the slices: random layers over several tiles with
+    ragged edges, a subset of slices, a winding single layer, a barrier
+    start, an unreachable goal."""
+    cT, eG = scenes.plan_layers(11, 3, 150, 130)
+    rng = np.random.default_rng(5)
+    goals = [(int(rng.integers(130)), int(rng.integers(150)), int(rng.integers(3))) for _ in range(6)]
+    plan_run(cT, eG, [0, 1, 2], (7, 140, 0), goals, "random layers")
+    cT, eG = scenes.plan_layers(12, 5, 70, 97, p_same=0.5)
+    plan_run(cT, eG, [0, 2, 3], (96, 0, 1), [(0, 69, 0), (50, 30, 2), (96, 0, 1)], "slice subset")
+    cT, eG = scenes.plan_serpentine(13, 90, 75)
+    plan_run(cT, eG, [0], (0, 0, 0), [(0, 89, 0), (74, 45, 0)], "serpentine")
+    cT, eG = scenes.plan_layers(14, 2, 64, 64, p_block=0.6)
+    cT[0, 10, 10] = 50.0
+    plan_run(cT, eG, [0, 1], (10, 10, 0), [(63, 63, 1), (0, 0, 0)], "barrier start, sparse map")
+    cT = np.full((1, 1, 1), 3.0, np.float32)
+    plan_run(cT, np.zeros_like(cT), [0], (0, 0, 0), [(0, 0, 0)], "single cell")
+
+
 CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}
 
 if __name__ == "__main__":
