@@ -286,6 +286,84 @@ def bench_submaps(P, torch, dev, steps, warmup, n_items=512):
             "graph_replay_ms": ms_graph, "identical": same}
 
 
+def bench_plan(P, torch, dev, steps, warmup, cpu=True):
+    """Path search through the slices (Sec. III-D) on the six-storey
+    building without beams (100 m x 100 m, 1000 x 1000 cells, 26.4 M
+    points, Table I quadruped): the library's pipeline builds the tomogram, evaluates it and
+    keeps slices; the search runs from the ground-floor cell nearest the
+    centre over every kept slice, and a path is read back to the farthest
+    reached node.  The oracle's Dijkstra is timed on the oracle's own
+    pipeline output for the same map."""
+    import numpy as np
+
+    import scenes
+    log("path search: generating the building")
+    sc = scenes.plan_building()
+    g = sc.grid
+    xyz = torch.from_numpy(sc.points).to(dev)
+    ext = P.pct_tomogram_extent(xyz, g)
+    G, Cc, _, _ = P.pct_build_tomogram(xyz, g, ext)
+    r = dict(scenes.ROBOT_TABLE1)
+    cost, keep = P.pct_eval_traversability(G, Cc, g, ext, [r])
+    cost = cost[0].contiguous()
+    del Cc
+    layers = [int(v) for v in np.flatnonzero(keep[0].cpu().numpy())]
+
+    def centre_start(cT0, eG0):
+        ys, xs = np.nonzero((cT0 < r["c_barrier"]) & (eG0 < 0.5))
+        k = int(np.argmin((ys - g["ny"] / 2) ** 2 + (xs - g["nx"] / 2) ** 2))
+        return (int(xs[k]), int(ys[k]), 0)
+
+    s = centre_start(cost[layers[0]].cpu().numpy(), G[layers[0]].cpu().numpy())
+    dist, ws, info = P.pct_plan_distance(cost, G, g, ext, r, layers, s)
+    for _ in range(warmup):
+        P.pct_plan_distance(cost, G, g, ext, r, layers, s, workspace=ws, dist=dist)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, _, info = P.pct_plan_distance(cost, G, g, ext, r, layers, s, workspace=ws, dist=dist)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms_dist = float(np.median(times))
+    d = dist.cpu().numpy()
+    reached = int(np.isfinite(d).sum())
+    l, y, x = np.unravel_index(int(np.argmax(np.where(np.isfinite(d), d, -1.0))), d.shape)
+    goal = (int(x), int(y), int(l))
+    ptimes = []
+    for i in range(warmup + steps):
+        t0 = time.perf_counter()
+        path = P.pct_plan_path(dist, g, s, goal, ws)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            ptimes.append((time.perf_counter() - t0) * 1e3)
+    nodes = len(layers) * g["nx"] * g["ny"]
+    out = {"workload": "six-storey building without beams, 100 m x 100 m at 0.1 m (1000 x 1000 cells), 26.4 M points, "
+                       "slice interval 0.3 m, Table I quadruped; search from the ground-floor centre over the "
+                       "kept slices, path to the farthest reached node",
+           "slices": int(ext.n_slices), "layers": len(layers), "nodes": nodes, "reached": reached,
+           "rounds": info["rounds"], "tiles_processed": info["tiles"], "distance_ms": ms_dist,
+           "nodes_per_s": nodes / (ms_dist * 1e-3), "path_ms": float(np.median(ptimes)),
+           "path_nodes": int(path.shape[0]), "goal_cost": float(d[goal[2], goal[1], goal[0]])}
+    if cpu:
+        import oracle
+        log("path search: oracle pipeline and Dijkstra")
+        tm = oracle.tomogram(sc.points, g, ids=False)
+        cT = oracle.evaluate(tm["ground"], tm["ceil"], g["res"], r)
+        lo = np.flatnonzero(oracle.simplify(tm["ground"], cT, r["c_barrier"]))
+        c32 = np.ascontiguousarray(cT[lo], np.float32)
+        e32 = np.ascontiguousarray(tm["ground"][lo])
+        del cT
+        so = centre_start(c32[0], e32[0])
+        t0 = time.perf_counter()
+        do = oracle.plan(c32, e32, r["c_barrier"], so)
+        ms_cpu = (time.perf_counter() - t0) * 1e3
+        out["cpu_oracle"] = {"distance_ms": ms_cpu, "cores": 1, "kind": "oracle",
+                             "nodes": int(do.size), "reached": int(np.isfinite(do).sum()),
+                             "sample": "Dijkstra over the oracle's own kept slices of the same map, whole map"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +372,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain profile measurement")
+    ap.add_argument("--no-plan", action="store_true", help="skip the path-search measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -419,6 +498,8 @@ def main():
         del g, c, cost, keep
         out["batched_vs_plain"] = {"profiles": bench_profiles(P, torch, sc, xyz, dev, args.steps, args.warmup)}
         out["batched_vs_plain"]["submaps"] = bench_submaps(P, torch, dev, args.steps, args.warmup)
+    if not args.no_plan:
+        out["plan"] = bench_plan(P, torch, dev, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a window)")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_window)

@@ -359,15 +359,17 @@ size_t pct_plan_workspace_bytes(int32_t nx, int32_t ny, int32_t n_layers);
 /* Distances from the start node (sx, sy, layer s_layer) to every node.
  * d_cost, d_ground: float32 [N][ny][nx] (c^T of one robot, e^G); c^B is
  * h_robot->c_barrier.  h_layers: host [n_layers], strictly increasing slice
- * indices in [0, N).  d_dist: float64 [n_layers][ny][nx], overwritten
+ * indices in [0, N).  band: width of the distance band whose tiles one
+ * round processes (0: the default, 16384); it changes the amount of work,
+ * never the result.  d_dist: float64 [n_layers][ny][nx], overwritten
  * (+inf: unreachable).  The workspace keeps the node costs and gateways for
  * pct_plan_path.  Synchronous (one host read-back per round of tiles);
  * *h_rounds (nullable) receives the round count, *h_tiles (nullable) the
  * tiles processed.  The start may itself be a barrier node. */
 pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const pct_grid* grid,
                              const pct_extent* extent, const pct_robot* h_robot, const int32_t* h_layers,
-                             int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double* d_dist, void* d_ws,
-                             size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream);
+                             int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double band, double* d_dist,
+                             void* d_ws, size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream);
 
 /* A least-cost path from the start to the goal (gx, gy, layer g_layer),
  * read back from d_dist of the preceding pct_plan_distance call with the

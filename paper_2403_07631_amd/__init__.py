@@ -210,7 +210,8 @@ def pct_autotune_reset():
 
 # --------------------------------------------------------------------- path search
 
-def pct_plan_distance(cost, ground, grid, extent: pct_extent, robot, layers, start, workspace=None, dist=None):
+def pct_plan_distance(cost, ground, grid, extent: pct_extent, robot, layers, start, workspace=None, dist=None,
+                      band=0.0):
     """Least path costs from ``start`` = (x, y, layer index) over the slices
     ``layers`` (strictly increasing slice indices) of one robot's c^T
     [N, ny, nx] and e^G.  Returns (dist [L, ny, nx] float64, workspace,
@@ -230,7 +231,8 @@ def pct_plan_distance(cost, ground, grid, extent: pct_extent, robot, layers, sta
     rounds, tiles = C.c_int32(), C.c_int64()
     _check("pct_plan_distance",
            lib().pct_plan_distance(_ptr(cost), _ptr(ground), C.byref(g), C.byref(extent), C.byref(rb), lay, L,
-                                   int(start[0]), int(start[1]), int(start[2]), _ptr(dist), _ptr(ws), ws.numel(),
+                                   int(start[0]), int(start[1]), int(start[2]), float(band), _ptr(dist), _ptr(ws),
+                                   ws.numel(),
                                    C.byref(rounds), C.byref(tiles), _stream(dev)))
     return dist, ws, {"rounds": int(rounds.value), "tiles": int(tiles.value)}
 

@@ -77,7 +77,7 @@ def load(path):
         "pct_build_tomogram_batched": ([vp, i64, It, i32, vp, vp, vp, vp, i32, vp, sz, vp], i32),
         "pct_eval_traversability_batched": ([vp, vp, It, i32, Rb, i32, vp, vp, i32, vp, sz, vp], i32),
         "pct_plan_workspace_bytes": ([i32, i32, i32], sz),
-        "pct_plan_distance": ([vp, vp, G, E, Rb, vp, i32, i32, i32, i32, vp, vp, sz, C.POINTER(i32),
+        "pct_plan_distance": ([vp, vp, G, E, Rb, vp, i32, i32, i32, i32, C.c_double, vp, vp, sz, C.POINTER(i32),
                                C.POINTER(i64), vp], i32),
         "pct_plan_path": ([vp, G, i32, i32, i32, i32, i32, i32, i32, vp, i32, C.POINTER(i32), vp, sz, vp], i32),
     }

@@ -710,8 +710,8 @@ static pct_status check_node(const pct_grid* g, int32_t n_layers, int32_t x, int
 
 pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const pct_grid* grid,
                              const pct_extent* extent, const pct_robot* h_robot, const int32_t* h_layers,
-                             int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double* d_dist, void* d_ws,
-                             size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream) {
+                             int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double band, double* d_dist,
+                             void* d_ws, size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream) {
     clear_error();
     pct_status st = check_grid(grid);
     if (st != PCT_OK) return st;
@@ -729,12 +729,13 @@ pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const p
     st = check_node(grid, n_layers, sx, sy, s_layer, "start");
     if (st != PCT_OK) return st;
     if (!d_cost || !d_ground || !d_dist) return fail(PCT_ERR_ARG, "device pointers are null");
+    if (!(band >= 0.0)) return fail(PCT_ERR_ARG, "band must be >= 0");
     const size_t need = plan_ws_bytes(grid->nx, grid->ny, n_layers);
     if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "plan workspace too small: %zu < %zu", ws_bytes, need);
     int rounds = 0;
     long long tiles = 0;
     st = launch_plan(d_cost, d_ground, grid->nx, grid->ny, h_layers, n_layers, h_robot->c_barrier, sx, sy, s_layer,
-                     d_dist, d_ws, &rounds, &tiles, (hipStream_t)stream);
+                     d_dist, d_ws, &rounds, &tiles, (hipStream_t)stream, band > 0.0 ? band : kPlanDefaultBand);
     if (h_rounds) *h_rounds = rounds;
     if (h_tiles) *h_tiles = tiles;
     return st;

@@ -31,6 +31,7 @@
 // activates the tile of the adjacent layer.  Rounds repeat until no tile is
 // active.
 #include <math.h>
+#include <string.h>
 
 #include "pct_internal.h"
 
@@ -39,8 +40,10 @@ namespace pct {
 namespace {
 
 constexpr int kPT = 64;            // tile side, cells
-constexpr int kPS = kPT + 3;       // LDS row stride of the distance tile (doubles; conflict-free columns)
+constexpr int kPS = kPT + 1;       // LDS row stride of the distance tile (doubles)
 constexpr int kCS = kPT + 1;       // LDS row stride of the node-cost tile (floats)
+
+__device__ __forceinline__ int cidx(int r, int c) { return r * kCS + c; }
 constexpr double kSqrt2 = 1.4142135623730951;   // sqrt(2) rounded to double
 
 // gateway bits of a node (l, cell)
@@ -101,10 +104,15 @@ __global__ __launch_bounds__(256) void k_plan_prep(const float* __restrict__ cos
 }
 
 __global__ __launch_bounds__(256) void k_plan_init(double* __restrict__ dist, long long n, long long s,
-                                                   unsigned* __restrict__ flag, int n_tiles, int t0) {
+                                                   unsigned* __restrict__ flag, unsigned long long* __restrict__ key,
+                                                   int n_tiles, int t0) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dist[i] = i == s ? 0.0 : INFINITY;
-    if (i < n_tiles) flag[i] = i == t0 ? 1u : 0u;
+    if (i < n) dist[i] = INFINITY;   // the start takes 0 on its tile's first visit
+    (void)s;
+    if (i < n_tiles) {
+        flag[i] = i == t0 ? 1u : 0u;
+        key[i] = i == t0 ? 0ull : ~0ull;   // bits of +0.0
+    }
 }
 
 // Lane i receives lane i-1's (i+1's) value; the edge lane gets 0.
@@ -129,41 +137,45 @@ __device__ __forceinline__ double from_lane_above(double v) {
 // lockstep) or, for the edge lanes, halo cells.  A lane touches only its
 // own row or column of the tile in LDS during a sweep.
 template <bool VERT, bool REV>
-__device__ __forceinline__ bool sweep(double* sd, const float* scn, int q) {
-    // LDS coordinates: node (r, c) of the tile is sd[(r + 1) * kPS + c + 1]
+__device__ __forceinline__ bool sweep(double* sd, const double (*hz)[kPT + 2], const float* scn, int q) {
+    // node (r, c) of the tile is sd[r * kPS + c]; the halo lines (row -1,
+    // row 64, column -1, column 64, each indexed from -1 to 64) are in hz,
+    // a separate array, so that their loads can run ahead of the stores
     bool changed = false;
-    const int s0 = REV ? kPT : -1;   // halo position before the first step
-    double prev = VERT ? sd[(s0 + 1) * kPS + q + 1] : sd[(q + 1) * kPS + s0 + 1];
-#pragma unroll 4
+    double prev = VERT ? hz[REV ? 1 : 0][q + 1] : hz[REV ? 3 : 2][q + 1];   // halo before the first step
+#pragma unroll 8
     for (int i = 0; i < kPT; ++i) {
         const int s = REV ? kPT - 1 - i : i;      // step along the sweep
         const int sp = REV ? s + 1 : s - 1;       // previous step
-        double* me = VERT ? &sd[(s + 1) * kPS + q + 1] : &sd[(q + 1) * kPS + s + 1];
-        const float c = VERT ? scn[s * kCS + q] : scn[q * kCS + s];
+        double* me = VERT ? &sd[s * kPS + q] : &sd[q * kPS + s];
+        const float c = VERT ? scn[cidx(s, q)] : scn[cidx(q, s)];
         // halo nodes beside lanes 0 and 63 at the previous step
-        const double h0 = VERT ? sd[(sp + 1) * kPS] : sd[sp + 1];
-        const double h1 = VERT ? sd[(sp + 1) * kPS + kPT + 1] : sd[(kPT + 1) * kPS + sp + 1];
-        double a = from_lane_below(prev), b = from_lane_above(prev);
-        if (q == 0) a = h0;
-        if (q == kPT - 1) b = h1;
-        const double ws = (double)c + 1.0, wd = (double)c + kSqrt2;
-        const double cand = fmin(prev + ws, fmin(a + wd, b + wd));
+        const double h0 = VERT ? hz[2][sp + 1] : hz[0][sp + 1];
+        const double h1 = VERT ? hz[3][sp + 1] : hz[1][sp + 1];
         const double old = *me;
-        if (cand < old) {
-            *me = cand;
-            changed = true;
-            prev = cand;
-        } else {
-            prev = old;
-        }
+        double a = from_lane_below(prev), b = from_lane_above(prev);
+        a = q == 0 ? h0 : a;
+        b = q == kPT - 1 ? h1 : b;
+        const double ws = (double)c + 1.0, wd = (double)c + kSqrt2;
+        // sums are canonical, so the minima need no NaN quieting
+        const double cand = fmin(prev + ws, fmin(a + wd, b + wd));
+        const bool lower = cand < old;
+        prev = lower ? cand : old;
+        *me = prev;
+        changed |= lower;
     }
     return changed;
 }
 
+// Non-negative doubles order like their bit patterns.
+__device__ __forceinline__ unsigned long long dbits(double v) { return __builtin_bit_cast(unsigned long long, v); }
+
 __global__ __launch_bounds__(64) void k_plan_relax(PlanGeom g, const float* __restrict__ cn,
                                                    const uint8_t* __restrict__ gw, double* __restrict__ dist,
-                                                   const unsigned* __restrict__ list, unsigned* __restrict__ flag) {
-    __shared__ double sd[(kPT + 2) * kPS];
+                                                   const unsigned* __restrict__ list, unsigned* __restrict__ flag,
+                                                   unsigned long long* __restrict__ key, long long src) {
+    __shared__ double sd[kPT * kPS];
+    __shared__ double hz[4][kPT + 2];
     __shared__ float scn[kPT * kCS];
     const int q = threadIdx.x;
     const int t = (int)list[blockIdx.x];
@@ -172,79 +184,183 @@ __global__ __launch_bounds__(64) void k_plan_relax(PlanGeom g, const float* __re
     const int ty = tt / g.ntx, tx = tt - ty * g.ntx;
     const int x0 = tx * kPT, y0 = ty * kPT;
     const long long lo = (long long)l * g.plane;
+    const int x = x0 + q;
+    const bool xin = x < g.nx;
 
-    // distances with a one-cell halo (+inf outside the grid), node costs
-    for (int r = 0; r < kPT + 2; ++r) {
-        const int y = y0 - 1 + r;
-        for (int c = q; c < kPT + 2; c += 64) {
-            const int x = x0 - 1 + c;
-            const bool in = x >= 0 && y >= 0 && x < g.nx && y < g.ny;
-            sd[r * kPS + c] = in ? dist[lo + (long long)y * g.nx + x] : INFINITY;
+    // distances of the tile and its one-cell halo (+inf outside the grid);
+    // loads are issued in batches so that many are in flight.  Lane q keeps
+    // its column's values (orig) to find the nodes that change.
+    double orig[kPT];
+    {
+        double top, bot;
+        constexpr int RB = 22;   // rows -1 .. 64 = 3 batches
+#pragma unroll
+        for (int r0 = -1; r0 < kPT + 1; r0 += RB) {
+            double v[RB];
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                const int y = y0 + r0 + j;
+                v[j] = (xin && y >= 0 && y < g.ny) ? dist[lo + (long long)y * g.nx + x] : INFINITY;
+            }
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                const int r = r0 + j;
+                if (r < 0) top = v[j];
+                else if (r >= kPT) bot = v[j];
+                else orig[r] = v[j];
+            }
         }
+        hz[0][q + 1] = top;
+        hz[1][q + 1] = bot;
+#pragma unroll
+        for (int r = 0; r < kPT; ++r) sd[r * kPS + q] = orig[r];
     }
-    __syncthreads();   // lane q now updates column q + 1, written by lane q + 1
-    for (int r = 0; r < kPT; ++r) {
-        const int y = y0 + r, x = x0 + q;
-        const bool in = x < g.nx && y < g.ny;
-        float c = INFINITY;
-        if (in) {
-            const long long i = lo + (long long)y * g.nx + x;
-            c = cn[i];
-            // gateways into this node: the adjacent layer's distance, at no cost
-            const unsigned b = gw[i];
-            double d = sd[(r + 1) * kPS + q + 1];
-            if (b & kInFromBelow) d = fmin(d, dist[i - g.plane] + 0.0);
-            if (b & kInFromAbove) d = fmin(d, dist[i + g.plane] + 0.0);
-            sd[(r + 1) * kPS + q + 1] = d;
+    {
+        // halo columns x0 - 1 and x0 + 64 (rows -1 .. 64), and the four
+        // corners again in the halo rows: 136 values over the lanes
+        double v[3];
+        double* dst[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int idx = q + 64 * k;
+            int xx, yy;
+            dst[k] = nullptr;
+            if (idx < 2 * (kPT + 2)) {
+                const int side = idx / (kPT + 2), r = idx - side * (kPT + 2);
+                xx = side ? x0 + kPT : x0 - 1;
+                yy = y0 - 1 + r;
+                dst[k] = &hz[2 + side][r];
+            } else if (idx < 2 * (kPT + 2) + 4) {
+                const int cidx = idx - 2 * (kPT + 2);   // (row -1 | 64) x (column -1 | 64)
+                xx = (cidx & 1) ? x0 + kPT : x0 - 1;
+                yy = (cidx & 2) ? y0 + kPT : y0 - 1;
+                dst[k] = &hz[(cidx & 2) ? 1 : 0][(cidx & 1) ? kPT + 1 : 0];
+            } else {
+                xx = -1;
+                yy = -1;
+            }
+            const bool in = dst[k] && xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny;
+            v[k] = in ? dist[lo + (long long)yy * g.nx + xx] : INFINITY;
         }
-        scn[r * kCS + q] = c;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (dst[k]) *dst[k] = v[k];
+    }
+    // node costs; gateways into a node offer the adjacent layer's distance
+    // at no cost (lane q updates only its own column here)
+    constexpr int CB = 16;
+    bool moved = false;                        // some node of the tile can improve
+    unsigned long long outup = 0, outdn = 0;   // nodes of column q with a gateway up / down
+    for (int r0 = 0; r0 < kPT; r0 += CB) {
+        float c[CB];
+        unsigned b[CB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int y = y0 + r0 + j;
+            const bool in = xin && y < g.ny;
+            const long long i = lo + (long long)y * g.nx + x;
+            c[j] = in ? cn[i] : INFINITY;
+            b[j] = in ? (unsigned)gw[i] : 0u;
+        }
+        double pu[CB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const long long i = lo + (long long)(y0 + r0 + j) * g.nx + x;
+            double d = INFINITY;
+            if (b[j] & kInFromBelow) d = dist[i - g.plane] + 0.0;
+            if (b[j] & kInFromAbove) d = fmin(d, dist[i + g.plane] + 0.0);
+            pu[j] = d;
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            double* me = &sd[(r0 + j) * kPS + q];
+            // the start node enters at distance 0 on the first visit of its tile
+            const bool is_src = xin && y0 + r0 + j < g.ny && lo + (long long)(y0 + r0 + j) * g.nx + x == src;
+            const double in = is_src ? 0.0 : pu[j];
+            if (in < *me) {
+                *me = in;
+                moved = true;
+            }
+            scn[cidx(r0 + j, q)] = c[j];
+            outup |= (unsigned long long)((b[j] & kOutUp) != 0) << (r0 + j);
+            outdn |= (unsigned long long)((b[j] & kOutDown) != 0) << (r0 + j);
+        }
     }
     __syncthreads();
 
-    for (;;) {
-        bool ch = sweep<false, false>(sd, scn, q);
+    // The tile was at a fixed point of its own edges after its last visit,
+    // and only its halo and gateway inputs can have changed since: unless a
+    // gateway or the start lowered a node above, or a halo node lowers a
+    // border node, nothing in the tile can change.
+    {
+        auto relax3 = [&](int r, int c, double straight, double d1, double d2) {
+            const float cc = scn[cidx(r, c)];
+            const double cand = fmin(straight + ((double)cc + 1.0), fmin(d1, d2) + ((double)cc + kSqrt2));
+            return cand < sd[r * kPS + c];
+        };
+        moved |= relax3(0, q, hz[0][q + 1], hz[0][q], hz[0][q + 2]);                    // top
+        moved |= relax3(kPT - 1, q, hz[1][q + 1], hz[1][q], hz[1][q + 2]);              // bottom
+        moved |= relax3(q, 0, hz[2][q + 1], hz[2][q], hz[2][q + 2]);                    // left
+        moved |= relax3(q, kPT - 1, hz[3][q + 1], hz[3][q], hz[3][q + 2]);              // right
+    }
+    if (!__ballot(moved)) return;
+
+    // Sweep the directions in turn (left-to-right, right-to-left,
+    // top-to-bottom, bottom-to-top), skipping a direction when no node has
+    // changed since its last sweep: after a sweep, every edge of its
+    // direction holds, so the tile is at its fixed point when all four are
+    // clean.
+    unsigned dirty = 0xFu;
+    for (int d = 0; dirty; d = (d + 1) & 3) {
+        if (!(dirty & (1u << d))) continue;
+        bool ch;
+        if (d == 0) ch = sweep<false, false>(sd, hz, scn, q);
+        else if (d == 1) ch = sweep<false, true>(sd, hz, scn, q);
+        else if (d == 2) ch = sweep<true, false>(sd, hz, scn, q);
+        else ch = sweep<true, true>(sd, hz, scn, q);
+        dirty &= ~(1u << d);
+        if (__ballot(ch)) dirty = 0xFu & ~(1u << d);
         __syncthreads();
-        ch |= sweep<false, true>(sd, scn, q);
-        __syncthreads();
-        ch |= sweep<true, false>(sd, scn, q);
-        __syncthreads();
-        ch |= sweep<true, true>(sd, scn, q);
-        __syncthreads();
-        if (!__ballot(ch)) break;
     }
 
-    // write back improved nodes; note which neighbours must look again
+    // write back the nodes that changed (values only go down); note which
+    // neighbours must look again and the least changed distance (their
+    // priority)
     bool nb_up = false, nb_dn = false, nb_l = false, nb_r = false;
     bool c_ul = false, c_ur = false, c_dl = false, c_dr = false, g_up = false, g_dn = false;
+    double vmin = INFINITY;
     const int w = min(kPT, g.nx - x0), h = min(kPT, g.ny - y0);
-    if (q < w) {
-        for (int r = 0; r < h; ++r) {
-            const long long i = lo + (long long)(y0 + r) * g.nx + x0 + q;
-            const double nd = sd[(r + 1) * kPS + q + 1];
-            if (nd < dist[i]) {
-                dist[i] = nd;
-                nb_up |= r == 0;
-                nb_dn |= r == h - 1;
-                nb_l |= q == 0;
-                nb_r |= q == w - 1;
-                c_ul |= r == 0 && q == 0;
-                c_ur |= r == 0 && q == w - 1;
-                c_dl |= r == h - 1 && q == 0;
-                c_dr |= r == h - 1 && q == w - 1;
-                const unsigned b = gw[i];
-                g_up |= (b & kOutUp) != 0;
-                g_dn |= (b & kOutDown) != 0;
-            }
+    const bool qin = q < w;
+#pragma unroll
+    for (int r = 0; r < kPT; ++r) {
+        const double nd = sd[r * kPS + q];
+        if (qin && r < h && nd < orig[r]) {
+            dist[lo + (long long)(y0 + r) * g.nx + x] = nd;
+            vmin = fmin(vmin, nd);
+            nb_up |= r == 0;
+            nb_dn |= r == h - 1;
+            nb_l |= q == 0;
+            nb_r |= q == w - 1;
+            c_ul |= r == 0 && q == 0;
+            c_ur |= r == 0 && q == w - 1;
+            c_dl |= r == h - 1 && q == 0;
+            c_dr |= r == h - 1 && q == w - 1;
+            g_up |= ((outup >> r) & 1ull) != 0;
+            g_dn |= ((outdn >> r) & 1ull) != 0;
         }
     }
     const unsigned long long m_up = __ballot(nb_up), m_dn = __ballot(nb_dn), m_l = __ballot(nb_l),
                              m_r = __ballot(nb_r), m_ul = __ballot(c_ul), m_ur = __ballot(c_ur),
                              m_dl = __ballot(c_dl), m_dr = __ballot(c_dr), m_gu = __ballot(g_up),
                              m_gd = __ballot(g_dn);
+    for (int o = 32; o > 0; o >>= 1) vmin = fmin(vmin, __shfl_xor(vmin, o, 64));
     if (q == 0) {
+        const unsigned long long kv = dbits(vmin);
         auto act = [&](int ll, int yy, int xx) {
             if (ll < 0 || ll >= g.L || yy < 0 || yy >= g.nty || xx < 0 || xx >= g.ntx) return;
-            flag[(ll * g.nty + yy) * g.ntx + xx] = 1u;
+            const int tn = (ll * g.nty + yy) * g.ntx + xx;
+            atomicMin(&key[tn], kv);
+            flag[tn] = 1u;
         };
         if (m_up) act(l, ty - 1, tx);
         if (m_dn) act(l, ty + 1, tx);
@@ -259,23 +375,44 @@ __global__ __launch_bounds__(64) void k_plan_relax(PlanGeom g, const float* __re
     }
 }
 
-// Active flags -> next worklist (flags cleared); count[0] must be zero.
-__global__ __launch_bounds__(256) void k_plan_compact(unsigned* __restrict__ flag, int n_tiles,
-                                                      unsigned* __restrict__ list, unsigned* __restrict__ count) {
+// Active tiles whose key (the least distance that activated them) is at
+// most the band limit -> worklist (flag and key cleared); the others stay
+// active: st[1] counts them and st2 receives their least key.  st[0] (the
+// list length), st[1] and st2 must be reset before the launch.
+__global__ __launch_bounds__(256) void k_plan_compact(unsigned* __restrict__ flag, unsigned long long* __restrict__ key,
+                                                      int n_tiles, unsigned long long band, unsigned* __restrict__ list,
+                                                      unsigned* __restrict__ st, unsigned long long* __restrict__ st2) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool on = t < n_tiles && flag[t] != 0u;
-    const unsigned long long m = __ballot(on);
+    const bool act = t < n_tiles && flag[t] != 0u;
+    const unsigned long long kt = act ? key[t] : ~0ull;
+    const bool on = act && kt <= band;
+    const bool rest = act && !on;
+    const unsigned long long m = __ballot(on), mr = __ballot(rest);
     const int lane = threadIdx.x & 63;
     unsigned base = 0;
-    if (lane == 0 && m) base = atomicAdd(count, (unsigned)__popcll(m));
+    if (lane == 0 && m) base = atomicAdd(&st[0], (unsigned)__popcll(m));
+    if (lane == 0 && mr) atomicAdd(&st[1], (unsigned)__popcll(mr));
+    if (rest) atomicMin(st2, kt);
     base = __shfl(base, 0, 64);
     if (on) {
         flag[t] = 0u;
+        key[t] = ~0ull;
         list[base + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned)t;
     }
 }
 
-__global__ void k_plan_zero1(unsigned* p) { *p = 0u; }
+struct PlanStatus {
+    unsigned n_list, n_rest;
+    unsigned long long rest_key;
+};
+
+__global__ void k_plan_status_reset(PlanStatus* st) {
+    st->n_list = 0u;
+    st->n_rest = 0u;
+    st->rest_key = ~0ull;
+}
+
+
 
 // One wavefront walks back from the goal: lanes 0..9 test the candidate
 // predecessors (gateway from below, gateway from above, the eight planar
@@ -363,8 +500,9 @@ struct PlanWs {
     float* cn;
     uint8_t* gw;
     unsigned* flag;
-    unsigned* list[2];
-    unsigned* count;   // [2]
+    unsigned long long* key;
+    unsigned* list;
+    PlanStatus* st;
     int* layers;
     int* out;
 };
@@ -382,9 +520,9 @@ size_t plan_ws_layout(const PlanGeom& g, PlanWs* w, void* base) {
     ws.cn = (float*)take(sizeof(float) * (size_t)nn);
     ws.gw = (uint8_t*)take((size_t)nn);
     ws.flag = (unsigned*)take(sizeof(unsigned) * (size_t)nt);
-    ws.list[0] = (unsigned*)take(sizeof(unsigned) * (size_t)nt);
-    ws.list[1] = (unsigned*)take(sizeof(unsigned) * (size_t)nt);
-    ws.count = (unsigned*)take(sizeof(unsigned) * 2);
+    ws.key = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)nt);
+    ws.list = (unsigned*)take(sizeof(unsigned) * (size_t)nt);
+    ws.st = (PlanStatus*)take(sizeof(PlanStatus));
     ws.layers = (int*)take(sizeof(int) * (size_t)g.L);
     ws.out = (int*)take(sizeof(int) * 4);
     if (w) *w = ws;
@@ -397,7 +535,7 @@ size_t plan_ws_bytes(int nx, int ny, int L) { return plan_ws_layout(make_plan_ge
 
 pct_status launch_plan(const float* cost, const float* ground, int nx, int ny, const int* h_layers, int L, float cB,
                        int sx, int sy, int sl, double* dist, void* ws_base, int* h_rounds, long long* h_tiles,
-                       hipStream_t s) {
+                       hipStream_t s, double delta) {
     const PlanGeom g = make_plan_geom(nx, ny, L);
     PlanWs w;
     plan_ws_layout(g, &w, ws_base);
@@ -410,24 +548,38 @@ pct_status launch_plan(const float* cost, const float* ground, int nx, int ny, c
     const long long src = (long long)sl * g.plane + (long long)sy * nx + sx;
     const int t0 = (sl * g.nty + sy / kPT) * g.ntx + sx / kPT;
     const long long ni = std::max<long long>(nn, nt);
-    hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, s, dist, nn, src, w.flag, nt, t0);
+    hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, s, dist, nn, src, w.flag, w.key,
+                       nt, t0);
     PCT_LAUNCH_CHECK();
+    // Rounds take the active tiles whose activating distance lies within
+    // a band of width delta above the least one (tiles roughly in order of
+    // distance, as Dijkstra's algorithm takes nodes); a band with no tile
+    // left moves up to the least remaining key.
+    double band = delta;
     int rounds = 0;
     long long tiles = 0;
-    unsigned n_active = 0;
-    for (int cur = 0;; cur ^= 1) {
-        // flags -> list[cur]
-        hipLaunchKernelGGL(k_plan_zero1, dim3(1), dim3(1), 0, s, w.count + cur);
-        hipLaunchKernelGGL(k_plan_compact, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, w.flag, nt,
-                           w.list[cur], w.count + cur);
+    PlanStatus hs;
+    for (;;) {
+        unsigned long long band_bits;
+        memcpy(&band_bits, &band, sizeof band_bits);
+        hipLaunchKernelGGL(k_plan_status_reset, dim3(1), dim3(1), 0, s, w.st);
+        hipLaunchKernelGGL(k_plan_compact, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, w.flag, w.key, nt,
+                           band_bits, w.list, &w.st->n_list, &w.st->rest_key);
         PCT_LAUNCH_CHECK();
-        PCT_HIP(hipMemcpyAsync(&n_active, w.count + cur, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        PCT_HIP(hipMemcpyAsync(&hs, w.st, sizeof hs, hipMemcpyDeviceToHost, s));
         PCT_HIP(hipStreamSynchronize(s));
-        if (n_active == 0) break;
-        hipLaunchKernelGGL(k_plan_relax, dim3(n_active), dim3(64), 0, s, g, w.cn, w.gw, dist, w.list[cur], w.flag);
+        if (hs.n_list == 0) {
+            if (hs.n_rest == 0) break;
+            double kmin;
+            memcpy(&kmin, &hs.rest_key, sizeof kmin);
+            band = kmin + delta;
+            continue;
+        }
+        hipLaunchKernelGGL(k_plan_relax, dim3(hs.n_list), dim3(64), 0, s, g, w.cn, w.gw, dist, w.list, w.flag, w.key,
+                           src);
         PCT_LAUNCH_CHECK();
         ++rounds;
-        tiles += n_active;
+        tiles += hs.n_list;
     }
     if (h_rounds) *h_rounds = rounds;
     if (h_tiles) *h_tiles = tiles;

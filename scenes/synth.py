@@ -376,10 +376,11 @@ def plan_serpentine(seed: int, ny: int, nx: int, pitch: int = 8, gap: int = 3, c
 
 def plan_building(seed: int = 7, side: float = 100.0, n_floors: int = 6, per_cell: float = 4.0) -> Scene:
     """The path-search map: the six-storey building of the large map on a
-    ``side`` x ``side`` footprint, sampled densely enough (``per_cell``
-    points per 0.1 m cell and storey, plus 10 % for stairs and beams) that
-    floors and stairs are observed, so that paths exist through the slices."""
+    ``side`` x ``side`` footprint without beams (a beam across a staircase
+    closes it), sampled densely enough (``per_cell`` points per 0.1 m cell
+    and storey, plus 10 %) that floors and stairs are observed, so that paths
+    exist through the slices from the ground floor to the top."""
     n_points = int(per_cell * (side / 0.1) ** 2 * n_floors * 1.1)
-    sc = multistorey_scene(seed, side, side, n_points, n_floors=n_floors)
+    sc = multistorey_scene(seed, side, side, n_points, n_floors=n_floors, beam_cover=0.0)
     sc.name = "plan-building"
     return sc

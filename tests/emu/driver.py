@@ -520,7 +520,7 @@ def case_traj_value_grad():
         "oracle within tolerance")
 
 
-def plan_run(cT, eG, layers, start, goals, what):
+def plan_run(cT, eG, layers, start, goals, what, band=0.0):
     """Distances and paths of the library against the oracle's, bit for bit."""
     N, ny, nx = cT.shape
     g = grid_s(dict(x0=0.0, y0=0.0, res=0.1, nx=nx, ny=ny, slice_dz=0.3))
@@ -534,7 +534,8 @@ def plan_run(cT, eG, layers, start, goals, what):
     ws = Buf(L.pct_plan_workspace_bytes(nx, ny, Lc))
     rounds, tiles = C.c_int32(), C.c_int64()
     check("plan", L.pct_plan_distance(P(cb), P(gb), C.byref(g), C.byref(e), C.byref(rb), lay, Lc, start[0], start[1],
-                                      start[2], P(dist), P(ws), ws.nbytes, C.byref(rounds), C.byref(tiles), None))
+                                      start[2], band, P(dist), P(ws), ws.nbytes, C.byref(rounds), C.byref(tiles),
+                                      None))
     d = dist.get((Lc, ny, nx), np.float64)
     ref = oracle.plan(cT[layers], eG[layers], cB, start)
     assert np.array_equal(d.view(np.uint64), ref.view(np.uint64)), f"{what}: distances differ"
@@ -565,6 +566,8 @@ def case_plan():
     rng = np.random.default_rng(5)
     goals = [(int(rng.integers(130)), int(rng.integers(150)), int(rng.integers(3))) for _ in range(6)]
     plan_run(cT, eG, [0, 1, 2], (7, 140, 0), goals, "random layers")
+    plan_run(cT, eG, [0, 1, 2], (7, 140, 0), goals, "random layers, narrow band", band=16.0)
+    plan_run(cT, eG, [0, 1, 2], (7, 140, 0), goals, "random layers, one band", band=1e300)
     cT, eG = scenes.plan_layers(12, 5, 70, 97, p_same=0.5)
     plan_run(cT, eG, [0, 2, 3], (96, 0, 1), [(0, 69, 0), (50, 30, 2), (96, 0, 1)], "slice subset")
     cT, eG = scenes.plan_serpentine(13, 90, 75)

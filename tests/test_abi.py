@@ -188,3 +188,34 @@ def test_batch_rejects_before_launch(P):
     assert L.pct_tomogram_extent_batched(C.c_void_p(0x1000), 10, items, 2, C.byref(tc), C.byref(ts),
                                          C.c_void_p(0x1000), 1 << 20, None) == P.PCT_ERR_ARG
     assert b"item 1" in L.pct_last_error()
+
+
+def test_plan_argument_checks(P):
+    """The path search validates its arguments before touching the device."""
+    import ctypes as C
+    L = P.lib()
+    g = P.grid_struct(dict(x0=0.0, y0=0.0, res=0.1, nx=100, ny=80, slice_dz=0.3))
+    e = P.pct_extent(0.0, 1.0, 5, 0, 0, 0)
+    rb = P.robot_struct(P.robot_from_physical(scenes.ROBOT_CONFIG0, 0.1))
+    assert L.pct_plan_workspace_bytes(100, 80, 3) > 100 * 80 * 3 * 5
+    assert L.pct_plan_workspace_bytes(0, 80, 3) == 0
+    dummy = C.c_void_p(16)
+
+    def call(layers, start, ws_bytes=1 << 30, ptr=dummy, band=0.0):
+        lay = (C.c_int32 * max(1, len(layers)))(*layers)
+        return L.pct_plan_distance(ptr, ptr, C.byref(g), C.byref(e), C.byref(rb), lay, len(layers), *start, band,
+                                   ptr, ptr, ws_bytes, None, None, None)
+
+    assert call([0, 2, 2], (0, 0, 0)) == P.PCT_ERR_ARG       # not strictly increasing
+    assert call([0, 5], (0, 0, 0)) == P.PCT_ERR_ARG          # slice outside the extent
+    assert call([], (0, 0, 0)) == P.PCT_ERR_ARG              # no layer
+    assert call([0, 1], (100, 0, 0)) == P.PCT_ERR_ARG        # start outside the map
+    assert call([0, 1], (0, 0, 2)) == P.PCT_ERR_ARG          # start layer outside
+    assert call([0, 1], (0, 0, 0), ptr=None) == P.PCT_ERR_ARG
+    assert call([0, 1], (0, 0, 0), ws_bytes=16) == P.PCT_ERR_WORKSPACE
+    assert call([0, 1], (0, 0, 0), band=-1.0) == P.PCT_ERR_ARG
+    n = C.c_int32()
+    assert L.pct_plan_path(dummy, C.byref(g), 2, 0, 0, 0, 0, 0, 5, dummy, 10, C.byref(n), dummy, 1 << 30,
+                           None) == P.PCT_ERR_ARG            # goal layer outside
+    assert L.pct_plan_path(dummy, C.byref(g), 2, 0, 0, 0, 0, 0, 1, dummy, 0, C.byref(n), dummy, 1 << 30,
+                           None) == P.PCT_ERR_ARG            # max_len 0

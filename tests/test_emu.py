@@ -47,6 +47,7 @@ def run_cases(cases, order="fwd", timeout=900):
     (["many_chunks", "two_level"], "fwd"),
     (["batch", "batch_resident", "batch_mixed_radius"], "rand"),
     (["traj_value_grad", "autotune"], "fwd"),
+    (["plan"], "rand"),
 ])
 def test_kernels_on_cpu(emu_lib, cases, order):
     run_cases(cases, order)

@@ -178,8 +178,8 @@ def bellman_check(d, cT, eG, layers, start, cb):
 
 
 def test_full_size_building(P):
-    """The benchmark's map (100 m x 100 m, six storeys, 4 points per cell and
-    storey, Table I quadruped): the GPU pipeline builds, evaluates and keeps
+    """The benchmark's map (100 m x 100 m, six storeys without beams, 4 points
+    per cell and storey, Table I quadruped): the GPU pipeline builds, evaluates and keeps
     slices; the path search from the ground-floor centre is checked against
     the Bellman equations at all nodes, and the path to the farthest reached
     node is valid with the exact cost."""
