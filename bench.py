@@ -39,7 +39,7 @@ def log(msg):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("eval.hip", "build.hip", "pct_internal.h"):
+    for f in ("eval.hip", "pct_internal.h"):
         with open(os.path.join(ROOT, "paper_2403_07631_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "pct_internal.h"
+#include "plan_internal.h"
 
 namespace pct {
 

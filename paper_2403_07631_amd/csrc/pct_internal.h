@@ -154,13 +154,6 @@ pct_status launch_traj_value_grad(const float* ground, const float* ceil, const 
                                   const float* wp, const int* slice, int T, int W, const float* gf, float* f,
                                   float* gwp, float* gground, float* gceil, float* gz, long long n_points,
                                   hipStream_t s);
-size_t plan_ws_bytes(int nx, int ny, int L);
-constexpr double kPlanDefaultBand = 16384.0;  // distance band per round of the path search
-pct_status launch_plan(const float* cost, const float* ground, int nx, int ny, const int* h_layers, int L, float cB,
-                       int sx, int sy, int sl, double* dist, void* ws_base, int* h_rounds, long long* h_tiles,
-                       hipStream_t s, double delta);
-pct_status launch_plan_path(const double* dist, int nx, int ny, int L, int sx, int sy, int sl, int gx, int gy, int gl,
-                            int* path, int max_len, void* ws_base, int* h_len, hipStream_t s);
 pct_status launch_route(const float* gG, const float* gC, const int* aG, const int* aC, long long plane, int N,
                         long long n_points, float* gz, hipStream_t s);
 

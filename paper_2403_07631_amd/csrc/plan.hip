@@ -34,6 +34,7 @@
 #include <string.h>
 
 #include "pct_internal.h"
+#include "plan_internal.h"
 
 namespace pct {
 

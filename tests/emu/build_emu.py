@@ -31,7 +31,8 @@ def sources():
 
 
 def inputs():
-    files = sources() + [os.path.join(CSRC, "pct_internal.h"), os.path.join(ROOT, "include", "pct.h"),
+    headers = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h"))
+    files = sources() + headers + [os.path.join(ROOT, "include", "pct.h"),
                          os.path.join(HERE, "hip", "hip_runtime.h"), os.path.join(HERE, "emu_runtime.cpp"),
                          os.path.abspath(__file__)]
     return files
