@@ -34,6 +34,10 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 
+struct alignas(16) float4 {
+    float x, y, z, w;
+};
+
 struct dim3 {
     unsigned x, y, z;
     constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}

@@ -28,29 +28,60 @@ def emu_lib():
     return build_emu.build()
 
 
-def run_cases(cases, order="fwd", timeout=900):
+def _env(order):
     env = dict(os.environ)
     env["LD_PRELOAD"] = build_emu.asan_runtime()
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:halt_on_error=1"
     env["EMU_ORDER"] = order
-    env["OMP_NUM_THREADS"] = env.get("OMP_NUM_THREADS", "4")
-    r = subprocess.run([sys.executable, os.path.join(EMU, "driver.py"), *cases], env=env, capture_output=True,
-                       text=True, timeout=timeout)
-    out = r.stdout + "\n".join(l for l in r.stderr.splitlines() if "makecontext" not in l)
-    assert r.returncode == 0 and "[emu] all passed" in r.stdout, out[-6000:]
-    return out
+    env["OMP_NUM_THREADS"] = "1"
+    return env
 
 
-@pytest.mark.parametrize("cases,order", [
-    (["tiny", "edges", "config0", "multirobot", "fallback_eval"], "rev"),
-    (["crop", "dense", "multirobot_large"], "rand"),
-    (["many_chunks", "two_level"], "fwd"),
-    (["batch", "batch_resident", "batch_mixed_radius"], "rand"),
-    (["traj_value_grad", "autotune"], "fwd"),
-    (["plan"], "rand"),
-])
-def test_kernels_on_cpu(emu_lib, cases, order):
-    run_cases(cases, order)
+def _start(cases, order):
+    return subprocess.Popen([sys.executable, os.path.join(EMU, "driver.py"), *cases], env=_env(order),
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def _finish(proc, timeout):
+    try:
+        out, err = proc.communicate(timeout=timeout)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        out, err = proc.communicate()
+        raise AssertionError(f"timed out\n{out[-6000:]}")
+    text = out + "\n".join(l for l in err.splitlines() if "makecontext" not in l)
+    assert proc.returncode == 0 and "[emu] all passed" in out, text[-6000:]
+    return text
+
+
+def run_cases(cases, order="fwd", timeout=900):
+    return _finish(_start(cases, order), timeout)
+
+
+GROUPS = [
+    (("tiny", "edges", "config0", "multirobot", "fallback_eval"), "rev"),
+    (("crop", "dense", "multirobot_large"), "rand"),
+    (("many_chunks", "two_level"), "fwd"),
+    (("batch", "batch_resident", "batch_mixed_radius"), "rand"),
+    (("traj_value_grad", "autotune"), "fwd"),
+    (("plan",), "rand"),
+]
+
+
+@pytest.fixture(scope="module")
+def running(emu_lib):
+    """All groups start at once, each in its own process (one core each)."""
+    procs = {g: _start(list(g[0]), g[1]) for g in GROUPS}
+    yield procs
+    for p in procs.values():
+        if p.poll() is None:
+            p.kill()
+            p.communicate()
+
+
+@pytest.mark.parametrize("group", GROUPS, ids=["+".join(g[0]) for g in GROUPS])
+def test_kernels_on_cpu(running, group):
+    _finish(running[group], timeout=1200)
 
 
 @pytest.mark.skipif(os.environ.get("PCT_EMU_FULL") != "1", reason="full-size map on the CPU build takes minutes; "
