@@ -306,13 +306,32 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
     r = dict(scenes.ROBOT_TABLE1)
     cost, keep = P.pct_eval_traversability(G, Cc, g, ext, [r])
     cost = cost[0].contiguous()
-    del Cc
     layers = [int(v) for v in np.flatnonzero(keep[0].cpu().numpy())]
 
     def centre_start(cT0, eG0):
         ys, xs = np.nonzero((cT0 < r["c_barrier"]) & (eG0 < 0.5))
         k = int(np.argmin((ys - g["ny"] / 2) ** 2 + (xs - g["nx"] / 2) ** 2))
         return (int(xs[k]), int(ys[k]), 0)
+
+    # sparse storage of the kept slices' unique cells (Sec. III-C)
+    kp = keep[0].contiguous()
+    uq = P.pct_unique_cells(G, Cc, cost, kp, g, ext, r)
+    uts = []
+    for i in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uq = P.pct_unique_cells(G, Cc, cost, kp, g, ext, r)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            uts.append((time.perf_counter() - t0) * 1e3)
+    m = int(uq["cell"].numel())
+    plane = g["nx"] * g["ny"]
+    unique = {"cells": m, "kept_slices": len(layers), "ms": float(np.median(uts)),
+              "dense_bytes": len(layers) * plane * 12, "sparse_bytes": m * 16,
+              "share_of_kept_cells": m / (len(layers) * plane),
+              "bytes_moved": 2 * len(layers) * plane * 24 + m * 28}
+    unique["moved_gbs"] = unique["bytes_moved"] / (unique["ms"] * 1e-3) / 1e9
+    del uq, Cc
 
     s = centre_start(cost[layers[0]].cpu().numpy(), G[layers[0]].cpu().numpy())
     dist, ws, info = P.pct_plan_distance(cost, G, g, ext, r, layers, s)
@@ -344,7 +363,8 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
            "slices": int(ext.n_slices), "layers": len(layers), "nodes": nodes, "reached": reached,
            "rounds": info["rounds"], "tiles_processed": info["tiles"], "distance_ms": ms_dist,
            "nodes_per_s": nodes / (ms_dist * 1e-3), "path_ms": float(np.median(ptimes)),
-           "path_nodes": int(path.shape[0]), "goal_cost": float(d[goal[2], goal[1], goal[0]])}
+           "path_nodes": int(path.shape[0]), "goal_cost": float(d[goal[2], goal[1], goal[0]]),
+           "unique_cells": unique}
     if cpu:
         import oracle
         log("path search: oracle pipeline and Dijkstra")

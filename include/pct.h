@@ -384,6 +384,32 @@ pct_status pct_plan_path(const double* d_dist, const pct_grid* grid, int32_t n_l
                          int32_t s_layer, int32_t gx, int32_t gy, int32_t g_layer, int32_t* d_path, int32_t max_len,
                          int32_t* h_len, void* d_ws, size_t ws_bytes, void* stream);
 
+/* ---- sparse storage of the simplified tomogram (Sec. III-C) ----
+ * Only the unique cells of the kept slices: for kept slice k, with p the
+ * last kept slice below it (none for the first), cell c is unique when
+ * c^T_k < c^B, and (no p, or e^G_k > e^G_p, or c^T_k < c^T_p), and (k is the
+ * last slice, or e^G_{k+1} > e^G_k, or c^T_k < c^T_{k+1}) - Eqs. (8)-(9), the
+ * cells that make a slice kept. */
+
+/* Workspace bytes for pct_unique_cells on this grid and extent. */
+size_t pct_unique_workspace_bytes(const pct_grid* grid, const pct_extent* extent);
+
+/* The unique cells of the kept slices, slice after slice in increasing
+ * order, cells in raster order (index y * nx + x): d_cell int32, and
+ * d_ground_out, d_ceil_out, d_cost_out float32 (e^G, e^C, c^T of the cell
+ * in its slice), each [capacity].  d_ground, d_ceil, d_cost: float32
+ * [N][ny][nx] of one robot; d_keep: uint8 [N] (the slice test's keep flags;
+ * copied to the host).  *h_count = the number of unique cells; h_slice_off
+ * (host [N+1], nullable): slice k's cells are h_slice_off[k] ..
+ * h_slice_off[k+1] (empty for removed slices).  With d_cell null only the
+ * count (and offsets) are produced; PCT_ERR_CAPACITY if d_cell is given and
+ * the count exceeds capacity (*h_count is still set).  Synchronous. */
+pct_status pct_unique_cells(const float* d_ground, const float* d_ceil, const float* d_cost, const uint8_t* d_keep,
+                            const pct_grid* grid, const pct_extent* extent, const pct_robot* h_robot,
+                            int64_t capacity, int32_t* d_cell, float* d_ground_out, float* d_ceil_out,
+                            float* d_cost_out, int64_t* h_slice_off, int64_t* h_count, void* d_ws, size_t ws_bytes,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

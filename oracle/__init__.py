@@ -83,6 +83,10 @@ def lib():
         L.o_plan_path.argtypes = [f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double, f64p, C.c_int, C.c_int,
                                   C.c_int, C.c_int, C.c_int, C.c_int, i32p, C.c_int]
         L.o_plan_path.restype = C.c_int
+        i64p = C.POINTER(C.c_int64)
+        L.o_unique_cells.argtypes = [f32p, f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_double, u8p, C.c_int64, i32p,
+                                     f32p, f32p, f32p, i64p]
+        L.o_unique_cells.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -399,3 +403,24 @@ def plan_path(cT, eG, c_barrier, dist, start, goal, max_len=None):
     if n < 0:
         raise ValueError("bad node or not a distance field")
     return None if n == 0 else path[:n].copy()
+
+
+# ---------------------------------------------------------------------------
+# sparse storage of the unique cells of the kept slices (Sec. III-C)
+
+def unique_cells(eG, eC, cT, c_barrier, keep):
+    """Unique cells of the kept slices: dict of cell [M] int32, ground, ceil,
+    cost [M] float32 and slice_off [N+1] int64 (slice k's cells are
+    slice_off[k] .. slice_off[k+1])."""
+    eG, eC, cT = _f32(eG), _f32(eC), _f32(cT)
+    N, ny, nx = eG.shape
+    kp = np.ascontiguousarray(np.asarray(keep, dtype=np.uint8))
+    off = np.zeros(N + 1, np.int64)
+    args = (_p(eG, C.c_float), _p(eC, C.c_float), _p(cT, C.c_float), N, nx, ny, float(np.float32(c_barrier)),
+            _p(kp, C.c_uint8))
+    m = int(lib().o_unique_cells(*args, 0, None, None, None, None, _p(off, C.c_int64)))
+    out = dict(cell=np.empty(m, np.int32), ground=np.empty(m, np.float32), ceil=np.empty(m, np.float32),
+               cost=np.empty(m, np.float32), slice_off=off)
+    lib().o_unique_cells(*args, m, _p(out["cell"], C.c_int32), _p(out["ground"], C.c_float),
+                         _p(out["ceil"], C.c_float), _p(out["cost"], C.c_float), _p(off, C.c_int64))
+    return out

@@ -1016,3 +1016,44 @@ int o_plan_path(const float* cT, const float* eG, int L, int nx, int ny, double 
         }
     return len;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III-C, closing remark: the simplified tomogram stored sparsely, as
+ * the unique cells of the kept slices only.  For kept slice k, with p the
+ * last kept slice below it (none for the first), cell c is unique when
+ * (Eqs. (8)-(9)) c^T_k < c^B, and (p is none, or e_k > e_p, or
+ * c_k < c_p), and (k is the last slice, or e_{k+1} > e_k, or c_k < c_{k+1}).
+ * Slices are taken in increasing order and cells in raster order; each
+ * unique cell is stored as its cell index and its e^G, e^C, c^T.  Here c^T
+ * is FP32 (the comparisons are exact either way).  slice_off [N+1] receives
+ * the start of each slice's run (removed slices have empty runs).  Returns
+ * the number of unique cells; arrays are written only up to capacity. */
+int64_t o_unique_cells(const float* eG, const float* eC, const float* cT, int N, int nx, int ny, double cB,
+                       const uint8_t* keep, int64_t capacity, int32_t* cell, float* g_out, float* c_out,
+                       float* t_out, int64_t* slice_off) {
+    const int64_t plane = (int64_t)nx * ny;
+    int64_t m = 0;
+    int p = -1;
+    for (int k = 0; k < N; ++k) {
+        slice_off[k] = m;
+        if (!keep[k]) continue;
+        for (int64_t c = 0; c < plane; ++c) {
+            const double ck = cT[k * plane + c];
+            if (!(ck < cB)) continue;
+            const double ek = eG[k * plane + c];
+            int lower = p < 0 || ek > (double)eG[p * plane + c] || ck < (double)cT[p * plane + c];
+            int upper = k == N - 1 || (double)eG[(k + 1) * plane + c] > ek || ck < (double)cT[(k + 1) * plane + c];
+            if (!(lower && upper)) continue;
+            if (m < capacity) {
+                cell[m] = (int32_t)c;
+                g_out[m] = eG[k * plane + c];
+                c_out[m] = eC[k * plane + c];
+                t_out[m] = cT[k * plane + c];
+            }
+            ++m;
+        }
+        p = k;
+    }
+    slice_off[N] = m;
+    return m;
+}

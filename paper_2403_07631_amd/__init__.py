@@ -252,6 +252,43 @@ def pct_plan_path(dist, grid, start, goal, workspace, max_len=None):
     return None if n.value == 0 else path[:n.value]
 
 
+# --------------------------------------------------------------------- sparse storage
+
+def pct_unique_cells(ground, ceil, cost, keep, grid, extent: pct_extent, robot, workspace=None):
+    """The unique cells of the kept slices (Sec. III-C): returns dict of
+    cell int32 [M], ground, ceil, cost float32 [M] (on the device) and
+    slice_off int64 [N+1] (host numpy)."""
+    import numpy as np
+    g, rb = grid_struct(grid), robot_struct(robot)
+    N = extent.n_slices
+    dev = cost.device
+    for t in (ground, ceil, cost):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (N, g.ny, g.nx)):
+            raise ValueError("ground/ceil/cost must be contiguous CUDA float32 [N, ny, nx]")
+    if not (keep.is_cuda and keep.dtype == torch.uint8 and keep.numel() == N):
+        raise ValueError("keep must be a CUDA uint8 [N] tensor")
+    need = lib().pct_unique_workspace_bytes(C.byref(g), C.byref(extent))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    off = np.zeros(N + 1, np.int64)
+    offp = off.ctypes.data_as(C.POINTER(C.c_int64))
+    m = C.c_int64()
+    keep = keep.contiguous()
+    _check("pct_unique_cells",
+           lib().pct_unique_cells(_ptr(ground), _ptr(ceil), _ptr(cost), _ptr(keep), C.byref(g), C.byref(extent),
+                                  C.byref(rb), 0, None, None, None, None, offp, C.byref(m), _ptr(ws), ws.numel(),
+                                  _stream(dev)))
+    M = int(m.value)
+    out = dict(cell=torch.empty(M, dtype=torch.int32, device=dev), ground=torch.empty(M, dtype=torch.float32, device=dev),
+               ceil=torch.empty(M, dtype=torch.float32, device=dev), cost=torch.empty(M, dtype=torch.float32, device=dev))
+    if M > 0:
+        _check("pct_unique_cells",
+               lib().pct_unique_cells(_ptr(ground), _ptr(ceil), _ptr(cost), _ptr(keep), C.byref(g), C.byref(extent),
+                                      C.byref(rb), M, _ptr(out["cell"]), _ptr(out["ground"]), _ptr(out["ceil"]),
+                                      _ptr(out["cost"]), offp, C.byref(m), _ptr(ws), ws.numel(), _stream(dev)))
+    out["slice_off"] = off
+    return out
+
+
 # --------------------------------------------------------------------- trajectory cost
 
 def _wp(wp, slices):

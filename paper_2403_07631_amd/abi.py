@@ -80,6 +80,8 @@ def load(path):
         "pct_plan_distance": ([vp, vp, G, E, Rb, vp, i32, i32, i32, i32, C.c_double, vp, vp, sz, C.POINTER(i32),
                                C.POINTER(i64), vp], i32),
         "pct_plan_path": ([vp, G, i32, i32, i32, i32, i32, i32, i32, vp, i32, C.POINTER(i32), vp, sz, vp], i32),
+        "pct_unique_workspace_bytes": ([G, E], sz),
+        "pct_unique_cells": ([vp, vp, vp, vp, G, E, Rb, i64, vp, vp, vp, vp, vp, C.POINTER(i64), vp, sz, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

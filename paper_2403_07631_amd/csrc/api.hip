@@ -10,6 +10,7 @@
 
 #include "pct_internal.h"
 #include "plan_internal.h"
+#include "unique_internal.h"
 
 namespace pct {
 
@@ -766,6 +767,48 @@ pct_status pct_plan_path(const double* d_dist, const pct_grid* grid, int32_t n_l
     if (len < 0) return fail(PCT_ERR_ARG, "d_dist is not a distance field of this graph");
     *h_len = len;
     return PCT_OK;
+}
+
+size_t pct_unique_workspace_bytes(const pct_grid* grid, const pct_extent* extent) {
+    if (!grid || !extent || grid->nx < 1 || grid->ny < 1 || extent->n_slices < 1) return 0;
+    return unique_ws_bytes(grid->nx, grid->ny, extent->n_slices);
+}
+
+pct_status pct_unique_cells(const float* d_ground, const float* d_ceil, const float* d_cost, const uint8_t* d_keep,
+                            const pct_grid* grid, const pct_extent* extent, const pct_robot* h_robot,
+                            int64_t capacity, int32_t* d_cell, float* d_ground_out, float* d_ceil_out,
+                            float* d_cost_out, int64_t* h_slice_off, int64_t* h_count, void* d_ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    if (!h_count) return fail(PCT_ERR_ARG, "h_count is null");
+    if (capacity < 0) return fail(PCT_ERR_ARG, "capacity must be >= 0");
+    const int N = extent->n_slices;
+    if (N == 0) {
+        *h_count = 0;
+        if (h_slice_off) h_slice_off[0] = 0;
+        return PCT_OK;
+    }
+    if (!d_ground || !d_ceil || !d_cost || !d_keep) return fail(PCT_ERR_ARG, "device pointers are null");
+    if (d_cell && (!d_ground_out || !d_ceil_out || !d_cost_out))
+        return fail(PCT_ERR_ARG, "with d_cell, the three value outputs are required");
+    const size_t need = unique_ws_bytes(grid->nx, grid->ny, N);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "unique-cell workspace too small: %zu < %zu", ws_bytes,
+                                              need);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> keep((size_t)N);
+    PCT_HIP(hipMemcpyAsync(keep.data(), d_keep, (size_t)N, hipMemcpyDeviceToHost, s));
+    PCT_HIP(hipStreamSynchronize(s));
+    long long count = 0;
+    st = launch_unique(d_ground, d_ceil, d_cost, grid->nx, grid->ny, N, h_robot->c_barrier, keep.data(), capacity,
+                       d_cell, d_ground_out, d_ceil_out, d_cost_out, (long long*)h_slice_off, &count, d_ws, s);
+    *h_count = count;
+    return st;
 }
 
 }  // extern "C"

@@ -475,26 +475,6 @@ __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, u
 // wavefront reductions and atomics per cell.
 constexpr int kSimpCells = 4;
 
-// VEC: the slice planes of ground and cost start on 16-byte boundaries and
-// a lane's four cells are 16-byte aligned, so full groups load as float4.
-template <bool VEC>
-__device__ __forceinline__ void load_cells(const float* __restrict__ a, const float* __restrict__ b, long long off,
-                                           int nact, float fa, float fb, float* va, float* vb) {
-    if (VEC && nact == kSimpCells) {
-        const float4 x = *(const float4*)(a + off);
-        const float4 y = *(const float4*)(b + off);
-        va[0] = x.x; va[1] = x.y; va[2] = x.z; va[3] = x.w;
-        vb[0] = y.x; vb[1] = y.y; vb[2] = y.z; vb[3] = y.w;
-        return;
-    }
-#pragma unroll
-    for (int c = 0; c < kSimpCells; ++c) {
-        va[c] = c < nact ? a[off + c] : fa;
-        vb[c] = c < nact ? b[off + c] : fb;
-    }
-}
-
-template <bool VEC>
 __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ ground, const float* __restrict__ cost,
                                                  long long plane, int N, float cB, int W, int* __restrict__ maxp0,
                                                  unsigned* __restrict__ urun, long long cell0, int nact) {
@@ -502,16 +482,23 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
     const int lane = threadIdx.x & 63;
     float ek[CPT], ck[CPT], eprev[CPT];
     int p0[CPT];
-    load_cells<VEC>(ground, cost, cell0, nact, -INFINITY, cB, ek, ck);
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
+        const bool act = c < nact;
+        ek[c] = act ? ground[cell0 + c] : -INFINITY;
+        ck[c] = act ? cost[cell0 + c] : cB;
         eprev[c] = -INFINITY;
         p0[c] = 0;
     }
     for (int k = 0; k < N; ++k) {
         float ek1[CPT], ck1[CPT];
         const long long nb = (long long)(k + 1) * plane + cell0;
-        load_cells<VEC>(ground, cost, nb, k + 1 < N ? nact : 0, -INFINITY, cB, ek1, ck1);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const bool ld = k + 1 < N && c < nact;
+            ek1[c] = ld ? ground[nb + c] : -INFINITY;
+            ck1[c] = ld ? cost[nb + c] : cB;
+        }
         int mloc = -1, pminloc = 0x7fffffff;
         bool runA[CPT];
 #pragma unroll
@@ -551,7 +538,6 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
     }
 }
 
-template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__ ground, const float* __restrict__ cost,
                                                        const int nx, const int ny, const int N, const float cB,
                                                        const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun) {
@@ -559,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__
     const long long cell0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * kSimpCells;
     const long long left = plane - cell0;
     const int nact = left <= 0 ? 0 : (left < kSimpCells ? (int)left : kSimpCells);
-    simp_flags_cells<VEC>(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact);
+    simp_flags_cells(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact);
 }
 
 __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
@@ -619,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restr
     const int N = jb.p.N, W = (N + 31) / 32;
     int* maxp0 = (int*)(ws + jb.ws_off);
     unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    simp_flags_cells<false>(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
+    simp_flags_cells(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
                      nact > 0 ? cell0 : 0, nact);
 }
 
@@ -747,13 +733,8 @@ pct_status launch_simplify(const float* ground, const float* cost, const EvalPar
                        maxp0, urun, p.N, W);
     PCT_LAUNCH_CHECK();
     const long long blocks = (p.plane + (long long)kBlock * kSimpCells - 1) / ((long long)kBlock * kSimpCells);
-    const bool vec = p.plane % 4 == 0 && ((uintptr_t)ground & 15) == 0 && ((uintptr_t)cost & 15) == 0;
-    if (vec)
-        hipLaunchKernelGGL(k_simp_flags<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny, p.N,
-                           p.cB, W, maxp0, urun);
-    else
-        hipLaunchKernelGGL(k_simp_flags<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny,
-                           p.N, p.cB, W, maxp0, urun);
+    hipLaunchKernelGGL(k_simp_flags, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny, p.N, p.cB, W,
+                       maxp0, urun);
     PCT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_keep_chain, dim3(1), dim3(64), 0, s, maxp0, urun, p.N, W, keep);
     PCT_LAUNCH_CHECK();

@@ -579,6 +579,54 @@ def case_plan():
     plan_run(cT, np.zeros_like(cT), [0], (0, 0, 0), [(0, 0, 0)], "single cell")
 
 
+def unique_run(eG, eC, cT, keep, what):
+    """Unique cells of the kept slices against the oracle's, bit for bit."""
+    N, ny, nx = eG.shape
+    g = grid_s(dict(x0=0.0, y0=0.0, res=0.1, nx=nx, ny=ny, slice_dz=0.3))
+    e = abi.pct_extent(0.0, 1.0, N, 0, 0, 0)
+    r = robot()
+    rb = robot_s(r)
+    bufs = [Buf.of(np.ascontiguousarray(a, np.float32)) for a in (eG, eC, cT)]
+    kb = Buf.of(np.ascontiguousarray(np.asarray(keep, np.uint8)))
+    ws = Buf(L.pct_unique_workspace_bytes(C.byref(g), C.byref(e)))
+    off = np.zeros(N + 1, np.int64)
+    m = C.c_int64()
+    offp = off.ctypes.data_as(C.POINTER(C.c_int64))
+    check("unique count", L.pct_unique_cells(*[P(b) for b in bufs], P(kb), C.byref(g), C.byref(e), C.byref(rb), 0,
+                                             None, None, None, None, offp, C.byref(m), P(ws), ws.nbytes, None))
+    M = m.value
+    ref = oracle.unique_cells(eG, eC, cT, r["c_barrier"], keep)
+    assert M == len(ref["cell"]), f"{what}: {M} unique cells, oracle {len(ref['cell'])}"
+    assert np.array_equal(off, ref["slice_off"]), f"{what}: slice offsets differ"
+    if M > 0:
+        outs = [Buf(4 * M) for _ in range(4)]
+        if M > 1:
+            st = L.pct_unique_cells(*[P(b) for b in bufs], P(kb), C.byref(g), C.byref(e), C.byref(rb), M - 1,
+                                    *[P(o) for o in outs], offp, C.byref(m), P(ws), ws.nbytes, None)
+            assert st == abi.PCT_ERR_CAPACITY and m.value == M, f"{what}: capacity check"
+        check("unique", L.pct_unique_cells(*[P(b) for b in bufs], P(kb), C.byref(g), C.byref(e), C.byref(rb), M,
+                                           *[P(o) for o in outs], offp, C.byref(m), P(ws), ws.nbytes, None))
+        assert np.array_equal(outs[0].get(M, np.int32), ref["cell"]), f"{what}: cells differ"
+        for o, name in zip(outs[1:], ("ground", "ceil", "cost")):
+            assert np.array_equal(bits(o.get(M, np.float32)), bits(ref[name])), f"{what}: {name} differs"
+    say(f"unique cells {what} {N}x{ny}x{nx}: {M} cells in {int(np.count_nonzero(keep))} kept slices, bit-exact")
+
+
+def case_unique():
+    """Sparse storage of the kept slices' unique cells: an oracle-evaluated
+    building (ragged last block), a random keep list, no kept slice."""
+    sc = scenes.multistorey_scene(44, 9.3, 7.1, 250_000, n_floors=3)
+    tm = oracle.tomogram(sc.points, sc.grid)
+    r = robot()
+    cT = oracle.evaluate(tm["ground"], tm["ceil"], sc.grid["res"], r)
+    keep = oracle.simplify(tm["ground"], cT, r["c_barrier"])
+    c32 = cT.astype(np.float32)
+    unique_run(tm["ground"], tm["ceil"], c32, keep, "building")
+    rng = np.random.default_rng(9)
+    unique_run(tm["ground"], tm["ceil"], c32, rng.random(len(keep)) < 0.5, "random keep list")
+    unique_run(tm["ground"], tm["ceil"], c32, np.zeros(len(keep), bool), "nothing kept")
+
+
 CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}
 
 if __name__ == "__main__":

@@ -142,6 +142,7 @@ inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mas
 }
 inline int emu_readfirstlane(int v) { return emu::from_bits<int>(emu::wave_op(emu::OP_READFIRSTLANE, emu::to_bits(v), 0, 0)); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+inline int __popc(unsigned v) { return __builtin_popcount(v); }
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 #define __builtin_amdgcn_update_dpp emu_update_dpp
 #define __builtin_nontemporal_store(v, p) (void)(*(p) = (v))

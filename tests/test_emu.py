@@ -64,7 +64,7 @@ GROUPS = [
     (("many_chunks", "two_level"), "fwd"),
     (("batch", "batch_resident", "batch_mixed_radius"), "rand"),
     (("traj_value_grad", "autotune"), "fwd"),
-    (("plan",), "rand"),
+    (("plan", "unique"), "rand"),
 ]
 
 
