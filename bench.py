@@ -331,7 +331,7 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
               "share_of_kept_cells": m / (len(layers) * plane),
               "bytes_moved": 2 * len(layers) * plane * 24 + m * 28}
     unique["moved_gbs"] = unique["bytes_moved"] / (unique["ms"] * 1e-3) / 1e9
-    del uq, Cc
+    del uq
 
     s = centre_start(cost[layers[0]].cpu().numpy(), G[layers[0]].cpu().numpy())
     dist, ws, info = P.pct_plan_distance(cost, G, g, ext, r, layers, s)
@@ -356,6 +356,44 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
         torch.cuda.synchronize()
         if i >= warmup:
             ptimes.append((time.perf_counter() - t0) * 1e3)
+    # a streaming scan: 200 k new points into the map, re-evaluated around
+    # them, against rebuilding and re-evaluating the union
+    rng = np.random.default_rng(12)
+    scan = np.ascontiguousarray(np.column_stack([rng.uniform(40.0, 46.0, 200_000), rng.uniform(55.0, 61.0, 200_000),
+                                                 rng.uniform(0.0, 14.0, 200_000)]), np.float32)
+    scan_t = torch.from_numpy(scan).to(dev)
+    union_t = torch.cat([xyz, scan_t]).contiguous()
+    grow = P.pct_kernel_radius(r, g["res"]) + 2
+
+    def incremental():
+        ext_i = P.pct_extent(ext.z_min, ext.z_max, ext.n_slices, 0, ext.n_used, ext.n_dropped)
+        bb = P.pct_tomogram_insert(scan_t, g, ext_i, G, Cc2, id_base=int(xyz.shape[0]))
+        P.pct_eval_traversability_window(G, Cc2, g, ext_i, r, (bb[0] - grow, bb[1] - grow, bb[2] + 1 + grow,
+                                                                bb[3] + 1 + grow), cost, kp)
+        return bb
+
+    def rebuild():
+        eu = P.pct_tomogram_extent(union_t, g)
+        Gu, Cu, _, _ = P.pct_build_tomogram(union_t, g, eu)
+        P.pct_eval_traversability(Gu, Cu, g, eu, [r])
+
+    def wall(fn):
+        ts = []
+        for i in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if i >= warmup:
+                ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts))
+
+    Cc2 = Cc
+    bb = incremental()
+    insert = {"workload": "200 k points of a scan (6 m x 6 m x 14 m box) into the building",
+              "points": int(scan.shape[0]), "cell_box": list(bb), "incremental_ms": wall(incremental),
+              "rebuild_ms": wall(rebuild)}
+    insert["ratio"] = insert["rebuild_ms"] / insert["incremental_ms"]
     nodes = len(layers) * g["nx"] * g["ny"]
     out = {"workload": "six-storey building without beams, 100 m x 100 m at 0.1 m (1000 x 1000 cells), 26.4 M points, "
                        "slice interval 0.3 m, Table I quadruped; search from the ground-floor centre over the "
@@ -364,7 +402,7 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
            "rounds": info["rounds"], "tiles_processed": info["tiles"], "distance_ms": ms_dist,
            "nodes_per_s": nodes / (ms_dist * 1e-3), "path_ms": float(np.median(ptimes)),
            "path_nodes": int(path.shape[0]), "goal_cost": float(d[goal[2], goal[1], goal[0]]),
-           "unique_cells": unique}
+           "unique_cells": unique, "insert": insert}
     if cpu:
         import oracle
         log("path search: oracle pipeline and Dijkstra")

@@ -410,6 +410,40 @@ pct_status pct_unique_cells(const float* d_ground, const float* d_ceil, const fl
                             float* d_cost_out, int64_t* h_slice_off, int64_t* h_count, void* d_ws, size_t ws_bytes,
                             void* stream);
 
+/* ---- incremental updates for streaming scans ---- */
+
+/* Workspace bytes for pct_tomogram_insert of n points. */
+size_t pct_insert_workspace_bytes(int64_t n, const pct_grid* grid);
+
+/* Adds n points (ids id_base .. id_base + n - 1) to an existing tomogram in
+ * place (Sec. III-A applied to the union): every cell-slice takes the higher
+ * ground and the lower ceiling of its stored value and the new points,
+ * equal heights keeping the lower point id, so the result equals a build of
+ * the union of the old and new points (with the new ids) bit for bit.  The
+ * planes must not change: PCT_ERR_ARG if an in-grid new point lies below
+ * z_min or at or above the top plane (rebuild instead); nothing is written
+ * then.  extent (in/out): n_used, n_dropped and z_max are updated.  d_ground,
+ * d_ceil, d_arg_ground, d_arg_ceil: as written by pct_build_tomogram (the
+ * ids nullable together).  h_bbox (host [4], nullable): the cells the new
+ * points fell in, {x_min, y_min, x_max, y_max} (x_max < x_min when none).
+ * Synchronous.  Only tiles that receive points are read and written. */
+pct_status pct_tomogram_insert(const float* d_xyz, int64_t n, int32_t id_base, const pct_grid* grid,
+                               pct_extent* extent, float* d_ground, float* d_ceil, int32_t* d_arg_ground,
+                               int32_t* d_arg_ceil, int32_t* h_bbox, void* d_ws, size_t ws_bytes, void* stream);
+
+/* pct_eval_traversability for one robot on the cells [x0, x1) x [y0, y1)
+ * of every slice only (clamped to the grid); the other cells of d_cost are
+ * left as they are.  The window's values are those of a whole-map
+ * evaluation (the same FP32 operations; neighbours outside the window are
+ * read).  After an insertion, the cells whose c^T can change are the new
+ * points' cells grown by the inflation radius plus 2 (the stencil and the
+ * patch).  With d_keep (uint8 [N]) the slice test then runs on the whole
+ * map (workspace as for pct_eval_traversability with one robot). */
+pct_status pct_eval_traversability_window(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                          const pct_extent* extent, const pct_robot* h_robot, int32_t x0, int32_t y0,
+                                          int32_t x1, int32_t y1, float* d_cost, uint8_t* d_keep, void* d_ws,
+                                          size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

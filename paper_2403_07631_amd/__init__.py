@@ -252,6 +252,43 @@ def pct_plan_path(dist, grid, start, goal, workspace, max_len=None):
     return None if n.value == 0 else path[:n.value]
 
 
+# --------------------------------------------------------------------- incremental updates
+
+def pct_tomogram_insert(xyz, grid, extent: pct_extent, ground, ceil, arg_ground=None, arg_ceil=None, id_base=0,
+                        workspace=None):
+    """Adds the points ``xyz`` [n, 3] (ids id_base ..) to the tomogram in
+    place; ``extent`` is updated.  Returns the cell box (x_min, y_min,
+    x_max, y_max) of the new points (x_max < x_min when none)."""
+    g = grid_struct(grid)
+    if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.is_contiguous() and xyz.dim() == 2
+            and xyz.shape[1] == 3):
+        raise ValueError("xyz must be a contiguous CUDA float32 [n, 3] tensor")
+    n = xyz.shape[0]
+    need = lib().pct_insert_workspace_bytes(n, C.byref(g))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, xyz.device)
+    bb = (C.c_int32 * 4)()
+    _check("pct_tomogram_insert",
+           lib().pct_tomogram_insert(_ptr(xyz), n, int(id_base), C.byref(g), C.byref(extent), _ptr(ground), _ptr(ceil),
+                                     _ptr(arg_ground), _ptr(arg_ceil), bb, _ptr(ws), ws.numel(),
+                                     _stream(xyz.device)))
+    return tuple(int(v) for v in bb)
+
+
+def pct_eval_traversability_window(ground, ceil, grid, extent: pct_extent, robot, window, cost, keep=None,
+                                   workspace=None):
+    """Re-evaluates c^T of one robot on the cells window = (x0, y0, x1, y1)
+    (half-open) of every slice into ``cost`` [N, ny, nx]; with ``keep``
+    (uint8 [N]) the slice test runs again on the whole map."""
+    g, rb = grid_struct(grid), robot_struct(robot)
+    need = lib().pct_eval_workspace_bytes(C.byref(g), C.byref(extent), 1)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, ground.device)
+    x0, y0, x1, y1 = (int(v) for v in window)
+    _check("pct_eval_traversability_window",
+           lib().pct_eval_traversability_window(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(rb), x0,
+                                                y0, x1, y1, _ptr(cost), _ptr(keep), _ptr(ws), ws.numel(),
+                                                _stream(ground.device)))
+
+
 # --------------------------------------------------------------------- sparse storage
 
 def pct_unique_cells(ground, ceil, cost, keep, grid, extent: pct_extent, robot, workspace=None):

@@ -81,6 +81,9 @@ def load(path):
                                C.POINTER(i64), vp], i32),
         "pct_plan_path": ([vp, G, i32, i32, i32, i32, i32, i32, i32, vp, i32, C.POINTER(i32), vp, sz, vp], i32),
         "pct_unique_workspace_bytes": ([G, E], sz),
+        "pct_insert_workspace_bytes": ([i64, G], sz),
+        "pct_tomogram_insert": ([vp, i64, i32, G, E, vp, vp, vp, vp, vp, vp, sz, vp], i32),
+        "pct_eval_traversability_window": ([vp, vp, G, E, Rb, i32, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "pct_unique_cells": ([vp, vp, vp, vp, G, E, Rb, i64, vp, vp, vp, vp, vp, C.POINTER(i64), vp, sz, vp], i32),
     }
     for name, (args, res) in sig.items():

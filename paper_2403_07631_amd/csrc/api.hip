@@ -116,6 +116,10 @@ pct_status make_eval_params(const pct_robot& r, const pct_grid& g, int N, EvalPa
     p.ny = g.ny;
     p.N = N;
     p.plane = (long long)g.nx * g.ny;
+    p.wx0 = 0;
+    p.wy0 = 0;
+    p.wx1 = g.nx;
+    p.wy1 = g.ny;
     p.R = kernel_radius(r, g.res);
     if (p.R > PCT_MAX_KERNEL_RADIUS) return fail(PCT_ERR_CAPACITY, "inflation kernel radius exceeds %d", PCT_MAX_KERNEL_RADIUS);
     p.d_min = r.d_min;
@@ -809,6 +813,108 @@ pct_status pct_unique_cells(const float* d_ground, const float* d_ceil, const fl
                        d_cell, d_ground_out, d_ceil_out, d_cost_out, (long long*)h_slice_off, &count, d_ws, s);
     *h_count = count;
     return st;
+}
+
+size_t pct_insert_workspace_bytes(int64_t n, const pct_grid* grid) {
+    if (!grid || check_grid(grid) != PCT_OK || n < 0) return 0;
+    const GridDev g = make_grid_dev(*grid);
+    return std::max(extent_ws_bytes(std::max<int64_t>(n, 1)) + align_up(4 * sizeof(int)), build_ws_bytes(n, g, true));
+}
+
+pct_status pct_tomogram_insert(const float* d_xyz, int64_t n, int32_t id_base, const pct_grid* grid,
+                               pct_extent* extent, float* d_ground, float* d_ceil, int32_t* d_arg_ground,
+                               int32_t* d_arg_ceil, int32_t* h_bbox, void* d_ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count %lld outside [0, 2^31)", (long long)n);
+    if (id_base < 0 || (int64_t)id_base + n > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point ids exceed int32");
+    if ((d_arg_ground == nullptr) != (d_arg_ceil == nullptr))
+        return fail(PCT_ERR_ARG, "d_arg_ground and d_arg_ceil must both be given or both be null");
+    const int N = extent->n_slices;
+    if (N == 0) return fail(PCT_ERR_ARG, "the tomogram has no slices: build it first");
+    if (!d_ground || !d_ceil) return fail(PCT_ERR_ARG, "output pointers are null");
+    if (n > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    if (plane_count(extent->z_min, extent->z_max, grid->slice_dz, PCT_MAX_SLICES) != N)
+        return fail(PCT_ERR_ARG, "extent does not match the plane rule for this slice_dz");
+    if (h_bbox) h_bbox[0] = h_bbox[1] = 0, h_bbox[2] = h_bbox[3] = -1;
+    if (n == 0) return PCT_OK;
+    const size_t need = pct_insert_workspace_bytes(n, grid);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "insert workspace too small: %zu < %zu", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    const GridDev g = make_grid_dev(*grid);
+    // heights and cells of the new points
+    ExtentDev* d_out = (ExtentDev*)((char*)d_ws + extent_ws_bytes(n) - align_up(sizeof(ExtentDev)));
+    int* d_bb = (int*)((char*)d_ws + extent_ws_bytes(n));
+    st = launch_extent(d_xyz, n, g, d_ws, d_out, s);
+    if (st != PCT_OK) return st;
+    st = launch_cell_bbox(d_xyz, n, g, d_bb, s);
+    if (st != PCT_OK) return st;
+    ExtentDev hx{};
+    int bb[4];
+    PCT_HIP(hipMemcpyAsync(&hx, d_out, sizeof hx, hipMemcpyDeviceToHost, s));
+    PCT_HIP(hipMemcpyAsync(bb, d_bb, sizeof bb, hipMemcpyDeviceToHost, s));
+    PCT_HIP(hipStreamSynchronize(s));
+    if (hx.used > 0) {
+        // the union's planes must be the same: no new point below z_min, none
+        // at or above the top plane
+        const float top = plane_height(extent->z_min, grid->slice_dz, N - 1);
+        if (hx.zmin < extent->z_min || !(hx.zmax < top))
+            return fail(PCT_ERR_ARG, "new heights [%g, %g] leave [z_min %g, top plane %g): the planes change, rebuild",
+                        (double)hx.zmin, (double)hx.zmax, (double)extent->z_min, (double)top);
+        st = launch_build(d_xyz, n, g, extent->z_min, grid->slice_dz, N, d_ground, d_ceil, d_arg_ground, d_arg_ceil,
+                          d_ws, ws_bytes, s, true, id_base);
+        if (st != PCT_OK) return st;
+        extent->z_max = std::max(extent->z_max, hx.zmax);
+        if (h_bbox) {
+            for (int i = 0; i < 4; ++i) h_bbox[i] = bb[i];
+        }
+    }
+    extent->n_used += (int64_t)hx.used;
+    extent->n_dropped += n - (int64_t)hx.used;
+    return PCT_OK;
+}
+
+pct_status pct_eval_traversability_window(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                          const pct_extent* extent, const pct_robot* h_robot, int32_t x0, int32_t y0,
+                                          int32_t x1, int32_t y1, float* d_cost, uint8_t* d_keep, void* d_ws,
+                                          size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    const int N = extent->n_slices;
+    if (N == 0) return PCT_OK;
+    if (!d_ground || !d_ceil || !d_cost) return fail(PCT_ERR_ARG, "device pointers are null");
+    x0 = std::max(x0, 0);
+    y0 = std::max(y0, 0);
+    x1 = std::min(x1, grid->nx);
+    y1 = std::min(y1, grid->ny);
+    if (d_keep && (!d_ws || ws_bytes < eval_ws_bytes(N, 1)))
+        return fail(PCT_ERR_WORKSPACE, "eval workspace too small: %zu < %zu", ws_bytes, eval_ws_bytes(N, 1));
+    hipStream_t s = (hipStream_t)stream;
+    EvalParams p;
+    st = make_eval_params(*h_robot, *grid, N, &p);
+    if (st != PCT_OK) return st;
+    if (x0 < x1 && y0 < y1) {
+        p.wx0 = x0;
+        p.wy0 = y0;
+        p.wx1 = x1;
+        p.wy1 = y1;
+        st = launch_eval(d_ground, d_ceil, p, d_cost, s);
+        if (st != PCT_OK) return st;
+        p.wx0 = 0;
+        p.wy0 = 0;
+        p.wx1 = grid->nx;
+        p.wy1 = grid->ny;
+    }
+    if (d_keep) return launch_simplify(d_ground, d_cost, p, d_keep, d_ws, s);
+    return PCT_OK;
 }
 
 }  // extern "C"

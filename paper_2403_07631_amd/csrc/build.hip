@@ -532,11 +532,37 @@ __device__ __forceinline__ bool rec_less(float za, int ia, float zb, int ib, boo
     return za < zb || (ids && za == zb && ia < ib);
 }
 
-// One cell: sort its heights (ties by point id) and sweep the planes.
+// Merge of a cell-slice's value with the one already stored (insertion
+// into an existing tomogram): the higher ground / lower ceiling wins, equal
+// heights keep the lower point id (-1 only goes with the infinities).
 template <bool IDS>
+__device__ __forceinline__ void merge_old(int64_t o, const float* __restrict__ ground, const float* __restrict__ ceil,
+                                          const int* __restrict__ ag, const int* __restrict__ ac, float& gz, int& gi,
+                                          float& cz, int& ci) {
+    const float og = ground[o], oc = ceil[o];
+    const int oi = IDS ? ag[o] : 0, oj = IDS ? ac[o] : 0;
+    if (og > gz) {
+        gz = og;
+        gi = oi;
+    } else if (og == gz) {
+        gi = min(gi, oi);
+    }
+    if (oc < cz) {
+        cz = oc;
+        ci = oj;
+    } else if (oc == cz) {
+        ci = min(ci, oj);
+    }
+}
+
+// One cell: sort its heights (ties by point id) and sweep the planes.
+// MERGE: combine with the stored values instead of overwriting them (ids
+// are offset by id_base); a cell without records is left as it is.
+template <bool IDS, bool MERGE>
 __device__ void sweep_cell(float* zs, int* is, int n, int ix, int iy, const GridDev& g, float zmin, float ds,
                            int N, float* __restrict__ ground, float* __restrict__ ceil, int* __restrict__ ag,
-                           int* __restrict__ ac) {
+                           int* __restrict__ ac, int id_base) {
+    if (MERGE && n == 0) return;
     for (int a = 1; a < n; ++a) {
         float z = zs[a];
         int id = IDS ? is[a] : 0;
@@ -560,23 +586,26 @@ __device__ void sweep_cell(float* zs, int* is, int n, int ix, int iy, const Grid
             ++j;
             znext = j < n ? zs[j] : INFINITY;
         }
+        float gz = j > 0 ? zs[j - 1] : -INFINITY, cz = znext;
+        int gi = IDS && j > 0 ? is[rs] + id_base : -1, ci = IDS && j < n ? is[j] + id_base : -1;
+        if (MERGE) merge_old<IDS>(o, ground, ceil, ag, ac, gz, gi, cz, ci);
         // streaming stores: the grids are far larger than the caches
-        __builtin_nontemporal_store(j > 0 ? zs[j - 1] : -INFINITY, &ground[o]);
-        __builtin_nontemporal_store(znext, &ceil[o]);
+        __builtin_nontemporal_store(gz, &ground[o]);
+        __builtin_nontemporal_store(cz, &ceil[o]);
         if (IDS) {
-            __builtin_nontemporal_store(j > 0 ? is[rs] : -1, &ag[o]);
-            __builtin_nontemporal_store(j < n ? is[j] : -1, &ac[o]);
+            __builtin_nontemporal_store(gi, &ag[o]);
+            __builtin_nontemporal_store(ci, &ac[o]);
         }
     }
 }
 
 // A cell with more points than the LDS holds: per plane, a block-wide
 // max/min reduction over the tile's records (ties to the lowest id).
-template <bool IDS>
+template <bool IDS, bool MERGE>
 __device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __restrict__ rz,
                           const unsigned* __restrict__ rmeta, const int* __restrict__ rid, int ix, int iy,
                           const GridDev& g, float zmin, float ds, int N, float* __restrict__ ground,
-                          float* __restrict__ ceil, int* __restrict__ ag, int* __restrict__ ac) {
+                          float* __restrict__ ceil, int* __restrict__ ag, int* __restrict__ ac, int id_base) {
     __shared__ float s_gz[kReduceBlock], s_cz[kReduceBlock];
     __shared__ int s_gi[kReduceBlock], s_ci[kReduceBlock];
     const int64_t plane = (int64_t)g.nx * g.ny;
@@ -614,11 +643,14 @@ __device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __r
         }
         if (threadIdx.x == 0) {
             int64_t o = (int64_t)k * plane + (int64_t)iy * g.nx + ix;
-            ground[o] = s_gz[0];
-            ceil[o] = s_cz[0];
+            float gz = s_gz[0], cz = s_cz[0];
+            int gi = IDS && isfinite(gz) ? s_gi[0] + id_base : -1, ci = IDS && isfinite(cz) ? s_ci[0] + id_base : -1;
+            if (MERGE) merge_old<IDS>(o, ground, ceil, ag, ac, gz, gi, cz, ci);
+            ground[o] = gz;
+            ceil[o] = cz;
             if (IDS) {
-                ag[o] = isfinite(s_gz[0]) ? s_gi[0] : -1;
-                ac[o] = isfinite(s_cz[0]) ? s_ci[0] : -1;
+                ag[o] = gi;
+                ac[o] = ci;
             }
         }
         __syncthreads();
@@ -627,11 +659,11 @@ __device__ void huge_cell(unsigned c, unsigned r0, unsigned r1, const float* __r
 
 // One construction tile: records off[tg] .. off[tg+1] of the tile whose
 // position in its grid is tl.  Shared by the single-map and batched kernels.
-template <bool IDS>
+template <bool IDS, bool MERGE = false>
 __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, const float* __restrict__ rz,
                             const unsigned* __restrict__ rmeta, const int* __restrict__ rid, const GridDev& g,
                             float zmin, float ds, int N, float* __restrict__ ground, float* __restrict__ ceil,
-                            int* __restrict__ ag, int* __restrict__ ac) {
+                            int* __restrict__ ag, int* __restrict__ ac, int id_base = 0) {
     constexpr int CAP = IDS ? kReduceCapIds : kReduceCap;
     extern __shared__ unsigned s_mem[];
     const int cells = kBuildTileW * g.th;
@@ -642,6 +674,7 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
 
     const int tx = tl % g.ntx, ty = tl / g.ntx;
     const unsigned r0 = off[tg], r1 = off[tg + 1];
+    if (MERGE && r0 == r1) return;   // an insertion leaves tiles without new points alone
 
     for (int c = threadIdx.x; c < cells; c += kReduceBlock) s_cnt[c] = 0;
     __syncthreads();
@@ -690,7 +723,8 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
         if (c_hi == c_lo + 1 && s_start[c_hi] - g0 > (unsigned)CAP) {
             const int ix = tx * kBuildTileW + (c_lo % kBuildTileW);
             const int iy = ty * g.th + c_lo / kBuildTileW;
-            huge_cell<IDS>((unsigned)c_lo, r0, r1, rz, rmeta, rid, ix, iy, g, zmin, ds, N, ground, ceil, ag, ac);
+            huge_cell<IDS, MERGE>((unsigned)c_lo, r0, r1, rz, rmeta, rid, ix, iy, g, zmin, ds, N, ground, ceil, ag, ac,
+                                  id_base);
         } else {
             for (int c = c_lo + threadIdx.x; c < c_hi; c += kReduceBlock) s_cnt[c] = 0;
             __syncthreads();
@@ -707,8 +741,8 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
                 const int iy = ty * g.th + c / kBuildTileW;
                 if (ix >= g.nx || iy >= g.ny) continue;
                 const unsigned s = s_start[c] - g0;
-                sweep_cell<IDS>(s_z + s, s_id + s, (int)(s_start[c + 1] - s_start[c]), ix, iy, g, zmin, ds, N,
-                                ground, ceil, ag, ac);
+                sweep_cell<IDS, MERGE>(s_z + s, s_id + s, (int)(s_start[c + 1] - s_start[c]), ix, iy, g, zmin, ds,
+                                       N, ground, ceil, ag, ac, id_base);
             }
         }
         __syncthreads();
@@ -716,15 +750,16 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
     }
 }
 
-template <bool IDS>
+template <bool IDS, bool MERGE>
 __global__ __launch_bounds__(kReduceBlock) void k_tile_reduce(const unsigned* __restrict__ off,
                                                         const float* __restrict__ rz,
                                                         const unsigned* __restrict__ rmeta,
                                                         const int* __restrict__ rid, GridDev g, float zmin,
                                                         float ds, int N, float* __restrict__ ground,
                                                         float* __restrict__ ceil, int* __restrict__ ag,
-                                                        int* __restrict__ ac) {
-    reduce_tile<IDS>((int)blockIdx.x, (int)blockIdx.x, off, rz, rmeta, rid, g, zmin, ds, N, ground, ceil, ag, ac);
+                                                        int* __restrict__ ac, int id_base) {
+    reduce_tile<IDS, MERGE>((int)blockIdx.x, (int)blockIdx.x, off, rz, rmeta, rid, g, zmin, ds, N, ground, ceil, ag,
+                            ac, id_base);
 }
 
 inline size_t reduce_lds_bytes(const GridDev& g, bool ids) {
@@ -1020,7 +1055,8 @@ pct_status launch_extent(const float* xyz, int64_t n, const GridDev& g, void* ws
 size_t build_ws_bytes(int64_t n, const GridDev& g, bool ids) { return carve_build_ws(nullptr, n, g, ids).bytes; }
 
 pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmin, float ds, int N, float* ground,
-                        float* ceil, int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes, hipStream_t s) {
+                        float* ceil, int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes, hipStream_t s, bool merge,
+                        int id_base) {
     const bool ids = ag != nullptr;
     BuildWs w = carve_build_ws(ws, n, g, ids);
     if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "build workspace too small: %zu < %zu", ws_bytes, w.bytes);
@@ -1099,13 +1135,66 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
         }
     }
     const size_t rl = reduce_lds_bytes(g, ids);
-    if (ids)
-        hipLaunchKernelGGL(k_tile_reduce<true>, dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
-                           zmin, ds, N, ground, ceil, ag, ac);
+    if (ids && merge)
+        hipLaunchKernelGGL((k_tile_reduce<true, true>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta,
+                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, id_base);
+    else if (merge)
+        hipLaunchKernelGGL((k_tile_reduce<false, true>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta,
+                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, id_base);
+    else if (ids)
+        hipLaunchKernelGGL((k_tile_reduce<true, false>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta,
+                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, 0);
     else
-        hipLaunchKernelGGL(k_tile_reduce<false>, dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta, w.rid, g,
-                           zmin, ds, N, ground, ceil, ag, ac);
+        hipLaunchKernelGGL((k_tile_reduce<false, false>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz,
+                           w.rmeta, w.rid, g, zmin, ds, N, ground, ceil, ag, ac, 0);
     PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+// Bounding box of the cells that the in-grid points of a batch fall in:
+// bb = {x_min, y_min, x_max, y_max}, to be initialised to {INT_MAX, INT_MAX,
+// -1, -1}.
+__global__ __launch_bounds__(256) void k_cell_bbox(const float* __restrict__ xyz, int64_t n, GridDev g,
+                                                   int* __restrict__ bb) {
+    int x0 = 0x7fffffff, y0 = 0x7fffffff, x1 = -1, y1 = -1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        int ix, iy;
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !rasterize(x, y, g, ix, iy)) continue;
+        x0 = min(x0, ix);
+        y0 = min(y0, iy);
+        x1 = max(x1, ix);
+        y1 = max(y1, iy);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        x0 = min(x0, __shfl_xor(x0, o, 64));
+        y0 = min(y0, __shfl_xor(y0, o, 64));
+        x1 = max(x1, __shfl_xor(x1, o, 64));
+        y1 = max(y1, __shfl_xor(y1, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && x1 >= 0) {
+        atomicMin(&bb[0], x0);
+        atomicMin(&bb[1], y0);
+        atomicMax(&bb[2], x1);
+        atomicMax(&bb[3], y1);
+    }
+}
+
+__global__ void k_bbox_init(int* bb) {
+    bb[0] = 0x7fffffff;
+    bb[1] = 0x7fffffff;
+    bb[2] = -1;
+    bb[3] = -1;
+}
+
+pct_status launch_cell_bbox(const float* xyz, int64_t n, const GridDev& g, int* d_bb, hipStream_t s) {
+    hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(1), 0, s, d_bb);
+    PCT_LAUNCH_CHECK();
+    if (n > 0) {
+        const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL(k_cell_bbox, dim3((unsigned)blocks), dim3(256), 0, s, xyz, n, g, d_bb);
+        PCT_LAUNCH_CHECK();
+    }
     return PCT_OK;
 }
 

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(const float* __restrict__ groun
                                                  const EvalParams p, float* __restrict__ cost) {
     extern __shared__ float smem[];
     const int k = blockIdx.z;
-    const int tx0 = blockIdx.x * TW, ty0 = blockIdx.y * TH;
+    const int tx0 = p.wx0 + blockIdx.x * TW, ty0 = p.wy0 + blockIdx.y * TH;
     const int rp = p.rp;
     const int HG = R + rp + 1, HF = R + rp;
     const int WG = TW + 2 * HG, HGt = TH + 2 * HG;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(const float* __restrict__ groun
 #pragma unroll
         for (int a = 1; a <= R; ++a)
             v = fmaxf(v, fmaxf(sV[(a * TH + y) * WC + x + R - a], sV[(a * TH + y) * WC + x + R + a]));
-        if (gx < nx && gy < ny) cost[(long long)k * p.plane + (long long)gy * nx + gx] = v;
+        if (gx < p.wx1 && gy < p.wy1) cost[(long long)k * p.plane + (long long)gy * nx + gx] = v;
     }
 }
 
@@ -209,11 +209,11 @@ __device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground
     const int k = t0 / sg.n_sy;
     const int lane = threadIdx.x & 63;
     const int nx = p.nx, ny = p.ny;
-    const int x = sx * OUTW - HX + lane;
+    const int x = p.wx0 + sx * OUTW - HX + lane;
     const bool xin = x >= 0 && x < nx;
     const unsigned xc = (unsigned)min(max(x, 0), nx - 1);
-    const bool xout = lane >= HX && lane < HX + OUTW && x < nx;
-    const int Y0 = sy * sg.rows, Y1 = min(ny, Y0 + sg.rows);
+    const bool xout = lane >= HX && lane < HX + OUTW && x < p.wx1;
+    const int Y0 = p.wy0 + sy * sg.rows, Y1 = min(p.wy1, Y0 + sg.rows);
     const float* gk = ground + (long long)k * p.plane;
     const float* ck = ceil + (long long)k * p.plane;
     float* ok = cost + (long long)k * p.plane;
@@ -391,9 +391,10 @@ int tuned_rows(const EvalParams& p) {
 // halved while the strips give fewer than 16384 wavefronts, down to 32).
 StripGeom strip_geom(const EvalParams& p, int rows = 0) {
     const int outw = 64 - 2 * (p.R + 2);
+    const int wnx = p.wx1 - p.wx0, wny = p.wy1 - p.wy0;
     StripGeom g{};
-    g.n_sx = (p.nx + outw - 1) / outw;
-    auto work = [&](int r) { return (long long)p.N * g.n_sx * ((p.ny + r - 1) / r); };
+    g.n_sx = (wnx + outw - 1) / outw;
+    auto work = [&](int r) { return (long long)p.N * g.n_sx * ((wny + r - 1) / r); };
     if (rows <= 0) rows = tuned_rows(p);
     if (rows > 0) {
         g.rows = rows;
@@ -401,7 +402,7 @@ StripGeom strip_geom(const EvalParams& p, int rows = 0) {
         g.rows = kStripRows;
         while (g.rows > 32 && work(g.rows) < 16384) g.rows /= 2;
     }
-    g.n_sy = (p.ny + g.rows - 1) / g.rows;
+    g.n_sy = (wny + g.rows - 1) / g.rows;
     g.n_work = (int)work(g.rows);
     return g;
 }
@@ -434,7 +435,7 @@ pct_status launch_eval_r(const float* ground, const float* ceil, const EvalParam
         hipError_t e = hipFuncSetAttribute((const void*)k_eval<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return fail(PCT_ERR_DEVICE, "eval LDS request of %zu bytes refused: %s", lds, hipGetErrorString(e));
     }
-    dim3 grid((p.nx + TW - 1) / TW, (p.ny + TH - 1) / TH, p.N);
+    dim3 grid((p.wx1 - p.wx0 + TW - 1) / TW, (p.wy1 - p.wy0 + TH - 1) / TH, p.N);
     hipLaunchKernelGGL(k_eval<R>, grid, dim3(kBlock), lds, s, ground, ceil, p, cost);
     PCT_LAUNCH_CHECK();
     return PCT_OK;

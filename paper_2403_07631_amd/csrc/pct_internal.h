@@ -103,6 +103,7 @@ struct EvalParams {
     float As;    // gentle cost  alpha_s / (theta_s * 2r)^2 * (dx^2 + dy^2)
     float Ab;    // step cost    alpha_b / (theta_b * 2r)^2 * max(dx^2, dy^2)
     int rp, kp;  // patch radius, count threshold floor(theta_p * P)
+    int wx0, wy0, wx1, wy1;  // cells evaluated: [wx0, wx1) x [wy0, wy1) (the whole map unless a window is asked)
     float K[kKmax][kKmax];  // K[a][j]: Eq. (6) weight at horizontal offset a, vertical offset j
 };
 
@@ -114,9 +115,10 @@ pct_status launch_extent(const float* xyz, int64_t n, const GridDev& g, void* ws
 size_t extent_ws_bytes(int64_t n);
 
 size_t build_ws_bytes(int64_t n, const GridDev& g, bool ids);
+pct_status launch_cell_bbox(const float* xyz, int64_t n, const GridDev& g, int* d_bb, hipStream_t s);
 pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmin, float ds, int N,
                         float* ground, float* ceil, int32_t* ag, int32_t* ac, void* ws, size_t ws_bytes,
-                        hipStream_t s);
+                        hipStream_t s, bool merge = false, int id_base = 0);
 
 size_t eval_ws_bytes(int N, int n_robots);
 pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,

@@ -627,6 +627,66 @@ def case_unique():
     unique_run(tm["ground"], tm["ceil"], c32, np.zeros(len(keep), bool), "nothing kept")
 
 
+def case_insert():
+    """Insertion into an existing tomogram equals the build of the union
+    (heights and ids, bit for bit, and the oracle's); the re-evaluated
+    window makes the cost map equal a whole-map evaluation of the union;
+    heights that would move the planes are refused."""
+    sc = scenes.multistorey_scene(45, 13.3, 9.7, 300_000, n_floors=2)
+    g = sc.grid
+    pts = np.ascontiguousarray(sc.points, np.float32)
+    rng = np.random.default_rng(10)
+    # a scan of a box on the ground floor: new points within the height range
+    m = 40_000
+    bx = np.column_stack([rng.uniform(3.0, 4.7, m), rng.uniform(2.0, 3.3, m), rng.uniform(0.0, 0.9, m)])
+    new = np.ascontiguousarray(bx, np.float32)
+    xa = Buf.of(pts)
+    e = extent(xa, len(pts), g)
+    G, Cc, aG, aC = build(xa, len(pts), g, e, True)
+    N = e.n_slices
+    cells = N * g["nx"] * g["ny"]
+    r = robot()
+    cost, kp = evaluate(G, Cc, g, e, [r])
+    gs = grid_s(g)
+    xb = Buf.of(new)
+    ws = Buf(L.pct_insert_workspace_bytes(len(new), C.byref(gs)))
+    bb = (C.c_int32 * 4)()
+    check("insert", L.pct_tomogram_insert(P(xb), len(new), len(pts), C.byref(gs), C.byref(e), P(G), P(Cc), P(aG),
+                                          P(aC), bb, P(ws), ws.nbytes, None))
+    union = np.ascontiguousarray(np.concatenate([pts, new]), np.float32)
+    xu = Buf.of(union)
+    eu = extent(xu, len(union), g)
+    assert (eu.n_slices, eu.n_used, eu.n_dropped, np.float32(eu.z_max)) == (e.n_slices, e.n_used, e.n_dropped,
+                                                                              np.float32(e.z_max)), "extent"
+    Gu, Cu, aGu, aCu = build(xu, len(union), g, eu, True)
+    for a, b, name in ((G, Gu, "ground"), (Cc, Cu, "ceil"), (aG, aGu, "ids"), (aC, aCu, "ceil ids")):
+        dt = np.int32 if "ids" in name else np.float32
+        assert np.array_equal(bits(a.get(cells, dt)), bits(b.get(cells, dt))), f"insert: {name} differs from the union"
+    tm = oracle.tomogram(union, g)
+    assert np.array_equal(bits(G.get(cells, np.float32)), bits(tm["ground"].ravel())), "insert: oracle ground"
+    assert np.array_equal(aG.get(cells, np.int32), tm["arg_ground"].ravel()), "insert: oracle ids"
+    # window re-evaluation
+    rr = C.c_int32()
+    check("radius", L.pct_kernel_radius(C.byref(robot_s(r)), C.c_float(g["res"]), C.byref(rr)))
+    grow = rr.value + 2
+    win = (bb[0] - grow, bb[1] - grow, bb[2] + 1 + grow, bb[3] + 1 + grow)
+    rb = robot_s(r)
+    ews = Buf(L.pct_eval_workspace_bytes(C.byref(gs), C.byref(e), 1))
+    check("window", L.pct_eval_traversability_window(P(G), P(Cc), C.byref(gs), C.byref(e), C.byref(rb), *win, P(cost),
+                                                     P(kp), P(ews), ews.nbytes, None))
+    cu, ku = evaluate(Gu, Cu, g, eu, [r])
+    assert np.array_equal(bits(cost.get(cells, np.float32)), bits(cu.get(cells, np.float32))), "window: cost"
+    assert np.array_equal(kp.get(N, np.uint8), ku.get(N, np.uint8)), "window: keep"
+    # a point below z_min would move the planes: refused, nothing written
+    low = Buf.of(np.array([[5.0, 5.0, e.z_min - 1.0]], np.float32))
+    st = L.pct_tomogram_insert(P(low), 1, len(union), C.byref(gs), C.byref(e), P(G), P(Cc), P(aG), P(aC),
+                               bb, P(ws), ws.nbytes, None)
+    assert st == abi.PCT_ERR_ARG, "insert below z_min must be refused"
+    assert np.array_equal(bits(G.get(cells, np.float32)), bits(Gu.get(cells, np.float32)))
+    say(f"insert: {len(new)} points into {len(pts)}, box {tuple(bb)}, window {win}: tomogram, ids, cost and keep "
+        f"equal the union's")
+
+
 CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}
 
 if __name__ == "__main__":
