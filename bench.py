@@ -356,6 +356,53 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
         torch.cuda.synchronize()
         if i >= warmup:
             ptimes.append((time.perf_counter() - t0) * 1e3)
+    # trajectory optimisation (Sec. III-E) on the ground floor: 4096
+    # trajectories of 32 quintic pieces, 16 samples per piece
+    h = P.pct_plane_heights(ext, g["slice_dz"])
+    k0 = int(np.searchsorted(h, 0.3))
+    tprm = dict(w_z=2.0, w_c=0.05, w_v=1.0, w_a=0.5, w_h=20.0, w_T=1.0, c_safe=5.0, v_max=1.2, a_max=2.0,
+                d_ref=0.65, d_min=0.5, samples=16)
+    tp = scenes.traj_problems(60, 4096, 32, (5.0, 95.0), (5.0, 95.0), 0.65, slices=(k0,))
+    td = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in tp.items()}
+    t_iters = 10
+    kn0, ta0 = td["knots"].clone(), td["tau"].clone()
+    ev_ts, op_ts = [], []
+    for i in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi0, _, _ = P.pct_traj_eval(cost, G, Cc, g, ext, tprm, td["bound"], td["slices"], td["knots"], td["tau"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        phi_t, done_t = P.pct_traj_optimize(cost, G, Cc, g, ext, tprm, td["bound"], td["slices"], td["knots"],
+                                            td["tau"], t_iters, 1e-3)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        td["knots"].copy_(kn0)
+        td["tau"].copy_(ta0)
+        if i >= warmup:
+            ev_ts.append((t1 - t0) * 1e3)
+            op_ts.append((t2 - t1) * 1e3)
+    ntr = int(tp["tau"].shape[0])
+    done_mean = float(done_t.float().mean())
+    traj = {"workload": "4096 trajectories of 32 quintic pieces on the building's ground floor, 16 samples per "
+                        "piece, gradient descent with backtracking",
+            "trajectories": ntr, "pieces": 32, "samples": 16, "eval_ms": float(np.median(ev_ts)),
+            "optimize_iters": t_iters, "optimize_ms": float(np.median(op_ts)), "iterations_accepted_mean": done_mean,
+            "objective_mean_before": float(phi0.mean()), "objective_mean_after": float(phi_t.mean())}
+    traj["evals_per_s"] = ntr / (traj["eval_ms"] * 1e-3)
+    if cpu:
+        from oracle import traj as otraj
+        maps = (cost.cpu().numpy(), G.cpu().numpy(), Cc.cpu().numpy())
+        t0 = time.perf_counter()
+        n_o = 4
+        for t in range(n_o):
+            otraj.objective(tp["knots"][t], tp["tau"][t], tp["bound"][t, 0], tp["bound"][t, 1], tp["slices"][t],
+                            maps, g, tprm)
+        dt = time.perf_counter() - t0
+        del maps
+        traj["cpu_oracle"] = {"evals_per_s": n_o / dt, "cores": 1, "kind": "oracle",
+                              "sample": f"objective and gradient of the first {n_o} trajectories"}
+    del td, kn0, ta0
     # a streaming scan: 200 k new points into the map, re-evaluated around
     # them, against rebuilding and re-evaluating the union
     rng = np.random.default_rng(12)
@@ -402,7 +449,7 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
            "rounds": info["rounds"], "tiles_processed": info["tiles"], "distance_ms": ms_dist,
            "nodes_per_s": nodes / (ms_dist * 1e-3), "path_ms": float(np.median(ptimes)),
            "path_nodes": int(path.shape[0]), "goal_cost": float(d[goal[2], goal[1], goal[0]]),
-           "unique_cells": unique, "insert": insert}
+           "unique_cells": unique, "insert": insert, "traj": traj}
     if cpu:
         import oracle
         log("path search: oracle pipeline and Dijkstra")

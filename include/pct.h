@@ -47,6 +47,8 @@ typedef int32_t pct_status;
 #define PCT_MAX_KERNEL_RADIUS 16 /* support radius of the inflation kernel, in cells */
 #define PCT_MAX_PATCH_RADIUS 4   /* r_p of the step test's neighbour patch */
 #define PCT_MAX_GRID_SIDE 65535  /* nx, ny */
+#define PCT_MAX_PIECES 64        /* M, polynomial pieces of one trajectory */
+#define PCT_MAX_TRAJ_SAMPLES 64  /* K, penalty samples per piece (K + 1 times) */
 
 /* Grid of Sec. III-A: resolution r_g = res, slice interval d_s = slice_dz.
  * Cell (ix, iy) holds the points with floor((x - x0) / res) = ix and
@@ -443,6 +445,57 @@ pct_status pct_eval_traversability_window(const float* d_ground, const float* d_
                                           const pct_extent* extent, const pct_robot* h_robot, int32_t x0, int32_t y0,
                                           int32_t x1, int32_t y1, float* d_cost, uint8_t* d_keep, void* d_ws,
                                           size_t ws_bytes, void* stream);
+
+/* ---- trajectory optimisation (Sec. III-E, Eq. (10)) ---- */
+
+/* Weights and limits of the penalty form of Eq. (10).  Per sample, with G,
+ * C, H the bilinear e^G, c^T, e^C of the piece's slice at the sample's (x, y):
+ *     w_z (z - G - d_ref)^2 + w_c max(0, C - c_safe)^3
+ *   + w_v max(0, |v|^2 - v_max^2)^3 + w_a max(0, |a|^2 - a_max^2)^3
+ *   + w_h max(0, G + d_min - z)^3 + w_h max(0, z - H)^3,
+ * summed over K + 1 evenly spaced times per piece with trapezoid weights;
+ * the objective adds the jerk effort and w_T times the total duration.  All
+ * values finite, weights >= 0, v_max and a_max > 0, 1 <= samples <=
+ * PCT_MAX_TRAJ_SAMPLES. */
+typedef struct {
+    float w_z, w_c, w_v, w_a, w_h, w_T;
+    float c_safe, v_max, a_max;
+    float d_ref, d_min;
+    int32_t samples;
+} pct_traj_params;
+
+/* Objective, gradient and spline of n_traj trajectories of n_pieces quintic
+ * pieces (1 <= n_pieces <= PCT_MAX_PIECES), FP64 (Sec. III-E, Eq. (10)).
+ * Each trajectory is the minimum-jerk spline (continuous in derivatives
+ * 0..4) through its interior waypoints with durations T_i = exp(tau_i),
+ * between fixed start and goal states.
+ * d_cost, d_ground, d_ceil: float32 [N][ny][nx], c^T of one robot, e^G, e^C.
+ * d_bound: float64 [n][2][3][3], start then goal, rows position, velocity,
+ * acceleration.  d_slice: int32 [n][M], the slice each piece is evaluated
+ * on (outside [0, N): no map terms).  d_knots: float64 [n][M-1][3] interior
+ * waypoints (null when M = 1); d_tau: float64 [n][M].
+ * d_phi: float64 [n] objective (+inf where a duration or sample is not
+ * finite; the gradients are then NaN).  d_gknots [n][M-1][3], d_gtau [n][M]:
+ * its gradient.  d_coef (nullable): float64 [n][M][6][3], the monomial
+ * coefficients of each piece in its local time t in [0, T_i].
+ * Asynchronous on the stream; no workspace. */
+pct_status pct_traj_eval(const float* d_cost, const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                         const pct_extent* extent, const pct_traj_params* h_prm, int32_t n_traj, int32_t n_pieces,
+                         const double* d_bound, const int32_t* d_slice, const double* d_knots, const double* d_tau,
+                         double* d_phi, double* d_gknots, double* d_gtau, double* d_coef, void* stream);
+
+/* iters iterations of gradient descent with Armijo backtracking on the
+ * objective of pct_traj_eval, per trajectory, from d_knots / d_tau (updated
+ * in place).  The step starts at `step` (> 0, finite), is halved until the
+ * objective drops by at least 1e-4 * step * |gradient|^2 (at most 30
+ * times; a failed search ends that trajectory's run) and is doubled after
+ * each accepted iteration.  d_phi: the final objective; d_iters (nullable):
+ * int32 [n], the iterations accepted.  Asynchronous on the stream. */
+pct_status pct_traj_optimize(const float* d_cost, const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                             const pct_extent* extent, const pct_traj_params* h_prm, int32_t n_traj,
+                             int32_t n_pieces, const double* d_bound, const int32_t* d_slice, double* d_knots,
+                             double* d_tau, int32_t iters, double step, double* d_phi, int32_t* d_iters,
+                             void* stream);
 
 #ifdef __cplusplus
 }

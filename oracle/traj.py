@@ -29,7 +29,9 @@ Readings of the paper:
   - Maps are the piece's slice of c^T, e^G, e^C, interpolated bilinearly at
     cell centres and clamped to the grid edge with zero slope across the
     clamp.  Terms that use G are dropped where any of the four e^G corners
-    is missing; the ceiling term where any e^C corner is open (+inf).
+    is missing; the ceiling term where any e^C corner is open (+inf).  A
+    piece whose slice lies outside [0, N) has no map terms (the kinematic
+    terms remain).
   - Durations are T_i = exp(tau_i); the objective adds w_T * sum T_i.  The
     variables are the interior waypoints and the tau_i.
   - The optimiser: gradient descent with Armijo backtracking (sufficient
@@ -162,20 +164,21 @@ def penalty_terms(coef, T, slices, maps, grid, prm):
             a = sum(m * (m - 1) * c[m] * t ** (m - 2) for m in range(2, 6))
             if not bool(torch.isfinite(q).all() & torch.isfinite(v).all() & torch.isfinite(a).all()):
                 return torch.full((), float("inf"), dtype=DT)
-            u = (q[0] - x0) / r - 0.5
-            vv = (q[1] - y0) / r - 0.5
-            i0, i1, fu = _axis(u, nx)
-            j0, j1, fv = _axis(vv, ny)
-            f = prm["w_c"] * relu3(_bilinear(cT, k, i0, i1, j0, j1, fu, fv) - prm["c_safe"])
-            f = f + prm["w_v"] * relu3((v * v).sum() - prm["v_max"] ** 2)
+            f = prm["w_v"] * relu3((v * v).sum() - prm["v_max"] ** 2)
             f = f + prm["w_a"] * relu3((a * a).sum() - prm["a_max"] ** 2)
-            G = _bilinear(eG, k, i0, i1, j0, j1, fu, fv)
-            if G is not None:
-                f = f + prm["w_z"] * (q[2] - G - prm["d_ref"]) ** 2
-                f = f + prm["w_h"] * relu3(G + prm["d_min"] - q[2])
-            H = _bilinear(eC, k, i0, i1, j0, j1, fu, fv)
-            if H is not None:
-                f = f + prm["w_h"] * relu3(q[2] - H)
+            if 0 <= k < cT.shape[0]:
+                u = (q[0] - x0) / r - 0.5
+                vv = (q[1] - y0) / r - 0.5
+                i0, i1, fu = _axis(u, nx)
+                j0, j1, fv = _axis(vv, ny)
+                f = f + prm["w_c"] * relu3(_bilinear(cT, k, i0, i1, j0, j1, fu, fv) - prm["c_safe"])
+                G = _bilinear(eG, k, i0, i1, j0, j1, fu, fv)
+                if G is not None:
+                    f = f + prm["w_z"] * (q[2] - G - prm["d_ref"]) ** 2
+                    f = f + prm["w_h"] * relu3(G + prm["d_min"] - q[2])
+                H = _bilinear(eC, k, i0, i1, j0, j1, fu, fv)
+                if H is not None:
+                    f = f + prm["w_h"] * relu3(q[2] - H)
             F = F + w * f
     return F
 
@@ -229,6 +232,8 @@ def optimize(knots, tau, start, goal, slices, maps, grid, prm, iters, step):
     alpha = float(step)
     phi, gk, gt = objective(x_k, x_t, start, goal, slices, maps, grid, prm)
     done = 0
+    if not np.isfinite(phi):
+        return x_k, x_t, phi, done
     for _ in range(iters):
         g2 = float((gk * gk).sum() + (gt * gt).sum())
         if g2 == 0.0:

@@ -326,6 +326,69 @@ def pct_unique_cells(ground, ceil, cost, keep, grid, extent: pct_extent, robot, 
     return out
 
 
+# --------------------------------------------------------------------- trajectory optimisation
+
+_TRAJ_FIELDS = ("w_z", "w_c", "w_v", "w_a", "w_h", "w_T", "c_safe", "v_max", "a_max", "d_ref", "d_min")
+
+
+def traj_params_struct(prm):
+    """pct_traj_params from a dict with the weights, limits and samples."""
+    if isinstance(prm, _abi.pct_traj_params):
+        return prm
+    return _abi.pct_traj_params(*[float(prm[n]) for n in _TRAJ_FIELDS], int(prm["samples"]))
+
+
+def _traj_inputs(cost, ground, ceil, grid, extent, bound, slices, knots, tau):
+    g = grid_struct(grid)
+    N = extent.n_slices
+    for t in (cost, ground, ceil):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == N * g.nx * g.ny):
+            raise ValueError("cost/ground/ceil must be contiguous CUDA float32 [N, ny, nx]")
+    n, M = slices.shape
+    if not (slices.is_cuda and slices.dtype == torch.int32 and slices.is_contiguous()):
+        raise ValueError("slices must be a contiguous CUDA int32 [n, M] tensor")
+    if not (bound.is_cuda and bound.dtype == torch.float64 and bound.is_contiguous() and tuple(bound.shape) == (n, 2, 3, 3)):
+        raise ValueError("bound must be a contiguous CUDA float64 [n, 2, 3, 3] tensor")
+    if not (tau.is_cuda and tau.dtype == torch.float64 and tau.is_contiguous() and tuple(tau.shape) == (n, M)):
+        raise ValueError("tau must be a contiguous CUDA float64 [n, M] tensor")
+    if not (knots.is_cuda and knots.dtype == torch.float64 and knots.is_contiguous()
+            and tuple(knots.shape) == (n, M - 1, 3)):
+        raise ValueError("knots must be a contiguous CUDA float64 [n, M-1, 3] tensor")
+    return g, n, M
+
+
+def pct_traj_eval(cost, ground, ceil, grid, extent: pct_extent, prm, bound, slices, knots, tau, coefficients=False):
+    """Objective of Eq. (10) (penalty form) for n trajectories of M pieces:
+    returns (phi [n], d phi / d knots [n, M-1, 3], d phi / d tau [n, M]) and,
+    with ``coefficients``, the monomial coefficients [n, M, 6, 3]."""
+    g, n, M = _traj_inputs(cost, ground, ceil, grid, extent, bound, slices, knots, tau)
+    dev = tau.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    phi, gk, gt = torch.empty(n, **f64), torch.empty(n, M - 1, 3, **f64), torch.empty(n, M, **f64)
+    coef = torch.empty(n, M, 6, 3, **f64) if coefficients else None
+    p = traj_params_struct(prm)
+    _check("pct_traj_eval",
+           lib().pct_traj_eval(_ptr(cost), _ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(p), n, M,
+                               _ptr(bound), _ptr(slices), _ptr(knots) if M > 1 else None, _ptr(tau), _ptr(phi),
+                               _ptr(gk) if M > 1 else None, _ptr(gt), _ptr(coef), _stream(dev)))
+    return (phi, gk, gt, coef) if coefficients else (phi, gk, gt)
+
+
+def pct_traj_optimize(cost, ground, ceil, grid, extent: pct_extent, prm, bound, slices, knots, tau, iters, step):
+    """Gradient descent with Armijo backtracking on ``knots`` / ``tau`` in
+    place; returns (phi [n], iterations accepted [n])."""
+    g, n, M = _traj_inputs(cost, ground, ceil, grid, extent, bound, slices, knots, tau)
+    dev = tau.device
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    done = torch.empty(n, dtype=torch.int32, device=dev)
+    p = traj_params_struct(prm)
+    _check("pct_traj_optimize",
+           lib().pct_traj_optimize(_ptr(cost), _ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(p), n,
+                                   M, _ptr(bound), _ptr(slices), _ptr(knots) if M > 1 else None, _ptr(tau),
+                                   int(iters), float(step), _ptr(phi), _ptr(done), _stream(dev)))
+    return phi, done
+
+
 # --------------------------------------------------------------------- trajectory cost
 
 def _wp(wp, slices):

@@ -7,6 +7,8 @@ import ctypes as C
 
 PCT_OK, PCT_ERR_ARG, PCT_ERR_WORKSPACE, PCT_ERR_CAPACITY, PCT_ERR_DEVICE = 0, -1, -2, -3, -4
 PCT_MAX_SLICES = 1024
+PCT_MAX_PIECES = 64
+PCT_MAX_TRAJ_SAMPLES = 64
 PCT_ACCUMULATE = 1
 PCT_DESCRIPTORS_RESIDENT = 2
 
@@ -39,6 +41,11 @@ class pct_robot(C.Structure):
         return d
 
 
+class pct_traj_params(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("w_z", "w_c", "w_v", "w_a", "w_h", "w_T", "c_safe", "v_max", "a_max",
+                                          "d_ref", "d_min")] + [("samples", C.c_int32)]
+
+
 def load(path):
     """Open the shared library at `path` and set the argument and result
     types of every entry point."""
@@ -46,6 +53,7 @@ def load(path):
     vp, sz, i64, i32, f32 = C.c_void_p, C.c_size_t, C.c_int64, C.c_int32, C.c_float
     G, E, Rb = C.POINTER(pct_grid), C.POINTER(pct_extent), C.POINTER(pct_robot)
     It = C.POINTER(pct_item)
+    Tp = C.POINTER(pct_traj_params)
     sig = {
         "pct_abi_version": ([], i32),
         "pct_last_error": ([], C.c_char_p),
@@ -85,6 +93,8 @@ def load(path):
         "pct_tomogram_insert": ([vp, i64, i32, G, E, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "pct_eval_traversability_window": ([vp, vp, G, E, Rb, i32, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "pct_unique_cells": ([vp, vp, vp, vp, G, E, Rb, i64, vp, vp, vp, vp, vp, C.POINTER(i64), vp, sz, vp], i32),
+        "pct_traj_eval": ([vp, vp, vp, G, E, Tp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "pct_traj_optimize": ([vp, vp, vp, G, E, Tp, i32, i32, vp, vp, vp, vp, i32, C.c_double, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

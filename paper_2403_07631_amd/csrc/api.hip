@@ -10,6 +10,7 @@
 
 #include "pct_internal.h"
 #include "plan_internal.h"
+#include "traj_internal.h"
 #include "unique_internal.h"
 
 namespace pct {
@@ -915,6 +916,93 @@ pct_status pct_eval_traversability_window(const float* d_ground, const float* d_
     }
     if (d_keep) return launch_simplify(d_ground, d_cost, p, d_keep, d_ws, s);
     return PCT_OK;
+}
+
+namespace {
+
+pct_status traj_args(const float* d_cost, const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                     const pct_extent* extent, const pct_traj_params* h_prm, int32_t n_traj, int32_t n_pieces,
+                     const void* d_bound, const void* d_slice, const void* d_knots, const void* d_tau,
+                     const void* d_phi, pct::TrajArgs* out) {
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (!h_prm) return fail(PCT_ERR_ARG, "h_prm is null");
+    const pct_traj_params& p = *h_prm;
+    const float w[] = {p.w_z, p.w_c, p.w_v, p.w_a, p.w_h, p.w_T};
+    for (float x : w)
+        if (!(x >= 0.0f) || !isfinite(x)) return fail(PCT_ERR_ARG, "penalty weights must be finite and >= 0");
+    if (!isfinite(p.c_safe) || !isfinite(p.d_ref) || !isfinite(p.d_min))
+        return fail(PCT_ERR_ARG, "c_safe, d_ref and d_min must be finite");
+    if (!(p.v_max > 0.0f) || !(p.a_max > 0.0f) || !isfinite(p.v_max) || !isfinite(p.a_max))
+        return fail(PCT_ERR_ARG, "v_max and a_max must be finite and > 0");
+    if (p.samples < 1 || p.samples > PCT_MAX_TRAJ_SAMPLES)
+        return fail(PCT_ERR_ARG, "samples must be in [1, %d]", PCT_MAX_TRAJ_SAMPLES);
+    if (n_traj < 0) return fail(PCT_ERR_ARG, "n_traj must be >= 0");
+    if (n_pieces < 1 || n_pieces > PCT_MAX_PIECES) return fail(PCT_ERR_ARG, "n_pieces must be in [1, %d]", PCT_MAX_PIECES);
+    if (n_traj > 0) {
+        if (!d_bound || !d_slice || !d_tau || !d_phi) return fail(PCT_ERR_ARG, "trajectory pointers are null");
+        if (n_pieces > 1 && !d_knots) return fail(PCT_ERR_ARG, "d_knots is null");
+        if (extent->n_slices > 0 && (!d_cost || !d_ground || !d_ceil)) return fail(PCT_ERR_ARG, "map pointers are null");
+    }
+    pct::TrajArgs a{};
+    a.cost = d_cost;
+    a.ground = d_ground;
+    a.ceil = d_ceil;
+    a.nx = grid->nx;
+    a.ny = grid->ny;
+    a.N = extent->n_slices;
+    a.x0 = grid->x0;
+    a.y0 = grid->y0;
+    a.res = grid->res;
+    a.w_z = p.w_z;
+    a.w_c = p.w_c;
+    a.w_v = p.w_v;
+    a.w_a = p.w_a;
+    a.w_h = p.w_h;
+    a.w_T = p.w_T;
+    a.c_safe = p.c_safe;
+    a.v_max2 = (double)p.v_max * (double)p.v_max;
+    a.a_max2 = (double)p.a_max * (double)p.a_max;
+    a.d_ref = p.d_ref;
+    a.d_min = p.d_min;
+    a.K = p.samples;
+    a.M = n_pieces;
+    *out = a;
+    return PCT_OK;
+}
+
+}  // namespace
+
+pct_status pct_traj_eval(const float* d_cost, const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                         const pct_extent* extent, const pct_traj_params* h_prm, int32_t n_traj, int32_t n_pieces,
+                         const double* d_bound, const int32_t* d_slice, const double* d_knots, const double* d_tau,
+                         double* d_phi, double* d_gknots, double* d_gtau, double* d_coef, void* stream) {
+    clear_error();
+    pct::TrajArgs a;
+    pct_status st = traj_args(d_cost, d_ground, d_ceil, grid, extent, h_prm, n_traj, n_pieces, d_bound, d_slice,
+                              d_knots, d_tau, d_phi, &a);
+    if (st != PCT_OK) return st;
+    if (n_traj > 0 && (!d_gtau || (n_pieces > 1 && !d_gknots))) return fail(PCT_ERR_ARG, "gradient pointers are null");
+    return pct::launch_traj(a, n_traj, d_bound, d_slice, const_cast<double*>(d_knots), const_cast<double*>(d_tau),
+                            d_phi, d_gknots, d_gtau, d_coef, -1, 0.0, nullptr, (hipStream_t)stream);
+}
+
+pct_status pct_traj_optimize(const float* d_cost, const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                             const pct_extent* extent, const pct_traj_params* h_prm, int32_t n_traj,
+                             int32_t n_pieces, const double* d_bound, const int32_t* d_slice, double* d_knots,
+                             double* d_tau, int32_t iters, double step, double* d_phi, int32_t* d_iters,
+                             void* stream) {
+    clear_error();
+    pct::TrajArgs a;
+    pct_status st = traj_args(d_cost, d_ground, d_ceil, grid, extent, h_prm, n_traj, n_pieces, d_bound, d_slice,
+                              d_knots, d_tau, d_phi, &a);
+    if (st != PCT_OK) return st;
+    if (iters < 0) return fail(PCT_ERR_ARG, "iters must be >= 0");
+    if (!(step > 0.0) || !isfinite(step)) return fail(PCT_ERR_ARG, "step must be finite and > 0");
+    return pct::launch_traj(a, n_traj, d_bound, d_slice, d_knots, d_tau, d_phi, nullptr, nullptr, nullptr, iters,
+                            step, d_iters, (hipStream_t)stream);
 }
 
 }  // extern "C"

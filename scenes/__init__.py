@@ -17,6 +17,7 @@ from .synth import (  # noqa: F401
     plan_layers,
     plan_serpentine,
     plan_building,
+    traj_problems,
     ROBOT_CONFIG0,
     ROBOT_TABLE1,
 )

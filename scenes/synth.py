@@ -384,3 +384,37 @@ def plan_building(seed: int = 7, side: float = 100.0, n_floors: int = 6, per_cel
     sc = multistorey_scene(seed, side, side, n_points, n_floors=n_floors, beam_cover=0.0)
     sc.name = "plan-building"
     return sc
+
+
+def traj_problems(seed: int, n: int, M: int, x_range, y_range, z_body: float, step: float = 0.6,
+                  speed: float = 1.0, slices=(0,), turn: float = 0.5):
+    """Seeded trajectory-optimisation problems: n trajectories of M pieces
+    whose waypoints follow a random heading walk with the given step, inside
+    the xy box, at body height z_body (+ N(0, 0.05)), starting and ending at
+    rest.  Durations are step / speed times U(0.7, 1.3); each trajectory is
+    assigned one of ``slices``.  Returns bound [n, 2, 3, 3] (start and goal:
+    position, velocity, acceleration), slices [n, M] int32, knots
+    [n, M-1, 3] and tau [n, M] (log-durations), all float64."""
+    rng = np.random.default_rng(seed)
+    pts = np.zeros((n, M + 1, 3))
+    x0, x1 = x_range
+    y0, y1 = y_range
+    pts[:, 0, 0] = rng.uniform(x0, x1, n)
+    pts[:, 0, 1] = rng.uniform(y0, y1, n)
+    head = rng.uniform(0, 2 * math.pi, n)
+    for m in range(1, M + 1):
+        head = head + rng.normal(0, turn, n)
+        nx_ = pts[:, m - 1, 0] + step * np.cos(head)
+        ny_ = pts[:, m - 1, 1] + step * np.sin(head)
+        out = (nx_ < x0) | (nx_ > x1) | (ny_ < y0) | (ny_ > y1)
+        head = np.where(out, head + math.pi, head)
+        pts[:, m, 0] = np.clip(np.where(out, pts[:, m - 1, 0] + step * np.cos(head), nx_), x0, x1)
+        pts[:, m, 1] = np.clip(np.where(out, pts[:, m - 1, 1] + step * np.sin(head), ny_), y0, y1)
+    pts[:, :, 2] = z_body + rng.normal(0, 0.05, (n, M + 1))
+    bound = np.zeros((n, 2, 3, 3))
+    bound[:, 0, 0] = pts[:, 0]
+    bound[:, 1, 0] = pts[:, M]
+    sl = np.asarray(slices, np.int32)[rng.integers(0, len(slices), n)]
+    return dict(bound=bound, slices=np.repeat(sl[:, None], M, axis=1).astype(np.int32),
+                knots=np.ascontiguousarray(pts[:, 1:M]),
+                tau=np.log(step / speed * rng.uniform(0.7, 1.3, (n, M))))

@@ -687,6 +687,84 @@ def case_insert():
         f"equal the union's")
 
 
+TRAJ_PRM = dict(w_z=2.0, w_c=0.05, w_v=1.0, w_a=0.5, w_h=20.0, w_T=1.0, c_safe=5.0, v_max=1.2, a_max=2.0,
+                d_ref=0.65, d_min=0.5, samples=8)
+
+
+def traj_maps():
+    """An oracle-built and oracle-evaluated three-storey map."""
+    sc = scenes.multistorey_scene(44, 9.3, 7.1, 250_000, n_floors=3)
+    tm = oracle.tomogram(sc.points, sc.grid)
+    r = dict(scenes.ROBOT_TABLE1)
+    cT = oracle.evaluate(tm["ground"], tm["ceil"], sc.grid["res"], r).astype(np.float32)
+    return sc.grid, cT, tm["ground"], tm["ceil"]
+
+
+def traj_run(grid, maps, prm, pr, iters=None, step=1e-3):
+    cT, eG, eC = maps
+    n, M = pr["slices"].shape
+    gs = grid_s(grid)
+    e = abi.pct_extent(0.0, 1.0, cT.shape[0], 0, 0, 0)
+    tp = abi.pct_traj_params(*[float(prm[k]) for k in ("w_z", "w_c", "w_v", "w_a", "w_h", "w_T", "c_safe", "v_max",
+                                                        "a_max", "d_ref", "d_min")], int(prm["samples"]))
+    bufs = [Buf.of(np.ascontiguousarray(a)) for a in (cT, eG, eC)]
+    bd, sl = Buf.of(pr["bound"]), Buf.of(pr["slices"])
+    kn = Buf.of(pr["knots"]) if M > 1 else None
+    ta = Buf.of(pr["tau"])
+    phi = Buf(8 * n)
+    if iters is None:
+        gk, gt, cf = (Buf(8 * n * (M - 1) * 3) if M > 1 else None), Buf(8 * n * M), Buf(8 * n * M * 18)
+        check("traj_eval", L.pct_traj_eval(P(bufs[0]), P(bufs[1]), P(bufs[2]), C.byref(gs), C.byref(e), C.byref(tp), n,
+                                           M, P(bd), P(sl), P(kn), P(ta), P(phi), P(gk), P(gt), P(cf), None))
+        return (phi.get(n, np.float64), gk.get((n, M - 1, 3), np.float64) if M > 1 else np.zeros((n, 0, 3)),
+                gt.get((n, M), np.float64), cf.get((n, M, 6, 3), np.float64))
+    done = Buf(4 * n)
+    check("traj_optimize", L.pct_traj_optimize(P(bufs[0]), P(bufs[1]), P(bufs[2]), C.byref(gs), C.byref(e), C.byref(tp),
+                                               n, M, P(bd), P(sl), P(kn), P(ta), int(iters), float(step), P(phi),
+                                               P(done), None))
+    return (phi.get(n, np.float64), kn.get((n, M - 1, 3), np.float64) if M > 1 else np.zeros((n, 0, 3)),
+            ta.get((n, M), np.float64), done.get(n, np.int32))
+
+
+def case_traj_opt():
+    """Trajectory optimisation (Sec. III-E): objective, gradient and spline
+    coefficients against the oracle's KKT solve and autograd, for one to 64
+    pieces and 1 to 16 samples, slices outside the map included; then
+    optimiser runs against the oracle's loop."""
+    from oracle import traj as otraj
+    grid, cT, eG, eC = traj_maps()
+    maps = (cT, eG, eC)
+    N = cT.shape[0]
+    for M, K, n in ((1, 4, 2), (2, 1, 2), (5, 7, 3), (33, 3, 1), (64, 2, 1)):
+        prm = dict(TRAJ_PRM, samples=K)
+        pr = scenes.traj_problems(20 + M, n, M, (1.0, 8.0), (1.0, 6.0), 0.7, slices=(0, 3, N - 1, N + 2))
+        phi, gk, gt, cf = traj_run(grid, maps, prm, pr)
+        for t in range(n):
+            args = (pr["knots"][t], pr["tau"][t], pr["bound"][t, 0], pr["bound"][t, 1], pr["slices"][t], maps, grid,
+                    prm)
+            p_o, gk_o, gt_o = otraj.objective(*args)
+            c_o = otraj.coefficients(*args[:4])
+            scale = max(1.0, abs(p_o))
+            assert abs(phi[t] - p_o) <= 1e-9 * scale, (M, K, t, phi[t], p_o)
+            np.testing.assert_allclose(cf[t], c_o, rtol=1e-8, atol=1e-8 * np.abs(c_o).max())
+            gs_ = max(1.0, np.abs(np.concatenate([gk_o.ravel(), gt_o])).max())
+            np.testing.assert_allclose(gk[t], gk_o, rtol=1e-7, atol=1e-8 * gs_)
+            np.testing.assert_allclose(gt[t], gt_o, rtol=1e-7, atol=1e-8 * gs_)
+        say(f"traj eval: M={M} K={K} n={n}: phi, gradients and coefficients equal the oracle's")
+    for M, K, n, iters in ((1, 4, 1, 6), (4, 6, 2, 5)):
+        prm = dict(TRAJ_PRM, samples=K)
+        pr = scenes.traj_problems(40 + M, n, M, (1.0, 8.0), (1.0, 6.0), 0.7, slices=(0, 3))
+        phi, kn, ta, done = traj_run(grid, maps, prm, pr, iters=iters, step=1e-3)
+        for t in range(n):
+            k_o, t_o, p_o, d_o = otraj.optimize(pr["knots"][t], pr["tau"][t], pr["bound"][t, 0], pr["bound"][t, 1],
+                                                pr["slices"][t], maps, grid, prm, iters, 1e-3)
+            assert done[t] == d_o, (done[t], d_o)
+            assert abs(phi[t] - p_o) <= 1e-7 * max(1.0, abs(p_o)), (phi[t], p_o)
+            np.testing.assert_allclose(kn[t], k_o, rtol=1e-7, atol=1e-9)
+            np.testing.assert_allclose(ta[t], t_o, rtol=1e-7, atol=1e-9)
+        say(f"traj optimise: M={M} K={K} {iters} iterations: iterates equal the oracle's")
+
+
 CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}
 
 if __name__ == "__main__":

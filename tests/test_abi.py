@@ -219,3 +219,43 @@ def test_plan_argument_checks(P):
                            None) == P.PCT_ERR_ARG            # goal layer outside
     assert L.pct_plan_path(dummy, C.byref(g), 2, 0, 0, 0, 0, 0, 1, dummy, 0, C.byref(n), dummy, 1 << 30,
                            None) == P.PCT_ERR_ARG            # max_len 0
+
+
+def test_traj_argument_checks(P):
+    """The trajectory optimisation validates its arguments before touching
+    the device."""
+    import ctypes as C
+    from paper_2403_07631_amd import abi
+    L = P.lib()
+    g = P.grid_struct(dict(x0=0.0, y0=0.0, res=0.1, nx=100, ny=80, slice_dz=0.3))
+    e = P.pct_extent(0.0, 1.0, 5, 0, 0, 0)
+    good = dict(w_z=1.0, w_c=1.0, w_v=1.0, w_a=1.0, w_h=1.0, w_T=1.0, c_safe=5.0, v_max=1.0, a_max=1.0,
+                d_ref=0.5, d_min=0.3, samples=8)
+    d = C.c_void_p(16)
+
+    def ev(prm=good, n=4, M=8, ptr=d, knots=d):
+        p = P.traj_params_struct(prm)
+        return L.pct_traj_eval(ptr, ptr, ptr, C.byref(g), C.byref(e), C.byref(p), n, M, ptr, ptr, knots, ptr, ptr,
+                               ptr, ptr, None, None)
+
+    def opt(iters=5, step=1e-3):
+        p = P.traj_params_struct(good)
+        return L.pct_traj_optimize(d, d, d, C.byref(g), C.byref(e), C.byref(p), 4, 8, d, d, d, d, iters, step, d,
+                                   None, None)
+
+    assert abi.PCT_MAX_PIECES == 64 and abi.PCT_MAX_TRAJ_SAMPLES == 64
+    assert ev(M=0) == P.PCT_ERR_ARG
+    assert ev(M=65) == P.PCT_ERR_ARG
+    assert ev(prm=dict(good, samples=0)) == P.PCT_ERR_ARG
+    assert ev(prm=dict(good, samples=65)) == P.PCT_ERR_ARG
+    assert ev(prm=dict(good, w_c=-1.0)) == P.PCT_ERR_ARG
+    assert ev(prm=dict(good, w_T=float("inf"))) == P.PCT_ERR_ARG
+    assert ev(prm=dict(good, v_max=0.0)) == P.PCT_ERR_ARG
+    assert ev(prm=dict(good, d_ref=float("nan"))) == P.PCT_ERR_ARG
+    assert ev(n=-1) == P.PCT_ERR_ARG
+    assert ev(ptr=None) == P.PCT_ERR_ARG
+    assert ev(knots=None) == P.PCT_ERR_ARG            # interior waypoints needed for M > 1
+    assert opt(iters=-1) == P.PCT_ERR_ARG
+    assert opt(step=0.0) == P.PCT_ERR_ARG
+    assert opt(step=float("nan")) == P.PCT_ERR_ARG
+    assert ev(n=0) == P.PCT_OK                        # nothing to do

@@ -65,7 +65,7 @@ GROUPS = [
     (("batch", "batch_resident", "batch_mixed_radius"), "rand"),
     (("traj_value_grad", "autotune"), "fwd"),
     (("plan", "unique"), "rand"),
-    (("insert",), "rev"),
+    (("insert", "traj_opt"), "rev"),
 ]
 
 

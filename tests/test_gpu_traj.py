@@ -1,0 +1,149 @@
+"""GPU checks of the trajectory optimisation (Sec. III-E, Eq. (10)), through
+the C ABI.
+
+On an oracle-built and oracle-evaluated three-storey map, the objective, its
+gradient and the spline coefficients equal the oracle's (KKT solve of the
+minimum-jerk spline, autograd gradients) to FP64 rounding, for one to 64
+pieces, 1 to 64 samples and slices outside the map; optimiser runs take the
+same iterations as the oracle's loop.  On the benchmark's building with the
+benchmark's launch (4096 trajectories of 32 pieces), sampled trajectories
+equal the oracle's and every trajectory's objective does not increase."""
+import sys
+
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+PRM = dict(w_z=2.0, w_c=0.05, w_v=1.0, w_a=0.5, w_h=20.0, w_T=1.0, c_safe=5.0, v_max=1.2, a_max=2.0,
+           d_ref=0.65, d_min=0.5, samples=8)
+
+
+def say(msg):
+    print(f"[gpu] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_07631_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def small_map(oracle_lib):
+    sc = scenes.multistorey_scene(44, 9.3, 7.1, 250_000, n_floors=3)
+    tm = oracle_lib.tomogram(sc.points, sc.grid)
+    r = dict(scenes.ROBOT_TABLE1)
+    cT = oracle_lib.evaluate(tm["ground"], tm["ceil"], sc.grid["res"], r).astype(np.float32)
+    return sc.grid, (cT, tm["ground"], tm["ceil"])
+
+
+def dev(pr, maps):
+    import torch
+    d = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in pr.items()}
+    m = tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in maps)
+    return d, m
+
+
+def check_eval(P, grid, maps, prm, pr, ts):
+    from oracle import traj as otraj
+    d, m = dev(pr, maps)
+    ext = P.pct_extent(0.0, 1.0, maps[0].shape[0], 0, 0, 0)
+    phi, gk, gt, cf = P.pct_traj_eval(*m, grid, ext, prm, d["bound"], d["slices"], d["knots"], d["tau"],
+                                      coefficients=True)
+    phi, gk, gt, cf = (x.cpu().numpy() for x in (phi, gk, gt, cf))
+    for t in ts:
+        args = (pr["knots"][t], pr["tau"][t], pr["bound"][t, 0], pr["bound"][t, 1], pr["slices"][t], maps, grid, prm)
+        p_o, gk_o, gt_o = otraj.objective(*args)
+        c_o = otraj.coefficients(*args[:4])
+        assert abs(phi[t] - p_o) <= 1e-9 * max(1.0, abs(p_o)), (t, phi[t], p_o)
+        np.testing.assert_allclose(cf[t], c_o, rtol=1e-8, atol=1e-8 * np.abs(c_o).max())
+        gs = max(1.0, np.abs(np.concatenate([gk_o.ravel(), gt_o])).max())
+        np.testing.assert_allclose(gk[t], gk_o, rtol=1e-7, atol=1e-8 * gs)
+        np.testing.assert_allclose(gt[t], gt_o, rtol=1e-7, atol=1e-8 * gs)
+    return phi
+
+
+@pytest.mark.parametrize("M,K,n", [(1, 4, 3), (2, 1, 3), (5, 7, 4), (16, 16, 2), (33, 3, 2), (64, 2, 1),
+                                   (3, 64, 2)])
+def test_traj_eval_matches_oracle(P, small_map, M, K, n):
+    grid, maps = small_map
+    N = maps[0].shape[0]
+    pr = scenes.traj_problems(20 + M, n, M, (1.0, 8.0), (1.0, 6.0), 0.7, slices=(0, 3, N - 1, N + 2, -1))
+    check_eval(P, grid, maps, dict(PRM, samples=K), pr, range(n))
+    say(f"traj eval M={M} K={K}: equal to the oracle's")
+
+
+def test_traj_nonfinite_duration(P, small_map):
+    grid, maps = small_map
+    pr = scenes.traj_problems(5, 2, 3, (1.0, 8.0), (1.0, 6.0), 0.7)
+    pr["tau"][1, 1] = 800.0  # exp overflows
+    d, m = dev(pr, maps)
+    ext = P.pct_extent(0.0, 1.0, maps[0].shape[0], 0, 0, 0)
+    phi, gk, gt = P.pct_traj_eval(*m, grid, ext, PRM, d["bound"], d["slices"], d["knots"], d["tau"])
+    phi, gt = phi.cpu().numpy(), gt.cpu().numpy()
+    assert np.isfinite(phi[0]) and np.isinf(phi[1]) and np.isnan(gt[1]).all()
+
+
+@pytest.mark.parametrize("M,K,n,iters", [(1, 4, 2, 8), (4, 6, 3, 6), (12, 8, 2, 4)])
+def test_traj_optimize_matches_oracle(P, small_map, M, K, n, iters):
+    from oracle import traj as otraj
+    import torch
+    grid, maps = small_map
+    prm = dict(PRM, samples=K)
+    pr = scenes.traj_problems(40 + M, n, M, (1.0, 8.0), (1.0, 6.0), 0.7, slices=(0, 3))
+    d, m = dev(pr, maps)
+    ext = P.pct_extent(0.0, 1.0, maps[0].shape[0], 0, 0, 0)
+    phi, done = P.pct_traj_optimize(*m, grid, ext, prm, d["bound"], d["slices"], d["knots"], d["tau"], iters, 1e-3)
+    torch.cuda.synchronize()
+    for t in range(n):
+        k_o, t_o, p_o, d_o = otraj.optimize(pr["knots"][t], pr["tau"][t], pr["bound"][t, 0], pr["bound"][t, 1],
+                                            pr["slices"][t], maps, grid, prm, iters, 1e-3)
+        assert int(done[t]) == d_o
+        assert abs(float(phi[t]) - p_o) <= 1e-7 * max(1.0, abs(p_o))
+        np.testing.assert_allclose(d["knots"][t].cpu().numpy(), k_o, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(d["tau"][t].cpu().numpy(), t_o, rtol=1e-7, atol=1e-9)
+    say(f"traj optimise M={M} K={K}, {iters} iterations: iterates equal the oracle's")
+
+
+def building_problems(P, n=4096, M=32, K=16):
+    """The benchmark's launch: the building built and evaluated by the library,
+    trajectories on its ground floor."""
+    import torch
+    sc = scenes.plan_building()
+    g = sc.grid
+    xyz = torch.from_numpy(sc.points).cuda()
+    ext = P.pct_tomogram_extent(xyz, g)
+    G, Cc, _, _ = P.pct_build_tomogram(xyz, g, ext)
+    r = dict(scenes.ROBOT_TABLE1)
+    cost, _ = P.pct_eval_traversability(G, Cc, g, ext, [r])
+    cost = cost[0].contiguous()
+    k0 = int(np.searchsorted(P.pct_plane_heights(ext, g["slice_dz"]), 0.3))
+    pr = scenes.traj_problems(60, n, M, (5.0, 95.0), (5.0, 95.0), 0.65, slices=(k0,))
+    return g, ext, (cost, G, Cc), pr, dict(PRM, samples=K)
+
+
+def test_traj_building_launch(P):
+    import torch
+    g, ext, m, pr, prm = building_problems(P)
+    d = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in pr.items()}
+    phi0, _, _ = P.pct_traj_eval(*m, g, ext, prm, d["bound"], d["slices"], d["knots"], d["tau"])
+    phi, done = P.pct_traj_optimize(*m, g, ext, prm, d["bound"], d["slices"], d["knots"], d["tau"], 10, 1e-3)
+    torch.cuda.synchronize()
+    phi0, phi, done = phi0.cpu().numpy(), phi.cpu().numpy(), done.cpu().numpy()
+    assert np.isfinite(phi0).all() and np.all(phi <= phi0) and done.mean() > 1
+    # sampled trajectories against the oracle, on the library's own maps
+    from oracle import traj as otraj
+    maps = tuple(x.cpu().numpy() for x in m)
+    for t in (0, 1234, 4095):
+        args = (pr["knots"][t], pr["tau"][t], pr["bound"][t, 0], pr["bound"][t, 1], pr["slices"][t], maps, g, prm)
+        p_o, _, _ = otraj.objective(*args, grad=False)
+        assert abs(phi0[t] - p_o) <= 1e-9 * max(1.0, abs(p_o))
+    say(f"building: 4096 trajectories x 32 pieces, objective {phi0.mean():.1f} -> {phi.mean():.1f} "
+        f"in {done.mean():.1f} iterations on average")
