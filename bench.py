@@ -478,6 +478,9 @@ def main():
     ap.add_argument("--cpu-window", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain profile measurement")
     ap.add_argument("--no-plan", action="store_true", help="skip the path-search measurement")
+    ap.add_argument("--plan-only", action="store_true",
+                    help="run only the building's measurements (path search, unique cells, insertion, trajectories) "
+                         "and print them, for profiling; no benchmark line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -492,6 +495,9 @@ def main():
     import scenes
 
     dev = torch.device("cuda:0")
+    if args.plan_only:
+        print(json.dumps({"plan": bench_plan(P, torch, dev, args.steps, args.warmup, cpu=False)}), flush=True)
+        return
     log("generating the 20M-point map")
     sc = scenes.config1_scene()
     grid = sc.grid

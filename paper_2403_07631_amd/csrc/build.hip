@@ -535,12 +535,7 @@ __device__ __forceinline__ bool rec_less(float za, int ia, float zb, int ib, boo
 // Merge of a cell-slice's value with the one already stored (insertion
 // into an existing tomogram): the higher ground / lower ceiling wins, equal
 // heights keep the lower point id (-1 only goes with the infinities).
-template <bool IDS>
-__device__ __forceinline__ void merge_old(int64_t o, const float* __restrict__ ground, const float* __restrict__ ceil,
-                                          const int* __restrict__ ag, const int* __restrict__ ac, float& gz, int& gi,
-                                          float& cz, int& ci) {
-    const float og = ground[o], oc = ceil[o];
-    const int oi = IDS ? ag[o] : 0, oj = IDS ? ac[o] : 0;
+__device__ __forceinline__ void merge_vals(float og, float oc, int oi, int oj, float& gz, int& gi, float& cz, int& ci) {
     if (og > gz) {
         gz = og;
         gi = oi;
@@ -553,6 +548,13 @@ __device__ __forceinline__ void merge_old(int64_t o, const float* __restrict__ g
     } else if (oc == cz) {
         ci = min(ci, oj);
     }
+}
+
+template <bool IDS>
+__device__ __forceinline__ void merge_old(int64_t o, const float* __restrict__ ground, const float* __restrict__ ceil,
+                                          const int* __restrict__ ag, const int* __restrict__ ac, float& gz, int& gi,
+                                          float& cz, int& ci) {
+    merge_vals(ground[o], ceil[o], IDS ? ag[o] : 0, IDS ? ac[o] : 0, gz, gi, cz, ci);
 }
 
 // One cell: sort its heights (ties by point id) and sweep the planes.
@@ -579,22 +581,43 @@ __device__ void sweep_cell(float* zs, int* is, int n, int ix, int iy, const Grid
     int64_t o = (int64_t)iy * g.nx + ix;
     int j = 0, rs = 0;
     float znext = n > 0 ? zs[0] : INFINITY;
-    for (int k = 0; k < N; ++k, o += plane) {
-        const float hk = plane_height(zmin, ds, k);
-        while (j < n && znext <= hk) {
-            if (j == 0 || znext != zs[j - 1]) rs = j;
-            ++j;
-            znext = j < n ? zs[j] : INFINITY;
+    // MERGE reads the stored values of kAhead planes before it writes
+    // any of them, so that their loads overlap
+    constexpr int kAhead = MERGE ? 8 : 1;
+    for (int k0 = 0; k0 < N; k0 += kAhead) {
+        float og[kAhead], oc[kAhead];
+        int oi[kAhead], oj[kAhead];
+        if (MERGE) {
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                if (k0 + u >= N) break;
+                const int64_t q = o + u * plane;
+                og[u] = ground[q];
+                oc[u] = ceil[q];
+                oi[u] = IDS ? ag[q] : 0;
+                oj[u] = IDS ? ac[q] : 0;
+            }
         }
-        float gz = j > 0 ? zs[j - 1] : -INFINITY, cz = znext;
-        int gi = IDS && j > 0 ? is[rs] + id_base : -1, ci = IDS && j < n ? is[j] + id_base : -1;
-        if (MERGE) merge_old<IDS>(o, ground, ceil, ag, ac, gz, gi, cz, ci);
-        // streaming stores: the grids are far larger than the caches
-        __builtin_nontemporal_store(gz, &ground[o]);
-        __builtin_nontemporal_store(cz, &ceil[o]);
-        if (IDS) {
-            __builtin_nontemporal_store(gi, &ag[o]);
-            __builtin_nontemporal_store(ci, &ac[o]);
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u, o += plane) {
+            const int k = k0 + u;
+            if (k >= N) break;
+            const float hk = plane_height(zmin, ds, k);
+            while (j < n && znext <= hk) {
+                if (j == 0 || znext != zs[j - 1]) rs = j;
+                ++j;
+                znext = j < n ? zs[j] : INFINITY;
+            }
+            float gz = j > 0 ? zs[j - 1] : -INFINITY, cz = znext;
+            int gi = IDS && j > 0 ? is[rs] + id_base : -1, ci = IDS && j < n ? is[j] + id_base : -1;
+            if (MERGE) merge_vals(og[u], oc[u], oi[u], oj[u], gz, gi, cz, ci);
+            // streaming stores: the grids are far larger than the caches
+            __builtin_nontemporal_store(gz, &ground[o]);
+            __builtin_nontemporal_store(cz, &ceil[o]);
+            if (IDS) {
+                __builtin_nontemporal_store(gi, &ag[o]);
+                __builtin_nontemporal_store(ci, &ac[o]);
+            }
         }
     }
 }

@@ -85,18 +85,51 @@ __device__ __forceinline__ Pow powers(double T) {
 
 __device__ __forceinline__ double qel(const Pow& p, int a, int b) { return kQ[a][b] * p(hexp(a) + hexp(b) - 5); }
 
+// The wavefront's state in LDS, laid out for its M pieces (M + 1 knots).
 struct Smem {
-    double T[kMaxM], tau[kMaxM];
-    double P[kMaxM + 1][3], V[kMaxM + 1][3], A[kMaxM + 1][3];
-    double Dinv[kMaxM][4], Fm[kMaxM][4], Um[kMaxM][4];  // block factors per interior knot
-    double rp[kMaxM][2][3];                             // forward-eliminated right-hand sides
-    double lam[kMaxM + 1][2][3];                        // adjoint per interior knot
-    double gx[kMaxM][6][3];                             // d(effort + penalties) / d(piece end data)
-    double gT[kMaxM];                                   // ... / d T_i at fixed end data
-    double val[kMaxM];
-    double xk[kMaxM][3], xt[kMaxM];  // accepted variables
-    double gk[kMaxM][3], gt[kMaxM];  // gradient there
+    double *T, *tau;
+    double (*P)[3], (*V)[3], (*A)[3];
+    double (*Dinv)[4], (*Fm)[4], (*Um)[4];  // block factors per interior knot
+    double (*rp)[2][3];                     // forward-eliminated right-hand sides
+    double (*lam)[2][3];                    // adjoint per interior knot
+    double (*gx)[6][3];                     // d(effort + penalties) / d(piece end data)
+    double *gT;                             // ... / d T_i at fixed end data
+    double *val;
+    double (*xk)[3], *xt;  // accepted variables
+    double (*gk)[3], *gt;  // gradient there
 };
+
+__host__ __device__ constexpr int smem_doubles(int M) {
+    return 2 * M + 3 * 3 * (M + 1) + 3 * 4 * M + 6 * M + 6 * (M + 1) + 18 * M + 2 * M + 4 * M + 4 * M;
+}
+
+__device__ __forceinline__ Smem smem_view(double* base, int M) {
+    Smem s;
+    double* p = base;
+    auto take = [&](int n) {
+        double* q = p;
+        p += n;
+        return q;
+    };
+    s.T = take(M);
+    s.tau = take(M);
+    s.P = (double(*)[3])take(3 * (M + 1));
+    s.V = (double(*)[3])take(3 * (M + 1));
+    s.A = (double(*)[3])take(3 * (M + 1));
+    s.Dinv = (double(*)[4])take(4 * M);
+    s.Fm = (double(*)[4])take(4 * M);
+    s.Um = (double(*)[4])take(4 * M);
+    s.rp = (double(*)[2][3])take(6 * M);
+    s.lam = (double(*)[2][3])take(6 * (M + 1));
+    s.gx = (double(*)[6][3])take(18 * M);
+    s.gT = take(M);
+    s.val = take(M);
+    s.xk = (double(*)[3])take(3 * M);
+    s.xt = take(M);
+    s.gk = (double(*)[3])take(3 * M);
+    s.gt = take(M);
+    return s;
+}
 
 __device__ __forceinline__ void inv2(const double m[4], double o[4]) {
     const double det = m[0] * m[3] - m[1] * m[2];
@@ -117,7 +150,7 @@ __device__ __forceinline__ void mul2(const double a[4], const double b[4], doubl
 // Interior knot states of the minimum-jerk spline: lanes 0..2 (one axis
 // each) eliminate forward; lane 0 keeps the factors for the back pass and
 // the adjoint.
-__device__ void solve_knots(Smem& s, int M) {
+__device__ __forceinline__ void solve_knots(const Smem& s, int M) {
     const int ax = threadIdx.x;
     if (ax < 3) {
         double Dp[4] = {0, 0, 0, 0}, Up[4] = {0, 0, 0, 0}, rprev[2] = {0, 0};
@@ -189,7 +222,7 @@ __device__ void solve_knots(Smem& s, int M) {
 
 // The adjoint: H lambda = d(effort + penalties) / d(interior knot
 // velocities and accelerations), with the factors of solve_knots.
-__device__ void solve_adjoint(Smem& s, int M) {
+__device__ __forceinline__ void solve_adjoint(const Smem& s, int M) {
     const int ax = threadIdx.x;
     if (ax < 3) {
         double prev[2] = {0, 0};
@@ -270,7 +303,7 @@ __device__ __forceinline__ double pos3(double x) { return x > 0.0 ? x : 0.0; }
 // and s.tau.  Returns +inf (uniform over the wavefront) at a point with a
 // non-finite duration or sample.
 template <bool GRAD>
-__device__ double evaluate(Smem& s, const TrajArgs& a, int lpp, const int* __restrict__ slice, double* coef_out) {
+__device__ __forceinline__ double evaluate(const Smem& s, const TrajArgs& a, int lpp, const int* __restrict__ slice, double* coef_out) {
     const int lane = threadIdx.x;
     const int M = a.M;
     bool bad = false;
@@ -507,13 +540,17 @@ __device__ double evaluate(Smem& s, const TrajArgs& a, int lpp, const int* __res
     return phi;
 }
 
-__global__ __launch_bounds__(64) void k_traj(TrajArgs a, int lpp, const double* __restrict__ bound,
+// OPT = false: one evaluation with gradient (and coefficients); OPT = true:
+// `iters` optimiser iterations in place.
+template <bool OPT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_traj(TrajArgs a, int lpp, const double* __restrict__ bound,
                                              const int* __restrict__ slice_all, double* __restrict__ knots,
                                              double* __restrict__ tau, double* __restrict__ phi_out,
                                              double* __restrict__ gknots, double* __restrict__ gtau,
                                              double* __restrict__ coef, int iters, double step,
                                              int* __restrict__ iters_done) {
-    __shared__ Smem s;
+    extern __shared__ double s_traj[];
+    const Smem s = smem_view(s_traj, a.M);
     const int tr = blockIdx.x;
     const int lane = threadIdx.x;
     const int M = a.M;
@@ -535,7 +572,7 @@ __global__ __launch_bounds__(64) void k_traj(TrajArgs a, int lpp, const double* 
     if (lane < M) s.tau[lane] = ta[lane];
     __syncthreads();
 
-    if (iters < 0) {
+    if (!OPT) {
         double* cf = coef ? coef + (long long)tr * M * 18 : nullptr;
         const double phi = evaluate<true>(s, a, lpp, slice, cf);
         if (lane == 0) phi_out[tr] = phi;
@@ -612,8 +649,13 @@ pct_status launch_traj(const TrajArgs& a, int n_traj, const double* bound, const
     if (n_traj == 0) return PCT_OK;
     int lpp = 1;
     while (lpp * 2 * a.M <= 64) lpp *= 2;
-    hipLaunchKernelGGL(k_traj, dim3((unsigned)n_traj), dim3(64), 0, s, a, lpp, bound, slice, knots, tau, phi, gknots,
-                       gtau, coef, iters, step, iters_done);
+    const size_t lds = sizeof(double) * (size_t)smem_doubles(a.M);
+    if (iters < 0)
+        hipLaunchKernelGGL(k_traj<false>, dim3((unsigned)n_traj), dim3(64), lds, s, a, lpp, bound, slice, knots, tau, phi,
+                           gknots, gtau, coef, iters, step, iters_done);
+    else
+        hipLaunchKernelGGL(k_traj<true>, dim3((unsigned)n_traj), dim3(64), lds, s, a, lpp, bound, slice, knots, tau, phi,
+                           gknots, gtau, coef, iters, step, iters_done);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
