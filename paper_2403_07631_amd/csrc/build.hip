@@ -565,17 +565,26 @@ __device__ void sweep_cell(float* zs, int* is, int n, int ix, int iy, const Grid
                            int N, float* __restrict__ ground, float* __restrict__ ceil, int* __restrict__ ag,
                            int* __restrict__ ac, int id_base) {
     if (MERGE && n == 0) return;
-    for (int a = 1; a < n; ++a) {
-        float z = zs[a];
-        int id = IDS ? is[a] : 0;
-        int b = a - 1;
-        while (b >= 0 && rec_less(z, id, zs[b], IDS ? is[b] : 0, IDS)) {
-            zs[b + 1] = zs[b];
-            if (IDS) is[b + 1] = is[b];
-            --b;
+    // Shell sort by (height, id) with Ciura's gaps when merging (a scan can
+    // pile many new points into few cells); a plain insertion sort (gap 1)
+    // otherwise.  The order is total (ids are unique), so the result does
+    // not depend on the gaps.
+    constexpr int kGaps[] = {701, 301, 132, 57, 23, 10, 4, 1};
+    for (int gi = MERGE ? 0 : 7; gi < 8; ++gi) {
+        const int gap = kGaps[gi];
+        if (gap >= n) continue;
+        for (int a = gap; a < n; ++a) {
+            float z = zs[a];
+            int id = IDS ? is[a] : 0;
+            int b = a - gap;
+            while (b >= 0 && rec_less(z, id, zs[b], IDS ? is[b] : 0, IDS)) {
+                zs[b + gap] = zs[b];
+                if (IDS) is[b + gap] = is[b];
+                b -= gap;
+            }
+            zs[b + gap] = z;
+            if (IDS) is[b + gap] = id;
         }
-        zs[b + 1] = z;
-        if (IDS) is[b + 1] = id;
     }
     const int64_t plane = (int64_t)g.nx * g.ny;
     int64_t o = (int64_t)iy * g.nx + ix;
@@ -1195,7 +1204,25 @@ __global__ __launch_bounds__(256) void k_cell_bbox(const float* __restrict__ xyz
         x1 = max(x1, __shfl_xor(x1, o, 64));
         y1 = max(y1, __shfl_xor(y1, o, 64));
     }
-    if ((threadIdx.x & 63) == 0 && x1 >= 0) {
+    // one set of atomics per workgroup: they all go to the same four words
+    __shared__ int s_bb[4][4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_bb[w][0] = x0;
+        s_bb[w][1] = y0;
+        s_bb[w][2] = x1;
+        s_bb[w][3] = y1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; ++v) {
+            x0 = min(x0, s_bb[v][0]);
+            y0 = min(y0, s_bb[v][1]);
+            x1 = max(x1, s_bb[v][2]);
+            y1 = max(y1, s_bb[v][3]);
+        }
+    }
+    if (threadIdx.x == 0 && x1 >= 0) {
         atomicMin(&bb[0], x0);
         atomicMin(&bb[1], y0);
         atomicMax(&bb[2], x1);
@@ -1214,7 +1241,7 @@ pct_status launch_cell_bbox(const float* xyz, int64_t n, const GridDev& g, int* 
     hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(1), 0, s, d_bb);
     PCT_LAUNCH_CHECK();
     if (n > 0) {
-        const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+        const int64_t blocks = std::min<int64_t>(512, (n + 255) / 256);
         hipLaunchKernelGGL(k_cell_bbox, dim3((unsigned)blocks), dim3(256), 0, s, xyz, n, g, d_bb);
         PCT_LAUNCH_CHECK();
     }
