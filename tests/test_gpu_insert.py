@@ -107,3 +107,35 @@ def test_insert_full_size_building(P):
     new = box_scan(12, (40.0, 46.0), (55.0, 61.0), (0.0, 14.0), 200_000)
     bb, win = insert_and_check(P, sc.points, new, sc.grid, r)
     say(f"full-size insert: box {bb}, window {win}: equal to the union's")
+
+
+def test_insert_degenerate_cases(P):
+    """No points, points outside the grid only, a window outside the grid and
+    a whole-map window."""
+    import torch
+    sc = scenes.multistorey_scene(47, 6.3, 5.7, 80_000, n_floors=2)
+    g = sc.grid
+    r = P.robot_from_physical(sc.robot, g["res"])
+    xyz = torch.from_numpy(sc.points).cuda()
+    ext = P.pct_tomogram_extent(xyz, g)
+    G, Cc, aG, aC = P.pct_build_tomogram(xyz, g, ext, with_ids=True)
+    cost, keep = P.pct_eval_traversability(G, Cc, g, ext, [r])
+    cost, keep = cost[0].contiguous(), keep[0].contiguous()
+    before = [t.clone() for t in (G, Cc, aG, aC, cost, keep)]
+    n_used, n_dropped = ext.n_used, ext.n_dropped
+    bb = P.pct_tomogram_insert(torch.zeros((0, 3), device="cuda"), g, ext, G, Cc, aG, aC, id_base=len(sc.points))
+    assert bb[2] < bb[0] and (ext.n_used, ext.n_dropped) == (n_used, n_dropped)
+    outside = torch.tensor([[-5.0, 1.0, 0.5], [1.0, 100.0, 0.5], [float("nan"), 1.0, 0.5]], device="cuda")
+    bb = P.pct_tomogram_insert(outside, g, ext, G, Cc, aG, aC, id_base=len(sc.points))
+    assert bb[2] < bb[0] and (ext.n_used, ext.n_dropped) == (n_used, n_dropped + 3)
+    P.pct_eval_traversability_window(G, Cc, g, ext, r, (-50, -50, -10, -10), cost, keep)
+    P.pct_eval_traversability_window(G, Cc, g, ext, r, (g["nx"] + 5, 0, g["nx"] + 9, g["ny"]), cost, keep)
+    torch.cuda.synchronize()
+    for a, b in zip((G, Cc, aG, aC, cost, keep), before):
+        np.testing.assert_array_equal(bits(a), bits(b))
+    # a window covering the map (and more) equals the whole-map evaluation
+    cost.fill_(-1.0)
+    P.pct_eval_traversability_window(G, Cc, g, ext, r, (-3, -3, g["nx"] + 3, g["ny"] + 3), cost, keep)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bits(cost), bits(before[4]))
+    np.testing.assert_array_equal(bits(keep), bits(before[5]))
