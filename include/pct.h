@@ -287,6 +287,22 @@ typedef struct {
 /* Workspace bytes for the batched calls (the largest of the three). */
 size_t pct_batch_workspace_bytes(const pct_item* h_items, int32_t n_items, int32_t n_robots, int32_t with_ids);
 
+/* Graph capture on a stream, for callers without a framework of their own:
+ * pct_graph_begin starts capturing `stream` (thread-local mode); the library
+ * calls enqueued on it until pct_graph_end are recorded instead of run, and
+ * pct_graph_end returns an instantiated graph that pct_graph_launch replays
+ * on any stream.  Only calls that need no host synchronisation can be
+ * captured: the batched construction and evaluation with
+ * PCT_DESCRIPTORS_RESIDENT, the sampling and gradient calls.  A replay reads
+ * and writes the buffers the captured calls named.  pct_graph_end fails
+ * (and discards the capture) when a captured call was not capturable.
+ * pct_graph_destroy frees the graph. */
+typedef struct pct_graph_s* pct_graph;
+pct_status pct_graph_begin(void* stream);
+pct_status pct_graph_end(void* stream, pct_graph* out);
+pct_status pct_graph_launch(pct_graph graph, void* stream);
+pct_status pct_graph_destroy(pct_graph graph);
+
 /* pct_tomogram_extent for every item, in one launch and one stream
  * synchronisation.  d_xyz holds n_total points; item i uses points
  * [xyz_offset, xyz_offset + n_points).  Writes h_items[i].extent and the

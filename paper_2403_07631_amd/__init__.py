@@ -326,6 +326,36 @@ def pct_unique_cells(ground, ceil, cost, keep, grid, extent: pct_extent, robot, 
     return out
 
 
+# --------------------------------------------------------------------- graphs
+
+class Graph:
+    """A graph captured through the library's own helpers
+    (pct_graph_begin / pct_graph_end) on a torch stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.handle = C.c_void_p()
+
+    def __enter__(self):
+        _check("pct_graph_begin", lib().pct_graph_begin(C.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        st = lib().pct_graph_end(C.c_void_p(self.stream.cuda_stream), C.byref(self.handle))
+        if exc_type is None:
+            _check("pct_graph_end", st)
+        return False
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check("pct_graph_launch", lib().pct_graph_launch(self.handle, C.c_void_p(s.cuda_stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().pct_graph_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+
 # --------------------------------------------------------------------- trajectory optimisation
 
 _TRAJ_FIELDS = ("w_z", "w_c", "w_v", "w_a", "w_h", "w_T", "c_safe", "v_max", "a_max", "d_ref", "d_min")

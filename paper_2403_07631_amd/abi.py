@@ -93,6 +93,10 @@ def load(path):
         "pct_tomogram_insert": ([vp, i64, i32, G, E, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "pct_eval_traversability_window": ([vp, vp, G, E, Rb, i32, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "pct_unique_cells": ([vp, vp, vp, vp, G, E, Rb, i64, vp, vp, vp, vp, vp, C.POINTER(i64), vp, sz, vp], i32),
+        "pct_graph_begin": ([vp], i32),
+        "pct_graph_end": ([vp, C.POINTER(vp)], i32),
+        "pct_graph_launch": ([vp, vp], i32),
+        "pct_graph_destroy": ([vp], i32),
         "pct_traj_eval": ([vp, vp, vp, G, E, Tp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "pct_traj_optimize": ([vp, vp, vp, G, E, Tp, i32, i32, vp, vp, vp, vp, i32, C.c_double, vp, vp, vp], i32),
     }

@@ -918,6 +918,52 @@ pct_status pct_eval_traversability_window(const float* d_ground, const float* d_
     return PCT_OK;
 }
 
+struct pct_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+pct_status pct_graph_begin(void* stream) {
+    clear_error();
+    if (!stream) return fail(PCT_ERR_ARG, "graph capture needs a stream other than the null stream");
+    PCT_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+    return PCT_OK;
+}
+
+pct_status pct_graph_end(void* stream, pct_graph* out) {
+    clear_error();
+    if (!stream || !out) return fail(PCT_ERR_ARG, "stream and out are required");
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    PCT_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(PCT_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(err));
+    }
+    pct_graph h = new pct_graph_s{g, e};
+    *out = h;
+    return PCT_OK;
+}
+
+pct_status pct_graph_launch(pct_graph graph, void* stream) {
+    clear_error();
+    if (!graph) return fail(PCT_ERR_ARG, "graph is null");
+    PCT_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return PCT_OK;
+}
+
+pct_status pct_graph_destroy(pct_graph graph) {
+    clear_error();
+    if (!graph) return PCT_OK;
+    const hipError_t e1 = hipGraphExecDestroy(graph->exec);
+    const hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(PCT_ERR_DEVICE, "destroying the graph failed");
+    return PCT_OK;
+}
+
 namespace {
 
 pct_status traj_args(const float* d_cost, const float* d_ground, const float* d_ceil, const pct_grid* grid,

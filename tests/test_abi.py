@@ -259,3 +259,12 @@ def test_traj_argument_checks(P):
     assert opt(step=0.0) == P.PCT_ERR_ARG
     assert opt(step=float("nan")) == P.PCT_ERR_ARG
     assert ev(n=0) == P.PCT_OK                        # nothing to do
+
+
+def test_graph_helpers_reject_before_device_calls(P):
+    import ctypes as C
+    L = P.lib()
+    assert L.pct_graph_begin(None) == P.PCT_ERR_ARG          # the null stream cannot be captured
+    assert L.pct_graph_end(None, None) == P.PCT_ERR_ARG
+    assert L.pct_graph_launch(None, None) == P.PCT_ERR_ARG
+    assert L.pct_graph_destroy(None) == P.PCT_OK

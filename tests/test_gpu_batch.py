@@ -141,6 +141,47 @@ def test_graph_capture_replays(P):
         _ = (xyz * 2.0).sum().item()      # unrelated eager work between replays
 
 
+def test_graph_capture_with_library_helpers(P):
+    """The same capture through the C ABI's pct_graph_begin / pct_graph_end:
+    every replay equals the eager run; an empty capture replays as a no-op."""
+    import torch
+    items, pts, specs = make_batch(64, 6, extra_empty=False)
+    xyz = torch.from_numpy(pts).cuda()
+    rb = P.robot_from_physical(scenes.ROBOT_CONFIG0, 0.1)
+    b = P.Batch(xyz, specs)
+    P.pct_tomogram_extent_batched(b)
+    G, Cc, _, _ = P.pct_build_tomogram_batched(b)
+    cost, keep = P.pct_eval_traversability_batched(b, G, Cc, [rb])
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (G, Cc, cost, keep)]
+    outs = (torch.empty_like(G), torch.empty_like(Cc), None, None)
+    couts = (torch.empty_like(cost), torch.empty_like(keep))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P.pct_build_tomogram_batched(b, out=outs)
+        P.pct_eval_traversability_batched(b, outs[0], outs[1], [rb], out=couts)
+        torch.cuda.synchronize()
+        graph = P.Graph(s)
+        with graph:
+            P.pct_build_tomogram_batched(b, flags=P.PCT_DESCRIPTORS_RESIDENT, out=outs)
+            P.pct_eval_traversability_batched(b, outs[0], outs[1], [rb], flags=P.PCT_DESCRIPTORS_RESIDENT, out=couts)
+        empty = P.Graph(s)
+        with empty:
+            pass
+    for rep in range(3):
+        for t in (*outs[:2], *couts):
+            t.zero_()
+        torch.cuda.synchronize()
+        graph.launch(s)
+        empty.launch(s)
+        s.synchronize()
+        for a, r in zip((*outs[:2], *couts), ref):
+            assert torch.equal(a.view(torch.uint8), r.view(torch.uint8)), f"replay {rep} differs"
+        _ = (xyz * 2.0).sum().item()      # unrelated eager work between replays
+    del graph, empty
+
+
 def test_full_size_submap_batch(P, oracle_lib):
     """512 submaps of 50-400 cells and 10k-1M points (the batching
     workload), batched in the benchmark's configuration; every 32nd item is
