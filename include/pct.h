@@ -133,6 +133,15 @@ size_t pct_extent_workspace_bytes(int64_t n);
 pct_status pct_tomogram_extent(const float* d_xyz, int64_t n, const pct_grid* grid, pct_extent* h_out,
                                void* d_ws, size_t ws_bytes, void* stream);
 
+/* pct_tomogram_extent without the host synchronisation, so that it can be
+ * enqueued ahead or captured in a graph: the same record, written to
+ * d_out (device memory, one pct_extent) when the stream reaches it.  Where
+ * the host version fails on the plane rule, n_slices is -1 (two planes
+ * coincide in FP32) or -2 (more than PCT_MAX_SLICES planes).  Workspace as
+ * for pct_tomogram_extent (at least 256 bytes when n = 0). */
+pct_status pct_tomogram_extent_device(const float* d_xyz, int64_t n, const pct_grid* grid, pct_extent* d_out,
+                                      void* d_ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for pct_build_tomogram. */
 size_t pct_build_workspace_bytes(int64_t n, const pct_grid* grid, const pct_extent* extent);
 

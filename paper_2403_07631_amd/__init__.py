@@ -144,6 +144,28 @@ def pct_tomogram_extent(xyz, grid) -> pct_extent:
     return out
 
 
+def pct_tomogram_extent_device(xyz, grid, out=None, workspace=None):
+    """The extent record written to device memory without a host
+    synchronisation: a uint8 tensor of sizeof(pct_extent) bytes (decode with
+    ``extent_from_bytes``)."""
+    xyz = _points(xyz)
+    g = grid_struct(grid)
+    n = xyz.shape[0]
+    need = lib().pct_extent_workspace_bytes(n)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, xyz.device)
+    if out is None:
+        out = torch.empty(C.sizeof(pct_extent), dtype=torch.uint8, device=xyz.device)
+    _check("pct_tomogram_extent_device",
+           lib().pct_tomogram_extent_device(_ptr(xyz) if n else None, n, C.byref(g), _ptr(out), _ptr(ws), ws.numel(),
+                                            _stream(xyz.device)))
+    return out
+
+
+def extent_from_bytes(t) -> pct_extent:
+    """Decodes the record written by pct_tomogram_extent_device."""
+    return pct_extent.from_buffer_copy(bytes(t.cpu().numpy().tobytes()))
+
+
 def pct_build_tomogram(xyz, grid, extent: pct_extent, with_ids: bool = False, workspace=None):
     """Returns (ground, ceil, arg_ground, arg_ceil); the ids are None unless
     ``with_ids``.  Shapes [N, ny, nx]."""

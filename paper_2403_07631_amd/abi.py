@@ -64,6 +64,7 @@ def load(path):
         "pct_plane_heights": ([E, f32, vp, i32], i32),
         "pct_extent_workspace_bytes": ([i64], sz),
         "pct_tomogram_extent": ([vp, i64, G, E, vp, sz, vp], i32),
+        "pct_tomogram_extent_device": ([vp, i64, G, vp, vp, sz, vp], i32),
         "pct_build_workspace_bytes": ([i64, G, E], sz),
         "pct_build_tomogram": ([vp, i64, G, E, vp, vp, vp, vp, vp, sz, vp], i32),
         "pct_eval_workspace_bytes": ([G, E, i32], sz),

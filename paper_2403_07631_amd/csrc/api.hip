@@ -249,6 +249,19 @@ pct_status pct_tomogram_extent(const float* d_xyz, int64_t n, const pct_grid* gr
     return PCT_OK;
 }
 
+pct_status pct_tomogram_extent_device(const float* d_xyz, int64_t n, const pct_grid* grid, pct_extent* d_out,
+                                      void* d_ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    if (!d_out) return fail(PCT_ERR_ARG, "d_out is null");
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count %lld outside [0, 2^31)", (long long)n);
+    if (n > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    if (!d_ws || ws_bytes < extent_ws_bytes(n))
+        return fail(PCT_ERR_WORKSPACE, "extent workspace too small: %zu < %zu", ws_bytes, extent_ws_bytes(n));
+    return launch_extent_record(d_xyz, n, make_grid_dev(*grid), grid->slice_dz, d_ws, d_out, (hipStream_t)stream);
+}
+
 size_t pct_build_workspace_bytes(int64_t n, const pct_grid* grid, const pct_extent* extent) {
     (void)extent;
     if (!grid || check_grid(grid) != PCT_OK || n < 0) return 0;

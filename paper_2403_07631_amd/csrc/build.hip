@@ -1084,6 +1084,50 @@ pct_status launch_extent(const float* xyz, int64_t n, const GridDev& g, void* ws
     return PCT_OK;
 }
 
+// The extent record on the device, with the plane count of the plane rule
+// (-1: two planes coincide in FP32; -2: more than PCT_MAX_SLICES planes).
+__global__ void k_extent_record(const ExtentDev* __restrict__ x, int64_t n, float ds, pct_extent* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    pct_extent e{};
+    e.z_min = INFINITY;
+    e.z_max = -INFINITY;
+    const unsigned long long used = n > 0 ? x->used : 0ull;
+    e.n_used = (int64_t)used;
+    e.n_dropped = n - (int64_t)used;
+    if (used > 0) {
+        e.z_min = x->zmin;
+        e.z_max = x->zmax;
+        int N = -2;
+        float prev = -INFINITY;
+        for (int k = 0; k < PCT_MAX_SLICES; ++k) {
+            const float h = plane_height(e.z_min, ds, k);
+            if (!(h > prev)) {
+                N = -1;
+                break;
+            }
+            if (h > e.z_max) {
+                N = k + 1;
+                break;
+            }
+            prev = h;
+        }
+        e.n_slices = N;
+    }
+    *out = e;
+}
+
+pct_status launch_extent_record(const float* xyz, int64_t n, const GridDev& g, float ds, void* ws, pct_extent* d_out,
+                                hipStream_t s) {
+    ExtentDev* d_x = (ExtentDev*)((char*)ws + extent_ws_bytes(n) - align_up(sizeof(ExtentDev)));
+    if (n > 0) {
+        pct_status st = launch_extent(xyz, n, g, ws, d_x, s);
+        if (st != PCT_OK) return st;
+    }
+    hipLaunchKernelGGL(k_extent_record, dim3(1), dim3(64), 0, s, d_x, n, ds, d_out);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
 size_t build_ws_bytes(int64_t n, const GridDev& g, bool ids) { return carve_build_ws(nullptr, n, g, ids).bytes; }
 
 pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmin, float ds, int N, float* ground,

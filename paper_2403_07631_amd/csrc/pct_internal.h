@@ -113,6 +113,8 @@ pct_status make_eval_params(const pct_robot& r, const pct_grid& g, int N, EvalPa
 pct_status launch_extent(const float* xyz, int64_t n, const GridDev& g, void* ws, ExtentDev* d_out,
                          hipStream_t s);
 size_t extent_ws_bytes(int64_t n);
+pct_status launch_extent_record(const float* xyz, int64_t n, const GridDev& g, float ds, void* ws, pct_extent* d_out,
+                                hipStream_t s);
 
 size_t build_ws_bytes(int64_t n, const GridDev& g, bool ids);
 pct_status launch_cell_bbox(const float* xyz, int64_t n, const GridDev& g, int* d_bb, hipStream_t s);

@@ -276,3 +276,40 @@ def test_full_size_config1_windows(P, oracle_lib):
     eG = g.cpu().numpy()
     cT = cost[0].cpu().numpy().astype(np.float64)
     assert oracle_lib.simplify_check(eG, cT, cT, r["c_barrier"], 0.0, keep[0].cpu().numpy()) == -1
+
+
+def test_extent_on_device_matches_host(P):
+    """The capturable extent record equals the host call's, also for no
+    points, points outside the grid only, and when captured in a graph."""
+    import torch
+    sc = scenes.config0_scene()
+    xyz = torch.from_numpy(sc.points).cuda()
+    want = P.pct_tomogram_extent(xyz, sc.grid)
+    got = P.extent_from_bytes(P.pct_tomogram_extent_device(xyz, sc.grid))
+    for f in ("z_min", "z_max", "n_slices", "n_used", "n_dropped"):
+        assert getattr(got, f) == getattr(want, f), f
+    empty = P.extent_from_bytes(P.pct_tomogram_extent_device(xyz[:0], sc.grid))
+    assert (empty.n_slices, empty.n_used, empty.n_dropped) == (0, 0, 0) and empty.z_min == float("inf")
+    far = torch.full((5, 3), -1000.0, device="cuda")
+    out = P.extent_from_bytes(P.pct_tomogram_extent_device(far, sc.grid))
+    assert (out.n_slices, out.n_used, out.n_dropped) == (0, 0, 5)
+    # captured once, replayed after the points change
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    rec = torch.empty(32, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(P.lib().pct_extent_workspace_bytes(xyz.shape[0]), dtype=torch.uint8, device="cuda")
+    pts = xyz.clone()
+    with torch.cuda.stream(s):
+        P.pct_tomogram_extent_device(pts, sc.grid, out=rec, workspace=ws)
+        torch.cuda.synchronize()
+        graph = P.Graph(s)
+        with graph:
+            P.pct_tomogram_extent_device(pts, sc.grid, out=rec, workspace=ws)
+    pts[:, 2] += 1.5
+    torch.cuda.synchronize()
+    graph.launch(s)
+    s.synchronize()
+    moved = P.pct_tomogram_extent(pts, sc.grid)
+    got = P.extent_from_bytes(rec)
+    assert (got.z_min, got.z_max, got.n_slices, got.n_used) == (moved.z_min, moved.z_max, moved.n_slices, moved.n_used)
+    del graph
