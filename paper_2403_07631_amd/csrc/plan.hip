@@ -429,32 +429,59 @@ __global__ __launch_bounds__(64) void k_plan_path(PlanGeom g, const float* __res
     const int lane = threadIdx.x;
     long long v = (long long)gl * g.plane + (long long)gy * g.nx + gx;
     const long long s = (long long)sl * g.plane + (long long)sy * g.nx + sx;
+    __shared__ int s_layer[PCT_MAX_SLICES];
+    __shared__ int s_row[64][3];
+    for (int i = lane; i < g.L; i += 64) s_layer[i] = layers[i];
+    __syncthreads();
     int len = 0, status = 0;
-    if (dist[v] < INFINITY) {
+    // the current node's distance and cost travel with it: each step loads
+    // the candidates' distance, cost and gateway bits in one round and takes
+    // the chosen one's by a shuffle, so a step waits on one memory round.
+    // Path rows collect in LDS and go out 64 at a time (a store in flight
+    // would hold up the next step's loads).
+    auto flush = [&](int n_rows) {
+        __syncthreads();
+        if (lane < n_rows) {
+            const int r = len - n_rows + lane;
+            path[3 * r] = s_row[lane][0];
+            path[3 * r + 1] = s_row[lane][1];
+            path[3 * r + 2] = s_row[lane][2];
+        }
+        __syncthreads();
+    };
+    double dv = dist[v];
+    float cv = cn[v];
+    int x = gx, y = gy, l = gl;  // v's coordinates travel with it too (no divisions)
+    if (dv < INFINITY) {
         for (;;) {
             if (len >= max_len) {
                 status = -2;
                 break;
             }
-            const int l = (int)(v / g.plane);
-            const long long c = v - (long long)l * g.plane;
-            const int x = (int)(c % g.nx), y = (int)(c / g.nx);
+            const long long c = (long long)y * g.nx + x;
             if (lane == 0) {
-                path[3 * len] = x;
-                path[3 * len + 1] = y;
-                path[3 * len + 2] = layers[l];
+                s_row[len & 63][0] = x;
+                s_row[len & 63][1] = y;
+                s_row[len & 63][2] = s_layer[l];
             }
             ++len;
+            if ((len & 63) == 0) flush(64);
             if (v == s) break;
-            const double dv = dist[v];
             long long u = -1;
+            double du = 0.0;
+            float cu = 0.0f;
+            int ux = x, uy = y, ul = l;
             bool ok = false;
             if (lane < 2) {
                 const int m = lane == 0 ? l - 1 : l + 1;
                 if (m >= 0 && m < g.L) {
                     const long long uu = (long long)m * g.plane + c;
                     const unsigned bit = lane == 0 ? kOutUp : kOutDown;
-                    if ((gw[uu] & bit) && dist[uu] + 0.0 == dv) {
+                    const uint8_t gb = gw[uu];
+                    du = dist[uu];
+                    cu = cn[uu];
+                    ul = m;
+                    if ((gb & bit) && du + 0.0 == dv) {
                         u = uu;
                         ok = true;
                     }
@@ -464,11 +491,14 @@ __global__ __launch_bounds__(64) void k_plan_path(PlanGeom g, const float* __res
                 const int dy = e < 3 ? -1 : (e < 5 ? 0 : 1);
                 const int dx = e < 3 ? e - 1 : (e < 5 ? (e == 3 ? -1 : 1) : e - 6);
                 const int x2 = x + dx, y2 = y + dy;
-                const float cv = cn[v];
                 if (x2 >= 0 && y2 >= 0 && x2 < g.nx && y2 < g.ny && cv < INFINITY) {
                     const long long uu = (long long)l * g.plane + (long long)y2 * g.nx + x2;
+                    du = dist[uu];
+                    cu = cn[uu];
+                    ux = x2;
+                    uy = y2;
                     const double wgt = (double)cv + ((dx != 0 && dy != 0) ? kSqrt2 : 1.0);
-                    if (dist[uu] + wgt == dv) {
+                    if (du + wgt == dv) {
                         u = uu;
                         ok = true;
                     }
@@ -481,8 +511,15 @@ __global__ __launch_bounds__(64) void k_plan_path(PlanGeom g, const float* __res
             }
             const int first = __ffsll((long long)m) - 1;
             v = __shfl(u, first, 64);
+            dv = __shfl(du, first, 64);
+            cv = __shfl(cu, first, 64);
+            x = __shfl(ux, first, 64);
+            y = __shfl(uy, first, 64);
+            l = __shfl(ul, first, 64);
         }
     }
+    if ((len & 63) != 0) flush(len & 63);
+    __syncthreads();
     if (status == 0) {
         // reverse rows: start first
         for (int a = lane; a < len / 2; a += 64) {
