@@ -398,6 +398,21 @@ pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const p
                              int32_t n_layers, int32_t sx, int32_t sy, int32_t s_layer, double band, double* d_dist,
                              void* d_ws, size_t ws_bytes, int32_t* h_rounds, int64_t* h_tiles, void* stream);
 
+/* A single query, as the section's A* answers it: pct_plan_distance that
+ * stops once the goal's distance is final, i.e. when the least key of the
+ * tiles still active (a lower bound on every label they can still lower)
+ * exceeds the goal's label.  Then every label below *h_settled is final
+ * (equal to pct_plan_distance's), the goal's included; the others are upper
+ * bounds.  *h_goal_dist: the goal's least path cost (+inf: unreachable,
+ * after a complete search); *h_settled = +inf when the search ran to the
+ * end.  pct_plan_path reads the goal's path back from d_dist unchanged.
+ * Arguments otherwise as pct_plan_distance; synchronous. */
+pct_status pct_plan_query(const float* d_cost, const float* d_ground, const pct_grid* grid, const pct_extent* extent,
+                          const pct_robot* h_robot, const int32_t* h_layers, int32_t n_layers, int32_t sx, int32_t sy,
+                          int32_t s_layer, int32_t gx, int32_t gy, int32_t g_layer, double band, double* d_dist,
+                          void* d_ws, size_t ws_bytes, double* h_goal_dist, double* h_settled, int32_t* h_rounds,
+                          int64_t* h_tiles, void* stream);
+
 /* A least-cost path from the start to the goal (gx, gy, layer g_layer),
  * read back from d_dist of the preceding pct_plan_distance call with the
  * same workspace: from the goal, the first predecessor whose distance plus

@@ -259,6 +259,33 @@ def pct_plan_distance(cost, ground, grid, extent: pct_extent, robot, layers, sta
     return dist, ws, {"rounds": int(rounds.value), "tiles": int(tiles.value)}
 
 
+def pct_plan_query(cost, ground, grid, extent: pct_extent, robot, layers, start, goal, workspace=None, dist=None,
+                   band=0.0):
+    """Goal-directed search: stops once the goal's distance is final.
+    Returns (dist, workspace, {"rounds", "tiles", "goal_dist", "settled"});
+    labels below ``settled`` are final."""
+    g, rb = grid_struct(grid), robot_struct(robot)
+    N = extent.n_slices
+    for t in (cost, ground):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (N, g.ny, g.nx)):
+            raise ValueError("cost/ground must be contiguous CUDA float32 [N, ny, nx]")
+    lay = (C.c_int32 * len(layers))(*[int(v) for v in layers])
+    L = len(layers)
+    dev = cost.device
+    if dist is None:
+        dist = torch.empty((L, g.ny, g.nx), dtype=torch.float64, device=dev)
+    need = lib().pct_plan_workspace_bytes(g.nx, g.ny, max(L, 1))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    rounds, tiles, gd, st = C.c_int32(), C.c_int64(), C.c_double(), C.c_double()
+    _check("pct_plan_query",
+           lib().pct_plan_query(_ptr(cost), _ptr(ground), C.byref(g), C.byref(extent), C.byref(rb), lay, L,
+                                int(start[0]), int(start[1]), int(start[2]), int(goal[0]), int(goal[1]),
+                                int(goal[2]), float(band), _ptr(dist), _ptr(ws), ws.numel(), C.byref(gd), C.byref(st),
+                                C.byref(rounds), C.byref(tiles), _stream(dev)))
+    return dist, ws, {"rounds": int(rounds.value), "tiles": int(tiles.value), "goal_dist": float(gd.value),
+                      "settled": float(st.value)}
+
+
 def pct_plan_path(dist, grid, start, goal, workspace, max_len=None):
     """Least-cost path as int32 [n, 3] rows (x, y, slice index), start
     first, on the device; None if the goal is unreachable."""

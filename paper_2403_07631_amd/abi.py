@@ -88,6 +88,8 @@ def load(path):
         "pct_plan_workspace_bytes": ([i32, i32, i32], sz),
         "pct_plan_distance": ([vp, vp, G, E, Rb, vp, i32, i32, i32, i32, C.c_double, vp, vp, sz, C.POINTER(i32),
                                C.POINTER(i64), vp], i32),
+        "pct_plan_query": ([vp, vp, G, E, Rb, vp, i32, i32, i32, i32, i32, i32, i32, C.c_double, vp, vp, sz,
+                            C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i32), C.POINTER(i64), vp], i32),
         "pct_plan_path": ([vp, G, i32, i32, i32, i32, i32, i32, i32, vp, i32, C.POINTER(i32), vp, sz, vp], i32),
         "pct_unique_workspace_bytes": ([G, E], sz),
         "pct_insert_workspace_bytes": ([i64, G], sz),

@@ -761,6 +761,52 @@ pct_status pct_plan_distance(const float* d_cost, const float* d_ground, const p
     return st;
 }
 
+pct_status pct_plan_query(const float* d_cost, const float* d_ground, const pct_grid* grid, const pct_extent* extent,
+                          const pct_robot* h_robot, const int32_t* h_layers, int32_t n_layers, int32_t sx, int32_t sy,
+                          int32_t s_layer, int32_t gx, int32_t gy, int32_t g_layer, double band, double* d_dist,
+                          void* d_ws, size_t ws_bytes, double* h_goal_dist, double* h_settled, int32_t* h_rounds,
+                          int64_t* h_tiles, void* stream) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    const int N = extent->n_slices;
+    if (n_layers < 1 || n_layers > N) return fail(PCT_ERR_ARG, "n_layers %d outside [1, %d]", n_layers, N);
+    if (!h_layers) return fail(PCT_ERR_ARG, "h_layers is null");
+    for (int l = 0; l < n_layers; ++l) {
+        if (h_layers[l] < 0 || h_layers[l] >= N || (l > 0 && h_layers[l] <= h_layers[l - 1]))
+            return fail(PCT_ERR_ARG, "layers must be strictly increasing slice indices in [0, %d)", N);
+    }
+    st = check_node(grid, n_layers, sx, sy, s_layer, "start");
+    if (st != PCT_OK) return st;
+    st = check_node(grid, n_layers, gx, gy, g_layer, "goal");
+    if (st != PCT_OK) return st;
+    if (!d_cost || !d_ground || !d_dist) return fail(PCT_ERR_ARG, "device pointers are null");
+    if (!(band >= 0.0)) return fail(PCT_ERR_ARG, "band must be >= 0");
+    const size_t need = plan_ws_bytes(grid->nx, grid->ny, n_layers);
+    if (!d_ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "plan workspace too small: %zu < %zu", ws_bytes, need);
+    const long long plane = (long long)grid->nx * grid->ny;
+    const long long goal = (long long)g_layer * plane + (long long)gy * grid->nx + gx;
+    int rounds = 0;
+    long long tiles = 0;
+    double settled = INFINITY;
+    hipStream_t s = (hipStream_t)stream;
+    st = launch_plan(d_cost, d_ground, grid->nx, grid->ny, h_layers, n_layers, h_robot->c_barrier, sx, sy, s_layer,
+                     d_dist, d_ws, &rounds, &tiles, s, band > 0.0 ? band : kPlanDefaultBand, goal, &settled);
+    if (st != PCT_OK) return st;
+    double dg = INFINITY;
+    PCT_HIP(hipMemcpyAsync(&dg, d_dist + goal, sizeof dg, hipMemcpyDeviceToHost, s));
+    PCT_HIP(hipStreamSynchronize(s));
+    if (h_goal_dist) *h_goal_dist = dg;
+    if (h_settled) *h_settled = settled;
+    if (h_rounds) *h_rounds = rounds;
+    if (h_tiles) *h_tiles = tiles;
+    return PCT_OK;
+}
+
 pct_status pct_plan_path(const double* d_dist, const pct_grid* grid, int32_t n_layers, int32_t sx, int32_t sy,
                          int32_t s_layer, int32_t gx, int32_t gy, int32_t g_layer, int32_t* d_path, int32_t max_len,
                          int32_t* h_len, void* d_ws, size_t ws_bytes, void* stream) {

@@ -382,10 +382,21 @@ __global__ __launch_bounds__(64) void k_plan_relax(PlanGeom g, const float* __re
 // list length), st[1] and st2 must be reset before the launch.
 __global__ __launch_bounds__(256) void k_plan_compact(unsigned* __restrict__ flag, unsigned long long* __restrict__ key,
                                                       int n_tiles, unsigned long long band, unsigned* __restrict__ list,
-                                                      unsigned* __restrict__ st, unsigned long long* __restrict__ st2) {
+                                                      unsigned* __restrict__ st, unsigned long long* __restrict__ st2,
+                                                      unsigned long long* __restrict__ st3) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = t < n_tiles && flag[t] != 0u;
     const unsigned long long kt = act ? key[t] : ~0ull;
+    {
+        // least key of all active tiles (a lower bound on every label still
+        // to be lowered)
+        unsigned long long kmin = kt;
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long y = __shfl_xor(kmin, o, 64);
+            kmin = y < kmin ? y : kmin;
+        }
+        if ((threadIdx.x & 63) == 0 && kmin != ~0ull) atomicMin(st3, kmin);
+    }
     const bool on = act && kt <= band;
     const bool rest = act && !on;
     const unsigned long long m = __ballot(on), mr = __ballot(rest);
@@ -404,13 +415,14 @@ __global__ __launch_bounds__(256) void k_plan_compact(unsigned* __restrict__ fla
 
 struct PlanStatus {
     unsigned n_list, n_rest;
-    unsigned long long rest_key;
+    unsigned long long rest_key, min_key;
 };
 
 __global__ void k_plan_status_reset(PlanStatus* st) {
     st->n_list = 0u;
     st->n_rest = 0u;
     st->rest_key = ~0ull;
+    st->min_key = ~0ull;
 }
 
 
@@ -573,7 +585,7 @@ size_t plan_ws_bytes(int nx, int ny, int L) { return plan_ws_layout(make_plan_ge
 
 pct_status launch_plan(const float* cost, const float* ground, int nx, int ny, const int* h_layers, int L, float cB,
                        int sx, int sy, int sl, double* dist, void* ws_base, int* h_rounds, long long* h_tiles,
-                       hipStream_t s, double delta) {
+                       hipStream_t s, double delta, long long goal, double* h_settled) {
     const PlanGeom g = make_plan_geom(nx, ny, L);
     PlanWs w;
     plan_ws_layout(g, &w, ws_base);
@@ -597,15 +609,28 @@ pct_status launch_plan(const float* cost, const float* ground, int nx, int ny, c
     int rounds = 0;
     long long tiles = 0;
     PlanStatus hs;
+    double settled = INFINITY;
     for (;;) {
         unsigned long long band_bits;
         memcpy(&band_bits, &band, sizeof band_bits);
         hipLaunchKernelGGL(k_plan_status_reset, dim3(1), dim3(1), 0, s, w.st);
         hipLaunchKernelGGL(k_plan_compact, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, w.flag, w.key, nt,
-                           band_bits, w.list, &w.st->n_list, &w.st->rest_key);
+                           band_bits, w.list, &w.st->n_list, &w.st->rest_key, &w.st->min_key);
         PCT_LAUNCH_CHECK();
         PCT_HIP(hipMemcpyAsync(&hs, w.st, sizeof hs, hipMemcpyDeviceToHost, s));
+        double dg = INFINITY;
+        if (goal >= 0) PCT_HIP(hipMemcpyAsync(&dg, dist + goal, sizeof dg, hipMemcpyDeviceToHost, s));
         PCT_HIP(hipStreamSynchronize(s));
+        if (goal >= 0 && (hs.n_list != 0 || hs.n_rest != 0)) {
+            // no active tile can lower a label below its key: every label
+            // under the least key is final, the goal's among them
+            double kmin;
+            memcpy(&kmin, &hs.min_key, sizeof kmin);
+            if (kmin > dg) {
+                settled = kmin;
+                break;
+            }
+        }
         if (hs.n_list == 0) {
             if (hs.n_rest == 0) break;
             double kmin;
@@ -621,6 +646,7 @@ pct_status launch_plan(const float* cost, const float* ground, int nx, int ny, c
     }
     if (h_rounds) *h_rounds = rounds;
     if (h_tiles) *h_tiles = tiles;
+    if (h_settled) *h_settled = settled;
     return PCT_OK;
 }
 

@@ -226,3 +226,45 @@ def test_full_size_building(P):
             tot = tot + 0.0
     assert tot == d[goal[2], goal[1], goal[0]]
     say(f"full-size building: path of {len(p)} nodes to the farthest node, cost {tot:.3f}")
+
+
+def check_query(P, oracle_lib, cT, eG, layers, start, goals, what, cb=CB):
+    """Goal-directed queries: the goal's distance and path equal the oracle's
+    full search; every label below the settled bound equals the oracle's;
+    the query takes no more rounds than the full search."""
+    import torch
+    N, ny, nx = cT.shape
+    c = torch.from_numpy(np.ascontiguousarray(cT, np.float32)).cuda()
+    e = torch.from_numpy(np.ascontiguousarray(eG, np.float32)).cuda()
+    g = grid_of(ny, nx)
+    ref = oracle_lib.plan(cT[layers], eG[layers], cb, start)
+    _, _, full = P.pct_plan_distance(c, e, g, extent_of(N), robot_cb(P, cb), layers, start)
+    for goal in goals:
+        dist, ws, info = P.pct_plan_query(c, e, g, extent_of(N), robot_cb(P, cb), layers, start, goal)
+        d = dist.cpu().numpy()
+        want = ref[goal[2], goal[1], goal[0]]
+        assert np.float64(info["goal_dist"]).view(np.uint64) == np.float64(want).view(np.uint64)
+        settled = d < info["settled"]
+        np.testing.assert_array_equal(d[settled].view(np.uint64), ref[settled].view(np.uint64))
+        assert np.all(d[~settled] >= ref[~settled])
+        assert info["rounds"] <= full["rounds"]
+        p = P.pct_plan_path(dist, g, start, goal, ws)
+        rp = oracle_lib.plan_path(cT[layers], eG[layers], cb, ref, start, goal)
+        if rp is None:
+            assert p is None
+        else:
+            rp[:, 2] = np.asarray(layers)[rp[:, 2]]
+            np.testing.assert_array_equal(p.cpu().numpy(), rp)
+        say(f"query {what} to {goal}: distance and path equal the full search's, {info['rounds']} of "
+            f"{full['rounds']} rounds, {int(settled.sum())} labels settled")
+
+
+def test_goal_directed_queries(P, oracle_lib):
+    cT, eG = scenes.plan_layers(21, 6, 700, 517, p_block=0.25, p_same=0.4)
+    layers = [0, 1, 3, 4, 5]
+    check_query(P, oracle_lib, cT, eG, layers, (258, 350, 2),
+                [(270, 360, 2), (300, 420, 0), (10, 10, 4), (258, 350, 2)], "700x517")
+    cT, eG = scenes.plan_serpentine(13, 300, 257, pitch=6)
+    check_query(P, oracle_lib, cT, eG, [0], (0, 0, 0), [(0, 40, 0), (256, 150, 0)], "serpentine")
+    cT, eG = scenes.plan_layers(14, 2, 64, 64, p_block=0.6)
+    check_query(P, oracle_lib, cT, eG, [0, 1], (10, 10, 0), [(63, 63, 1), (11, 10, 0)], "sparse")
