@@ -579,6 +579,34 @@ def case_plan():
     plan_run(cT, np.zeros_like(cT), [0], (0, 0, 0), [(0, 0, 0)], "single cell")
 
 
+def case_plan_query():
+    """Goal-directed queries: the goal's distance equals the oracle's full
+    Dijkstra, labels below the settled bound are exact, the others upper
+    bounds."""
+    cT, eG = scenes.plan_layers(21, 3, 150, 130)
+    layers, start = [0, 1, 2], (7, 140, 0)
+    ref = oracle.plan(cT, eG, 50.0, start)
+    N, ny, nx = cT.shape
+    gs = grid_s(dict(x0=0.0, y0=0.0, res=0.1, nx=nx, ny=ny, slice_dz=0.3))
+    e = abi.pct_extent(0.0, 1.0, N, 0, 0, 0)
+    r = robot()
+    r["c_barrier"] = 50.0
+    rb = robot_s(r)
+    cb, eb = Buf.of(np.ascontiguousarray(cT, np.float32)), Buf.of(np.ascontiguousarray(eG, np.float32))
+    dist, ws = Buf(8 * N * ny * nx), Buf(L.pct_plan_workspace_bytes(nx, ny, N))
+    lay = (C.c_int32 * 3)(*layers)
+    for goal in [(20, 130, 0), (100, 20, 2), (7, 140, 0)]:
+        gd, st, ro, ti = C.c_double(), C.c_double(), C.c_int32(), C.c_int64()
+        check("plan_query", L.pct_plan_query(P(cb), P(eb), C.byref(gs), C.byref(e), C.byref(rb), lay, 3, *start,
+                                             *goal, 0.0, P(dist), P(ws), ws.nbytes, C.byref(gd), C.byref(st),
+                                             C.byref(ro), C.byref(ti), None))
+        d = dist.get((N, ny, nx), np.float64)
+        sm = d < st.value
+        assert gd.value == ref[goal[2], goal[1], goal[0]], (goal, gd.value)
+        assert np.array_equal(d[sm], ref[sm]) and np.all(d[~sm] >= ref[~sm])
+        say(f"plan query to {goal}: distance {gd.value:.3f} exact, {ro.value} rounds, {int(sm.sum())} labels settled")
+
+
 def unique_run(eG, eC, cT, keep, what):
     """Unique cells of the kept slices against the oracle's, bit for bit."""
     N, ny, nx = eG.shape

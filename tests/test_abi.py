@@ -268,3 +268,23 @@ def test_graph_helpers_reject_before_device_calls(P):
     assert L.pct_graph_end(None, None) == P.PCT_ERR_ARG
     assert L.pct_graph_launch(None, None) == P.PCT_ERR_ARG
     assert L.pct_graph_destroy(None) == P.PCT_OK
+
+
+def test_plan_query_argument_checks(P):
+    import ctypes as C
+    L = P.lib()
+    g = P.grid_struct(dict(x0=0.0, y0=0.0, res=0.1, nx=100, ny=80, slice_dz=0.3))
+    e = P.pct_extent(0.0, 1.0, 5, 0, 0, 0)
+    rb = P.robot_struct(P.robot_from_physical(scenes.ROBOT_CONFIG0, 0.1))
+    d = C.c_void_p(16)
+    lay = (C.c_int32 * 2)(0, 2)
+    gd, st, ro, ti = C.c_double(), C.c_double(), C.c_int32(), C.c_int64()
+
+    def q(goal, start=(0, 0, 0), ws_bytes=1 << 30):
+        return L.pct_plan_query(d, d, C.byref(g), C.byref(e), C.byref(rb), lay, 2, *start, *goal, 0.0, d, d,
+                                ws_bytes, C.byref(gd), C.byref(st), C.byref(ro), C.byref(ti), None)
+
+    assert q((100, 0, 0)) == P.PCT_ERR_ARG       # goal outside the map
+    assert q((0, 0, 2)) == P.PCT_ERR_ARG         # goal layer outside
+    assert q((0, 0, 1), start=(0, 80, 0)) == P.PCT_ERR_ARG
+    assert q((0, 0, 1), ws_bytes=16) == P.PCT_ERR_WORKSPACE

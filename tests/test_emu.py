@@ -65,6 +65,7 @@ GROUPS = [
     (("batch", "batch_resident", "batch_mixed_radius"), "rand"),
     (("traj_value_grad", "autotune"), "fwd"),
     (("plan", "unique"), "rand"),
+    (("plan_query",), "fwd"),
     (("insert", "traj_opt"), "rev"),
 ]
 
