@@ -226,6 +226,19 @@ def test_full_size_building(P):
             tot = tot + 0.0
     assert tot == d[goal[2], goal[1], goal[0]]
     say(f"full-size building: path of {len(p)} nodes to the farthest node, cost {tot:.3f}")
+    # the benchmark's single query: a goal 26.5 m away on the start layer
+    ys, xs = np.nonzero(np.isfinite(d[0]))
+    kq = int(np.argmin(np.abs(np.hypot(xs - s[0], ys - s[1]) - 265.0)))
+    qgoal = (int(xs[kq]), int(ys[kq]), 0)
+    dq, wq, qi = P.pct_plan_query(cost, G, g, ext, r, layers, s, qgoal)
+    dqn = dq.cpu().numpy()
+    settled = dqn < qi["settled"]
+    assert qi["goal_dist"] == d[0, qgoal[1], qgoal[0]]
+    np.testing.assert_array_equal(dqn[settled].view(np.uint64), d[settled].view(np.uint64))
+    assert np.all(dqn[~settled] >= d[~settled])
+    pq = P.pct_plan_path(dq, g, s, qgoal, wq).cpu().numpy()
+    np.testing.assert_array_equal(pq, P.pct_plan_path(dist, g, s, qgoal, ws).cpu().numpy())
+    say(f"full-size building: query to {qgoal} in {qi['rounds']} rounds, same cost and path as the full field")
 
 
 def check_query(P, oracle_lib, cT, eG, layers, start, goals, what, cb=CB):
