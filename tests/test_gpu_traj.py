@@ -147,3 +147,59 @@ def test_traj_building_launch(P):
         assert abs(phi0[t] - p_o) <= 1e-9 * max(1.0, abs(p_o))
     say(f"building: 4096 trajectories x 32 pieces, objective {phi0.mean():.1f} -> {phi.mean():.1f} "
         f"in {done.mean():.1f} iterations on average")
+
+
+def test_traj_from_searched_path(P):
+    """The section's pipeline: a path found by the path search through the
+    slices (Sec. III-D) gives the initial waypoints (every 8th node, cell
+    centres at body height) of a trajectory that the optimiser smooths; its
+    objective drops and matches the oracle's at the start and at the end."""
+    import torch
+    from oracle import traj as otraj
+    sc = scenes.plan_building()
+    g = sc.grid
+    xyz = torch.from_numpy(sc.points).cuda()
+    ext = P.pct_tomogram_extent(xyz, g)
+    G, Cc, _, _ = P.pct_build_tomogram(xyz, g, ext)
+    r = dict(scenes.ROBOT_TABLE1)
+    cost, keep = P.pct_eval_traversability(G, Cc, g, ext, [r])
+    cost = cost[0].contiguous()
+    layers = [int(v) for v in np.flatnonzero(keep[0].cpu().numpy())]
+    cT, eG = cost.cpu().numpy(), G.cpu().numpy()
+    ys, xs = np.nonzero((cT[layers[0]] < r["c_barrier"]) & (eG[layers[0]] < 0.5))
+    k = int(np.argmin((ys - 500) ** 2 + (xs - 500) ** 2))
+    s = (int(xs[k]), int(ys[k]), 0)
+    full, _, _ = P.pct_plan_distance(cost, G, g, ext, r, layers, s)
+    d0 = full[0].cpu().numpy()
+    gy, gx = np.nonzero(np.isfinite(d0))
+    kg = int(np.argmin(np.abs(np.hypot(gx - s[0], gy - s[1]) - 190.0)))
+    goal = (int(gx[kg]), int(gy[kg]), 0)
+    dist, ws, info = P.pct_plan_query(cost, G, g, ext, r, layers, s, goal)
+    assert np.isfinite(info["goal_dist"])
+    path = P.pct_plan_path(dist, g, s, goal, ws).cpu().numpy()
+    step = max(8, -(-(len(path) - 1) // 64))
+    nodes = path[::step] if (len(path) - 1) % step == 0 else np.vstack([path[::step], path[-1:]])
+    M = len(nodes) - 1
+    assert 2 <= M <= 64
+    res = g["res"]
+    pts = np.column_stack([g["x0"] + (nodes[:, 0] + 0.5) * res, g["y0"] + (nodes[:, 1] + 0.5) * res,
+                           eG[nodes[:, 2], nodes[:, 1], nodes[:, 0]] + r["d_ref"]]).astype(np.float64)
+    bound = np.zeros((1, 2, 3, 3))
+    bound[0, 0, 0], bound[0, 1, 0] = pts[0], pts[-1]
+    pr = dict(bound=bound, slices=nodes[1:, 2][None, :].astype(np.int32), knots=pts[1:-1][None].copy(),
+              tau=np.log(np.full((1, M), step * res / 0.8)))
+    prm = dict(PRM, d_ref=r["d_ref"], d_min=r["d_min"], c_safe=10.0, samples=8)
+    d = {kk: torch.from_numpy(np.ascontiguousarray(v)).cuda() for kk, v in pr.items()}
+    phi0, _, _ = P.pct_traj_eval(cost, G, Cc, g, ext, prm, d["bound"], d["slices"], d["knots"], d["tau"])
+    phi, done = P.pct_traj_optimize(cost, G, Cc, g, ext, prm, d["bound"], d["slices"], d["knots"], d["tau"], 30, 1e-4)
+    torch.cuda.synchronize()
+    maps = (cT, eG, Cc.cpu().numpy())
+    p0, _, _ = otraj.objective(pr["knots"][0], pr["tau"][0], bound[0, 0], bound[0, 1], pr["slices"][0], maps, g, prm,
+                               grad=False)
+    assert abs(float(phi0[0]) - p0) <= 1e-9 * max(1.0, abs(p0))
+    p1, _, _ = otraj.objective(d["knots"][0].cpu().numpy(), d["tau"][0].cpu().numpy(), bound[0, 0], bound[0, 1],
+                               pr["slices"][0], maps, g, prm, grad=False)
+    assert abs(float(phi[0]) - p1) <= 1e-9 * max(1.0, abs(p1))
+    assert float(phi[0]) < float(phi0[0]) and int(done[0]) >= 1
+    say(f"searched path of {len(path)} nodes -> {M} pieces: objective {float(phi0[0]):.1f} -> {float(phi[0]):.1f} "
+        f"in {int(done[0])} iterations")
