@@ -476,6 +476,10 @@ __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, u
 // wavefront reductions and atomics per cell.
 constexpr int kSimpCells = 4;
 
+// A lane's cells are cell0 + c * STRIDE for c < nact (nact <= kSimpCells).
+// STRIDE = 64 interleaves the lanes of a wavefront, so that each load
+// instruction reads 256 contiguous bytes.
+template <int STRIDE>
 __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ ground, const float* __restrict__ cost,
                                                  long long plane, int N, float cB, int W, int* __restrict__ maxp0,
                                                  unsigned* __restrict__ urun, long long cell0, int nact) {
@@ -486,8 +490,8 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const bool act = c < nact;
-        ek[c] = act ? ground[cell0 + c] : -INFINITY;
-        ck[c] = act ? cost[cell0 + c] : cB;
+        ek[c] = act ? ground[cell0 + c * STRIDE] : -INFINITY;
+        ck[c] = act ? cost[cell0 + c * STRIDE] : cB;
         eprev[c] = -INFINITY;
         p0[c] = 0;
     }
@@ -497,8 +501,8 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const bool ld = k + 1 < N && c < nact;
-            ek1[c] = ld ? ground[nb + c] : -INFINITY;
-            ck1[c] = ld ? cost[nb + c] : cB;
+            ek1[c] = ld ? ground[nb + c * STRIDE] : -INFINITY;
+            ck1[c] = ld ? cost[nb + c * STRIDE] : cB;
         }
         int mloc = -1, pminloc = 0x7fffffff;
         bool runA[CPT];
@@ -522,7 +526,7 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
                 for (int pp = pb; pp < pe; ++pp) {
 #pragma unroll
                     for (int c = 0; c < CPT; ++c) {
-                        if (runA[c] && pp >= p0[c] && cost[(long long)pp * plane + cell0 + c] > ck[c])
+                        if (runA[c] && pp >= p0[c] && cost[(long long)pp * plane + cell0 + c * STRIDE] > ck[c])
                             bits |= 1u << (pp - w * 32);
                     }
                 }
@@ -543,10 +547,12 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__
                                                        const int nx, const int ny, const int N, const float cB,
                                                        const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun) {
     const long long plane = (long long)nx * ny;
-    const long long cell0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * kSimpCells;
+    // the wavefront's 64 x kSimpCells cells, lane-interleaved
+    const long long wave0 = ((long long)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kSimpCells;
+    const long long cell0 = wave0 + (threadIdx.x & 63);
     const long long left = plane - cell0;
-    const int nact = left <= 0 ? 0 : (left < kSimpCells ? (int)left : kSimpCells);
-    simp_flags_cells(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact);
+    const int nact = left <= 0 ? 0 : (int)std::min<long long>(kSimpCells, (left + 63) / 64);
+    simp_flags_cells<64>(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact);
 }
 
 __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
@@ -606,7 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restr
     const int N = jb.p.N, W = (N + 31) / 32;
     int* maxp0 = (int*)(ws + jb.ws_off);
     unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    simp_flags_cells(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
+    simp_flags_cells<1>(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
                      nact > 0 ? cell0 : 0, nact);
 }
 
