@@ -602,18 +602,18 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restr
                                                             char* __restrict__ ws) {
     // global padded cell of this lane's first cell; a wavefront's 64 x kSimpCells
     // cells never span two jobs (job ranges are padded to that)
-    const long long g = ((long long)blockIdx.x * kBlock + threadIdx.x) * kSimpCells;
-    const int j = __builtin_amdgcn_readfirstlane(
-        find_job_cell(jobs, n_jobs, g - (long long)(threadIdx.x & 63) * kSimpCells));
+    const long long wave0 = ((long long)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kSimpCells;
+    const int j = __builtin_amdgcn_readfirstlane(find_job_cell(jobs, n_jobs, wave0));
     const EvalJob& jb = jobs[j];
-    const long long cell0 = g - jb.cell_base;
+    // the wavefront's cells, lane-interleaved as in the single-map kernel
+    const long long cell0 = wave0 - jb.cell_base + (threadIdx.x & 63);
     const long long left = jb.p.plane - cell0;
-    const int nact = (cell0 < 0 || left <= 0) ? 0 : (left < kSimpCells ? (int)left : kSimpCells);
+    const int nact = (cell0 < 0 || left <= 0) ? 0 : (int)std::min<long long>(kSimpCells, (left + 63) / 64);
     const int N = jb.p.N, W = (N + 31) / 32;
     int* maxp0 = (int*)(ws + jb.ws_off);
     unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    simp_flags_cells<1>(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
-                     nact > 0 ? cell0 : 0, nact);
+    simp_flags_cells<64>(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
+                         nact > 0 ? cell0 : 0, nact);
 }
 
 __global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, const char* __restrict__ ws,
