@@ -85,28 +85,31 @@ __global__ __launch_bounds__(kUBlock) void k_uniq_count(const float* __restrict_
     }
 }
 
-// Exclusive scan of n counts in place (one workgroup, chunk by chunk);
-// total[0] receives the sum.
+// Exclusive scan of n counts in place (one workgroup): each thread sums a
+// contiguous run, the run sums are scanned across the workgroup, and each
+// thread writes its run's prefixes.  total[0] receives the sum.
 __global__ __launch_bounds__(1024) void k_uniq_scan(unsigned long long* __restrict__ v, long long n,
                                                     unsigned long long* __restrict__ total) {
     __shared__ unsigned long long s_part[1024];
-    unsigned long long carry = 0;
-    for (long long base = 0; base < n; base += 1024) {
-        const long long i = base + threadIdx.x;
-        const unsigned long long x = i < n ? v[i] : 0ull;
-        s_part[threadIdx.x] = x;
+    const long long per = (n + 1023) / 1024;
+    const long long b = (long long)threadIdx.x * per, e = b + per < n ? b + per : n;
+    unsigned long long sum = 0;
+    for (long long i = b; i < e; ++i) sum += v[i];
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const unsigned long long y = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0ull;
         __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            const unsigned long long y = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0ull;
-            __syncthreads();
-            s_part[threadIdx.x] += y;
-            __syncthreads();
-        }
-        if (i < n) v[i] = carry + s_part[threadIdx.x] - x;
-        carry += s_part[1023];
+        s_part[threadIdx.x] += y;
         __syncthreads();
     }
-    if (threadIdx.x == 0) total[0] = carry;
+    unsigned long long run = s_part[threadIdx.x] - sum;
+    for (long long i = b; i < e; ++i) {
+        const unsigned long long x = v[i];
+        v[i] = run;
+        run += x;
+    }
+    if (threadIdx.x == 1023) total[0] = s_part[1023];
 }
 
 template <bool VEC>
