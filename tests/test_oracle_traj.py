@@ -13,6 +13,8 @@
   - missing ground drops the height terms; an open ceiling drops its term;
   - autograd gradients equal central differences of the forward on maps
     that are linear in x and y (the interpolation then has no kinks);
+  - a cost map linear in the cell indices and the textbook profile's speed
+    and acceleration give closed forms of the map and kinematic terms;
   - one piece with a time weight: the optimiser reaches the closed-form
     duration T* = (5 * 720 |Delta|^2 / w_T)^(1/6), and its objective never
     increases.
@@ -228,3 +230,52 @@ def test_optimizer_reaches_closed_form_duration():
         seen.append(phi)
     assert all(b <= a for a, b in zip(seen, seen[1:]))
     assert np.exp(tau[0]) == pytest.approx(t_star, rel=1e-6)
+
+
+def test_linear_cost_map_closed_form():
+    """Bilinear interpolation reproduces a map that is linear in the cell
+    indices, so on a straight constant-velocity line the cost term is the
+    trapezoid sum of (C(q(t)) - C_safe)^3 with C written out directly."""
+    nx, ny, res = 40, 30, 0.5
+    a0, bx, by = 2.0, 0.25, -0.125
+    jj, ii = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    cT = np.stack([a0 + bx * ii + by * jj] * 2).astype(np.float32)
+    eG = np.full_like(cT, -np.inf)
+    eC = np.full_like(cT, np.inf)
+    grid = dict(x0=0.0, y0=0.0, res=res, nx=nx, ny=ny)
+    v = np.array([1.5, 0.75, 0.0])
+    p0 = np.array([3.1, 4.2, 1.0])
+    Ts = np.array([1.25, 0.75])
+    knots = np.array([p0 + v * Ts[0]])
+    goal = state(p0 + v * Ts.sum(), v)
+    K = 5
+    prm = dict(ZERO_W, w_c=1.0, c_safe=-1.0, samples=K)
+    phi, _, _ = traj.objective(knots, np.log(Ts), state(p0, v), goal, [1, 0], (cT, eG, eC), grid, prm)
+    want, t0 = 0.0, 0.0
+    for T in Ts:
+        for j in range(K + 1):
+            t = T * j / K
+            q = p0 + v * (t0 + t)
+            C = a0 + bx * (q[0] / res - 0.5) + by * (q[1] / res - 0.5)
+            want += (T / K) * (0.5 if j in (0, K) else 1.0) * (C + 1.0) ** 3
+        t0 += T
+    assert phi == pytest.approx(want, rel=1e-12)
+
+
+def test_kinematic_terms_on_textbook_profile():
+    """Speed and acceleration penalties along the rest-to-rest profile, with
+    its velocity Delta (30 s^2 - 60 s^3 + 30 s^4) / T and acceleration
+    Delta (60 s - 180 s^2 + 120 s^3) / T^2 written out."""
+    d = np.array([3.0, -2.0, 0.5])
+    T, K = 2.0, 7
+    f32 = lambda x: float(np.float32(x))
+    prm = dict(ZERO_W, w_v=0.3, v_max=0.5, w_a=0.2, a_max=0.4, samples=K)
+    phi, _, _ = traj.objective(np.zeros((0, 3)), [np.log(T)], REST, state(d), [0], flat_maps(), GRID, prm)
+    want = 720 * (d @ d) / T ** 5
+    for j in range(K + 1):
+        s = j / K
+        v = d * (30 * s ** 2 - 60 * s ** 3 + 30 * s ** 4) / T
+        a = d * (60 * s - 180 * s ** 2 + 120 * s ** 3) / T ** 2
+        w = T / K * (0.5 if j in (0, K) else 1.0)
+        want += w * (f32(0.3) * max(0.0, v @ v - f32(0.5) ** 2) ** 3 + f32(0.2) * max(0.0, a @ a - f32(0.4) ** 2) ** 3)
+    assert phi == pytest.approx(want, rel=1e-11)
