@@ -85,31 +85,46 @@ __global__ __launch_bounds__(kUBlock) void k_uniq_count(const float* __restrict_
     }
 }
 
-// Exclusive scan of n counts in place (one workgroup): each thread sums a
-// contiguous run, the run sums are scanned across the workgroup, and each
-// thread writes its run's prefixes.  total[0] receives the sum.
+// Exclusive scan of n counts in place (one workgroup of 16 wavefronts),
+// 4096 counts at a time: four consecutive counts per thread, an inclusive
+// scan of the thread sums within each wavefront by shuffles, then the
+// wavefront totals across the workgroup.  total[0] receives the sum.
 __global__ __launch_bounds__(1024) void k_uniq_scan(unsigned long long* __restrict__ v, long long n,
                                                     unsigned long long* __restrict__ total) {
-    __shared__ unsigned long long s_part[1024];
-    const long long per = (n + 1023) / 1024;
-    const long long b = (long long)threadIdx.x * per, e = b + per < n ? b + per : n;
-    unsigned long long sum = 0;
-    for (long long i = b; i < e; ++i) sum += v[i];
-    s_part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const unsigned long long y = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0ull;
+    __shared__ unsigned long long s_wave[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long carry = 0;
+    for (long long base = 0; base < n; base += 4096) {
+        const long long i0 = base + 4 * (long long)threadIdx.x;
+        unsigned long long x[4], sum = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            x[c] = i0 + c < n ? v[i0 + c] : 0ull;
+            sum += x[c];
+        }
+        unsigned long long incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl(incl, lane - o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_wave[wave] = incl;
         __syncthreads();
-        s_part[threadIdx.x] += y;
+        unsigned long long before = carry, chunk = 0;
+        for (int w = 0; w < 16; ++w) {
+            const unsigned long long t = s_wave[w];
+            if (w < wave) before += t;
+            chunk += t;
+        }
+        unsigned long long run = before + incl - sum;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (i0 + c < n) v[i0 + c] = run;
+            run += x[c];
+        }
+        carry += chunk;
         __syncthreads();
     }
-    unsigned long long run = s_part[threadIdx.x] - sum;
-    for (long long i = b; i < e; ++i) {
-        const unsigned long long x = v[i];
-        v[i] = run;
-        run += x;
-    }
-    if (threadIdx.x == 1023) total[0] = s_part[1023];
+    if (threadIdx.x == 0) total[0] = carry;
 }
 
 template <bool VEC>
