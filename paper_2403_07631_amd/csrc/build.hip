@@ -217,15 +217,26 @@ __global__ __launch_bounds__(kBinBlock) void k_bin1_hist(const float* __restrict
 __device__ unsigned wave_scan_row(unsigned* __restrict__ row, int len) {
     const int lane = threadIdx.x & 63;
     unsigned carry = 0;
-    for (int base = 0; base < len; base += 64) {
-        const unsigned v = base + lane < len ? row[base + lane] : 0u;
-        unsigned incl = v;
-        for (int d = 1; d < 64; d <<= 1) {
-            const unsigned u = __shfl(incl, lane - d, 64);
-            if (lane >= d) incl += u;
+    // four 64-entry pieces per pass, their loads issued together (one
+    // wavefront per row leaves the loop bound by load latency otherwise)
+    for (int base = 0; base < len; base += 256) {
+        unsigned v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = base + 64 * q + lane;
+            v[q] = i < len ? row[i] : 0u;
         }
-        if (base + lane < len) row[base + lane] = carry + incl - v;
-        carry += __shfl(incl, 63, 64);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = base + 64 * q + lane;
+            unsigned incl = v[q];
+            for (int d = 1; d < 64; d <<= 1) {
+                const unsigned u = __shfl(incl, lane - d, 64);
+                if (lane >= d) incl += u;
+            }
+            if (i < len) row[i] = carry + incl - v[q];
+            carry += __shfl(incl, 63, 64);
+        }
     }
     return carry;
 }
