@@ -71,7 +71,7 @@ def check_eval(P, grid, maps, prm, pr, ts):
 
 
 @pytest.mark.parametrize("M,K,n", [(1, 4, 3), (2, 1, 3), (5, 7, 4), (16, 16, 2), (33, 3, 2), (64, 2, 1),
-                                   (3, 64, 2)])
+                                   (3, 64, 2), (64, 64, 1)])
 def test_traj_eval_matches_oracle(P, small_map, M, K, n):
     grid, maps = small_map
     N = maps[0].shape[0]
