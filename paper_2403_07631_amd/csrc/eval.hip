@@ -523,11 +523,23 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
             for (int w = pmin / 32; w <= (k - 1) / 32; ++w) {
                 unsigned bits = 0;
                 const int pb = max(pmin, w * 32), pe = min(k, w * 32 + 32);
-                for (int pp = pb; pp < pe; ++pp) {
+                // eight earlier slices at a time, their loads issued together
+                for (int pp0 = pb; pp0 < pe; pp0 += 8) {
+                    float cv[8][CPT];
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c) {
-                        if (runA[c] && pp >= p0[c] && cost[(long long)pp * plane + cell0 + c * STRIDE] > ck[c])
-                            bits |= 1u << (pp - w * 32);
+                    for (int u = 0; u < 8; ++u) {
+                        const int pp = pp0 + u;
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c)
+                            cv[u][c] = (pp < pe && runA[c] && pp >= p0[c])
+                                           ? cost[(long long)pp * plane + cell0 + c * STRIDE]
+                                           : -INFINITY;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c)
+                            if (cv[u][c] > ck[c]) bits |= 1u << (pp0 + u - w * 32);
                     }
                 }
                 bits = wave_or(bits);
