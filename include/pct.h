@@ -188,6 +188,26 @@ pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, c
                                    const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
                                    float* d_cost, uint8_t* d_keep, void* d_ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation and slice test as pct_eval_traversability, with the slice
+ * test's scratch (per-slice run starts and an N x N bit matrix) in a
+ * library-owned static device array of PCT_STATIC_WORKSPACE_BYTES instead
+ * of a caller workspace.  Each GPU the library runs on holds its own copy
+ * of that array until the process ends; the first call on a device finds
+ * its address (with that device current).  The call allocates nothing and
+ * clears the part of the array it uses before using it.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or threads without ordering) race and give wrong keep flags.
+ * The stream must belong to the current device (PCT_ERR_ARG otherwise).
+ * PCT_ERR_CAPACITY when the slice test would need more than the array
+ * holds (it cannot for n_slices <= PCT_MAX_SLICES).  Other arguments,
+ * outputs and errors as pct_eval_traversability. */
+#define PCT_STATIC_WORKSPACE_BYTES (136u * 1024u)
+pct_status pct_eval_traversability_static(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                          const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
+                                          float* d_cost, uint8_t* d_keep, void* stream);
+
 /* Autotuner for pct_eval_traversability.  Times the evaluation of this
  * map shape for each candidate strip height (the rows of one slice that
  * one wavefront walks: 32, 64, ... up to the first at or above ny, at most

@@ -208,6 +208,38 @@ def pct_eval_traversability(ground, ceil, grid, extent: pct_extent, robots, keep
     return cost, kp
 
 
+def pct_eval_traversability_static(ground, ceil, grid, extent: pct_extent, robots, keep: bool = True,
+                                   cost=None, keep_out=None):
+    """pct_eval_traversability with the slice test's scratch in the library's
+    static device array (the call allocates nothing on the device itself).
+    ``cost`` [R, N, ny, nx] float32 and ``keep_out`` [R, N] uint8 may be
+    given; otherwise they are allocated here, before the call.
+    Returns (cost, keep or None)."""
+    if isinstance(robots, (pct_robot, dict)):
+        robots = [robots]
+    rs = (pct_robot * len(robots))(*[robot_struct(r) for r in robots])
+    g = grid_struct(grid)
+    N = extent.n_slices
+    dev = ground.device
+    for t in (ground, ceil):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == (N, g.ny, g.nx)):
+            raise ValueError("ground/ceil must be contiguous CUDA float32 [N, ny, nx]")
+    shape = (len(robots), N, g.ny, g.nx)
+    if cost is None:
+        cost = torch.empty(shape, dtype=torch.float32, device=dev)
+    elif not (cost.is_cuda and cost.dtype == torch.float32 and cost.is_contiguous() and tuple(cost.shape) == shape):
+        raise ValueError("cost must be contiguous CUDA float32 %s" % (shape,))
+    kp = None
+    if keep:
+        kp = keep_out if keep_out is not None else torch.empty((len(robots), N), dtype=torch.uint8, device=dev)
+        if not (kp.is_cuda and kp.dtype == torch.uint8 and kp.is_contiguous() and tuple(kp.shape) == (len(robots), N)):
+            raise ValueError("keep_out must be contiguous CUDA uint8 [R, N]")
+    _check("pct_eval_traversability_static",
+           lib().pct_eval_traversability_static(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), rs,
+                                                len(robots), _ptr(cost), _ptr(kp), _stream(dev)))
+    return cost, kp
+
+
 def pct_autotune_traversability(ground, ceil, grid, extent, robot, scratch=None):
     """Tune the evaluation's strip height for this map shape (synchronous).
     Returns (best_rows, {rows: ms}); best_rows is 0 when the robot's

@@ -69,6 +69,7 @@ def load(path):
         "pct_build_tomogram": ([vp, i64, G, E, vp, vp, vp, vp, vp, sz, vp], i32),
         "pct_eval_workspace_bytes": ([G, E, i32], sz),
         "pct_eval_traversability": ([vp, vp, G, E, Rb, i32, vp, vp, vp, sz, vp], i32),
+        "pct_eval_traversability_static": ([vp, vp, G, E, Rb, i32, vp, vp, vp], i32),
         "pct_autotune_traversability": ([vp, vp, G, E, Rb, vp, C.POINTER(i32), vp, vp, i32, C.POINTER(i32), vp],
                                         i32),
         "pct_autotune_reset": ([], i32),

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "pct_internal.h"
@@ -142,6 +143,77 @@ pct_status make_eval_params(const pct_robot& r, const pct_grid& g, int N, EvalPa
     return PCT_OK;
 }
 
+}  // namespace pct
+
+namespace pct {
+namespace {
+
+pct_status eval_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                               const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots, float* d_cost,
+                               uint8_t* d_keep, void* d_ws, size_t ws_bytes, hipStream_t s) {
+    const int N = extent->n_slices;
+    const long long per_robot = (long long)N * grid->nx * grid->ny;
+    for (int i = 0; i < n_robots; ++i) {
+        EvalParams p;
+        pct_status st = make_eval_params(h_robots[i], *grid, N, &p);
+        if (st != PCT_OK) return st;
+        float* cost = d_cost + per_robot * i;
+        st = launch_eval(d_ground, d_ceil, p, cost, s);
+        if (st != PCT_OK) return st;
+        if (d_keep) {
+            st = launch_simplify(d_ground, cost, p, d_keep + (size_t)N * i, d_ws, s);
+            if (st != PCT_OK) return st;
+        }
+    }
+    (void)ws_bytes;
+    return PCT_OK;
+}
+
+pct_status check_eval_args(const float* d_ground, const float* d_ceil, const pct_grid* grid, const pct_extent* extent,
+                           const pct_robot* h_robots, int32_t n_robots, const float* d_cost) {
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (n_robots < 1 || !h_robots) return fail(PCT_ERR_ARG, "at least one robot is required");
+    for (int i = 0; i < n_robots; ++i) {
+        st = check_robot(&h_robots[i], grid->res);
+        if (st != PCT_OK) return st;
+    }
+    if (extent->n_slices > 0 && (!d_ground || !d_ceil || !d_cost)) return fail(PCT_ERR_ARG, "device pointers are null");
+    return PCT_OK;
+}
+
+// The static scratch of pct_eval_traversability_static.  In host code
+// `scratch` names a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[PCT_STATIC_WORKSPACE_BYTES];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;   // indexed by device ordinal
+
+pct_status static_scratch(hipStream_t s, void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(PCT_ERR_DEVICE, "hipGetDevice failed");
+    hipDevice_t sdev = -1;
+    hipError_t e = hipStreamGetDevice(s, &sdev);
+    if (e != hipSuccess) return fail(PCT_ERR_DEVICE, "hipStreamGetDevice failed: %s", hipGetErrorString(e));
+    if ((int)sdev != dev)
+        return fail(PCT_ERR_ARG, "the stream belongs to device %d but device %d is current", (int)sdev, dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PCT_ERR_DEVICE, "hipGetSymbolAddress of the static scratch failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return PCT_OK;
+}
+
+}  // namespace
 }  // namespace pct
 
 using namespace pct;
@@ -297,39 +369,41 @@ size_t pct_eval_workspace_bytes(const pct_grid* grid, const pct_extent* extent, 
     return eval_ws_bytes(std::max(1, (int)extent->n_slices), n_robots);
 }
 
+
 pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
                                    const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
                                    float* d_cost, uint8_t* d_keep, void* d_ws, size_t ws_bytes, void* stream) {
     clear_error();
-    pct_status st = check_grid(grid);
+    pct_status st = check_eval_args(d_ground, d_ceil, grid, extent, h_robots, n_robots, d_cost);
     if (st != PCT_OK) return st;
-    st = check_extent(extent);
-    if (st != PCT_OK) return st;
-    if (n_robots < 1 || !h_robots) return fail(PCT_ERR_ARG, "at least one robot is required");
-    for (int i = 0; i < n_robots; ++i) {
-        st = check_robot(&h_robots[i], grid->res);
-        if (st != PCT_OK) return st;
-    }
     const int N = extent->n_slices;
     if (N == 0) return PCT_OK;
-    if (!d_ground || !d_ceil || !d_cost) return fail(PCT_ERR_ARG, "device pointers are null");
     if (d_keep && (!d_ws || ws_bytes < eval_ws_bytes(N, n_robots)))
         return fail(PCT_ERR_WORKSPACE, "eval workspace too small: %zu < %zu", ws_bytes, eval_ws_bytes(N, n_robots));
+    return eval_traversability(d_ground, d_ceil, grid, extent, h_robots, n_robots, d_cost, d_keep, d_ws, ws_bytes,
+                               (hipStream_t)stream);
+}
+
+pct_status pct_eval_traversability_static(const float* d_ground, const float* d_ceil, const pct_grid* grid,
+                                          const pct_extent* extent, const pct_robot* h_robots, int32_t n_robots,
+                                          float* d_cost, uint8_t* d_keep, void* stream) {
+    clear_error();
+    pct_status st = check_eval_args(d_ground, d_ceil, grid, extent, h_robots, n_robots, d_cost);
+    if (st != PCT_OK) return st;
+    const int N = extent->n_slices;
+    if (N == 0) return PCT_OK;
+    const size_t need = eval_ws_bytes(N, n_robots);
+    if (d_keep && need > PCT_STATIC_WORKSPACE_BYTES)
+        return fail(PCT_ERR_CAPACITY, "the slice test needs %zu bytes of scratch, the static array holds %u", need,
+                    (unsigned)PCT_STATIC_WORKSPACE_BYTES);
     hipStream_t s = (hipStream_t)stream;
-    const long long per_robot = (long long)N * grid->nx * grid->ny;
-    for (int i = 0; i < n_robots; ++i) {
-        EvalParams p;
-        st = make_eval_params(h_robots[i], *grid, N, &p);
+    void* ws = nullptr;
+    if (d_keep) {
+        st = static_scratch(s, &ws);
         if (st != PCT_OK) return st;
-        float* cost = d_cost + per_robot * i;
-        st = launch_eval(d_ground, d_ceil, p, cost, s);
-        if (st != PCT_OK) return st;
-        if (d_keep) {
-            st = launch_simplify(d_ground, cost, p, d_keep + (size_t)N * i, d_ws, s);
-            if (st != PCT_OK) return st;
-        }
     }
-    return PCT_OK;
+    return eval_traversability(d_ground, d_ceil, grid, extent, h_robots, n_robots, d_cost, d_keep, ws,
+                               PCT_STATIC_WORKSPACE_BYTES, s);
 }
 
 pct_status pct_autotune_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
