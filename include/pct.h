@@ -226,6 +226,17 @@ pct_status pct_autotune_traversability(const float* d_ground, const float* d_cei
 /* Forgets every height the autotuner recorded (defaults apply again). */
 pct_status pct_autotune_reset(void);
 
+/* Records a strip height for the evaluation of maps of this shape (nx, ny,
+ * slice count) and this robot's inflation radius, as the autotuner does
+ * with the fastest candidate: for tuning results kept between processes,
+ * or to pin a height.  rows = 0 forgets the entry (the default applies).
+ * PCT_ERR_ARG if rows is not 0 and outside [16, PCT_MAX_STRIP_ROWS];
+ * PCT_ERR_CAPACITY if strips that short would need more than 2^30
+ * wavefronts for this map.  No device work. */
+#define PCT_MAX_STRIP_ROWS 4096
+pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_extent* extent, const pct_robot* h_robot,
+                                           int32_t rows);
+
 /* ---------------------------------------------------------------------- */
 /* Trajectory cost sampling (Sec. III-E) and adjoints                     */
 

@@ -262,6 +262,14 @@ def pct_autotune_reset():
     _check("pct_autotune_reset", lib().pct_autotune_reset())
 
 
+def pct_autotune_set_traversability(grid, extent, robot, rows: int):
+    """Record (rows > 0) or forget (rows = 0) the strip height used for
+    maps of this shape and this robot's inflation radius."""
+    g, rb = grid_struct(grid), robot_struct(robot)
+    _check("pct_autotune_set_traversability",
+           lib().pct_autotune_set_traversability(C.byref(g), C.byref(extent), C.byref(rb), int(rows)))
+
+
 # --------------------------------------------------------------------- path search
 
 def pct_plan_distance(cost, ground, grid, extent: pct_extent, robot, layers, start, workspace=None, dist=None,

@@ -73,6 +73,7 @@ def load(path):
         "pct_autotune_traversability": ([vp, vp, G, E, Rb, vp, C.POINTER(i32), vp, vp, i32, C.POINTER(i32), vp],
                                         i32),
         "pct_autotune_reset": ([], i32),
+        "pct_autotune_set_traversability": ([G, E, Rb, i32], i32),
         "pct_sample_cost_fwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp], i32),
         "pct_sample_cost_bwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp, vp, vp, i32, vp], i32),
         "pct_eval_traversability_bwd": ([vp, vp, G, E, Rb, vp, vp, vp, i32, vp], i32),

@@ -442,6 +442,27 @@ pct_status pct_autotune_reset(void) {
     return PCT_OK;
 }
 
+pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_extent* extent, const pct_robot* h_robot,
+                                           int32_t rows) {
+    clear_error();
+    pct_status st = check_grid(grid);
+    if (st != PCT_OK) return st;
+    st = check_extent(extent);
+    if (st != PCT_OK) return st;
+    if (!h_robot) return fail(PCT_ERR_ARG, "h_robot is null");
+    st = check_robot(h_robot, grid->res);
+    if (st != PCT_OK) return st;
+    if (rows < 0 || rows > PCT_MAX_STRIP_ROWS) return fail(PCT_ERR_ARG, "rows %d outside [0, %d]", rows, PCT_MAX_STRIP_ROWS);
+    EvalParams p;
+    st = make_eval_params(*h_robot, *grid, std::max(1, (int)extent->n_slices), &p);
+    if (st != PCT_OK) return st;
+    if (rows > 0 && rows < 16) return fail(PCT_ERR_ARG, "rows %d below 16", rows);
+    if (rows > 0 && p.rp == 1 && p.R <= 8 && !strip_rows_fit(p, rows))
+        return fail(PCT_ERR_CAPACITY, "strips of %d rows give too many wavefronts for this map", rows);
+    autotune_set(p, rows);
+    return PCT_OK;
+}
+
 namespace {
 
 pct_status check_sampling(const pct_grid* grid, const pct_extent* extent, const pct_robot* robot, int32_t T, int32_t W,

@@ -743,6 +743,20 @@ void autotune_reset() {
     g_tune_rows.clear();
 }
 
+bool strip_rows_fit(const EvalParams& p, int rows) {
+    const long long outw = 64 - 2 * (p.R + 2);
+    if (outw <= 0 || rows <= 0) return false;
+    const long long wnx = p.wx1 - p.wx0, wny = p.wy1 - p.wy0;
+    const long long work = (long long)p.N * ((wnx + outw - 1) / outw) * ((wny + rows - 1) / rows);
+    return work <= (1LL << 30);
+}
+
+void autotune_set(const EvalParams& p, int rows) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (rows > 0) g_tune_rows[TuneKey{p.nx, p.ny, p.N, p.R}] = rows;
+    else g_tune_rows.erase(TuneKey{p.nx, p.ny, p.N, p.R});
+}
+
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep, void* ws,
                            hipStream_t s) {
     const int W = (p.N + 31) / 32;

@@ -128,6 +128,8 @@ pct_status launch_eval(const float* ground, const float* ceil, const EvalParams&
 pct_status autotune_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
                          int* best_rows, int* cand_rows, float* cand_ms, int n_max, int* n_cand);
 void autotune_reset();
+void autotune_set(const EvalParams& p, int rows);
+bool strip_rows_fit(const EvalParams& p, int rows);
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
                            void* ws, hipStream_t s);
 

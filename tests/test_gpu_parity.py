@@ -214,9 +214,10 @@ def test_eval_many_robots_match_single(P, oracle_lib):
 
 
 def test_autotune_keeps_results(P):
-    """Tuning the strip height changes no value of the evaluation."""
+    """Tuning the strip height changes no value of the evaluation, on a map
+    with traversable cells."""
     import torch
-    sc = crop_scene(seed=24, n=300_000)
+    sc = scenes.multistorey_scene(24, 14.1, 10.3, 900_000, n_floors=3)
     xyz = torch.from_numpy(sc.points).cuda()
     ext = P.pct_tomogram_extent(xyz, sc.grid)
     g, c, _, _ = P.pct_build_tomogram(xyz, sc.grid, ext)
@@ -228,8 +229,71 @@ def test_autotune_keeps_results(P):
     torch.cuda.synchronize()
     P.pct_autotune_reset()
     assert best in cands and len(cands) >= 3
+    assert int((before < rb.c_barrier).sum()) > 1000
     np.testing.assert_array_equal(bits(after.cpu().numpy()), bits(before.cpu().numpy()))
     np.testing.assert_array_equal(ka.cpu().numpy(), kb.cpu().numpy())
+
+
+def test_building_every_strip_height(P, oracle_lib):
+    """The benchmark building (26.4 M points, 1000 x 1000 cells, 51 slices)
+    evaluated at every strip height the autotuner tries and at ragged ones,
+    for the Table I quadruped (inflation radius 4) and for the large map's
+    robot (radius 5, the benchmark's kernel): c^T equals the oracle's
+    Eqs. (1)-(6) to 1e-5 on windows (interior, corner, edges) that each hold
+    many traversable cells, every height gives the same bits, and the keep
+    flags follow the slice test on the library's own arrays."""
+    import torch
+    sc = scenes.plan_building()
+    grid = sc.grid
+    say("building: build")
+    xyz = torch.from_numpy(sc.points).cuda()
+    ext = P.pct_tomogram_extent(xyz, grid)
+    g, c, _, _ = P.pct_build_tomogram(xyz, grid, ext, with_ids=False)
+    torch.cuda.synchronize()
+    zmin, zmax, _ = oracle_lib.extent(sc.points, grid)
+    h = oracle_lib.planes(zmin, zmax, grid["slice_dz"])
+    assert ext.n_slices == len(h)
+    M = 7   # margin: inflation radius 5 + patch radius 1 + stencil 1
+    tomo = []
+    for wx0, wy0, wn in [(500, 500, 48), (0, 0, 40), (980, 311, 20), (413, 975, 25)]:
+        ex0, ey0 = max(0, wx0 - M), max(0, wy0 - M)
+        ex1, ey1 = min(grid["nx"], wx0 + wn + M), min(grid["ny"], wy0 + wn + M)
+        w = oracle_lib.build_window(sc.points, grid, h, ex0, ey0, ex1 - ex0, ey1 - ey0, ids=False)
+        sl = (slice(None), slice(ey0, ey1), slice(ex0, ex1))
+        np.testing.assert_array_equal(bits(g[sl].cpu().numpy()), bits(w[0]))
+        np.testing.assert_array_equal(bits(c[sl].cpu().numpy()), bits(w[1]))
+        tomo.append((wx0, wy0, wn, wy0 - ey0, wx0 - ex0, w))
+    eG = g.cpu().numpy()
+    for rname, rb in (("Table I", P.robot_struct(dict(scenes.ROBOT_TABLE1))),
+                      ("large-map robot", P.robot_from_physical(scenes.ROBOT_CONFIG0, grid["res"]))):
+        r = rb.as_dict()
+        wins = []
+        for wx0, wy0, wn, iy0, ix0, w in tomo:
+            lo, hi, _ = oracle_lib.envelope(w[0], w[1], grid["res"], r)
+            inner = (slice(None), slice(iy0, iy0 + wn), slice(ix0, ix0 + wn))
+            assert int((lo[inner] < r["c_barrier"]).sum()) > 1000, (rname, wx0, wy0)
+            wins.append((wx0, wy0, wn, lo[inner], hi[inner]))
+        first = None
+        try:
+            for rows in (32, 64, 128, 256, 512, 1024, 100, 1000):
+                P.pct_autotune_set_traversability(grid, ext, rb, rows)
+                say(f"building, {rname}: strips of {rows} rows")
+                cost, keep = P.pct_eval_traversability(g, c, grid, ext, [rb])
+                torch.cuda.synchronize()
+                for wx0, wy0, wn, lo, hi in wins:
+                    cw = cost[0][:, wy0:wy0 + wn, wx0:wx0 + wn].cpu().numpy().astype(np.float64)
+                    assert np.all(cw >= lo - TOL) and np.all(cw <= hi + TOL), (rname, rows, wx0, wy0)
+                if first is None:
+                    first = (cost, keep)
+                    cT = cost[0].cpu().numpy().astype(np.float64)
+                    assert oracle_lib.simplify_check(eG, cT, cT, r["c_barrier"], 0.0, keep[0].cpu().numpy()) == -1
+                    assert 0 < int(keep.sum()) < ext.n_slices
+                    del cT
+                else:
+                    assert torch.equal(cost.view(torch.int32), first[0].view(torch.int32)), (rname, rows)
+                    assert torch.equal(keep, first[1]), (rname, rows)
+        finally:
+            P.pct_autotune_reset()
 
 
 # --------------------------------------------------------------- full size
