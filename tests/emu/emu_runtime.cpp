@@ -357,6 +357,19 @@ hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute attr, int value) 
     return hipSuccess;
 }
 
+hipError_t hipGetDevice(int* device) {
+    *device = 0;
+    return hipSuccess;
+}
+hipError_t hipStreamGetDevice(hipStream_t, hipDevice_t* device) {
+    *device = 0;
+    return hipSuccess;
+}
+hipError_t hipGetSymbolAddress(void** ptr, const void* symbol) {
+    *ptr = const_cast<void*>(symbol);
+    return symbol ? hipSuccess : hipErrorInvalidValue;
+}
+
 // Events: launches run to completion when issued, so an event records the
 // host clock at the time it is recorded.
 struct emu_event {

@@ -34,6 +34,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) alignas(n)
 
 struct alignas(16) float4 {
     float x, y, z, w;
@@ -63,6 +64,12 @@ hipError_t hipStreamSynchronize(hipStream_t s);
 hipError_t hipGetLastError();
 const char* hipGetErrorString(hipError_t e);
 hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute attr, int value);
+// One device (ordinal 0); a __device__ variable's address is its host address.
+typedef int hipDevice_t;
+hipError_t hipGetDevice(int* device);
+hipError_t hipStreamGetDevice(hipStream_t s, hipDevice_t* device);
+hipError_t hipGetSymbolAddress(void** ptr, const void* symbol);
+#define HIP_SYMBOL(x) ((const void*)&(x))
 typedef struct emu_event* hipEvent_t;
 hipError_t hipEventCreate(hipEvent_t* e);
 hipError_t hipEventDestroy(hipEvent_t e);
