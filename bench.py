@@ -527,7 +527,7 @@ def main():
 
     g0, c0, _, _ = P.pct_build_tomogram(xyz, grid, ext0, workspace=ws_b)
     log("autotuning the evaluation's strip height")
-    tuned_rows, tune_ms = P.pct_autotune_traversability(g0, c0, grid, ext0, rb)
+    tuned_shape, tune_ms = P.pct_autotune_traversability(g0, c0, grid, ext0, rb)
     del g0, c0
 
     def step():
@@ -618,7 +618,8 @@ def main():
                      "hbm": {"alg_bytes_per_launch": eval_bytes, "achieved_gbs": eval_gbs,
                              "peak_gbs": HBM_PEAK_GBS, "frac": eval_gbs / HBM_PEAK_GBS}},
         "wall_s_timed": wall,
-        "autotune": {"strip_rows": tuned_rows, "candidates_ms": {str(k): v for k, v in tune_ms.items()}},
+        "autotune": {"strip_rows": tuned_shape[0], "strip_waves": tuned_shape[1],
+                     "candidates_ms": {f"{r}x{w}": v for (r, w), v in tune_ms.items()}},
     }
     if not args.no_batched:
         del g, c, cost, keep

@@ -209,33 +209,40 @@ pct_status pct_eval_traversability_static(const float* d_ground, const float* d_
                                           float* d_cost, uint8_t* d_keep, void* stream);
 
 /* Autotuner for pct_eval_traversability.  Times the evaluation of this
- * map shape for each candidate strip height (the rows of one slice that
- * one wavefront walks: 32, 64, ... up to the first at or above ny, at most
- * 1024) and records the fastest; later evaluations in this process of a
- * map with the same nx, ny, slice count and kernel radius use it.
- * Synchronous.  d_cost: float32 [N][ny][nx] scratch, overwritten.
- * h_rows/h_ms: host arrays of n_max entries for the candidates and their
- * times in ms (nullable); *h_count = the number of candidates;
- * *h_best_rows = the chosen height, 0 when this robot's evaluation does not
- * use strips (patch radius above 1 or inflation radius above 8). */
+ * map shape for each candidate strip shape and records the fastest; later
+ * evaluations in this process of a map with the same nx, ny, slice count
+ * and kernel radius use it.  A strip is the rows of one slice that one
+ * workgroup walks down (32, 64, ... up to the first at or above ny, at most
+ * 1024), either one wavefront per 64-column strip (waves = 1) or 2 or
+ * PCT_STRIP_WAVES wavefronts side by side sharing the inflation's row pass
+ * through LDS (waves = 2, PCT_STRIP_WAVES).  At most 24 candidates.
+ * Synchronous.
+ * d_cost: float32 [N][ny][nx] scratch, overwritten.
+ * h_rows/h_waves/h_ms: host arrays of n_max entries for the candidates'
+ * heights, wavefronts and times in ms (each nullable); *h_count = the
+ * number of candidates; *h_best_rows, *h_best_waves (nullable) = the
+ * chosen shape, rows 0 when this robot's evaluation does not use strips
+ * (patch radius above 1 or inflation radius above 8). */
+#define PCT_STRIP_WAVES 4
 pct_status pct_autotune_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
                                        const pct_extent* extent, const pct_robot* h_robot, float* d_cost,
-                                       int32_t* h_best_rows, int32_t* h_rows, float* h_ms, int32_t n_max,
-                                       int32_t* h_count, void* stream);
+                                       int32_t* h_best_rows, int32_t* h_best_waves, int32_t* h_rows,
+                                       int32_t* h_waves, float* h_ms, int32_t n_max, int32_t* h_count, void* stream);
 
 /* Forgets every height the autotuner recorded (defaults apply again). */
 pct_status pct_autotune_reset(void);
 
-/* Records a strip height for the evaluation of maps of this shape (nx, ny,
- * slice count) and this robot's inflation radius, as the autotuner does
- * with the fastest candidate: for tuning results kept between processes,
- * or to pin a height.  rows = 0 forgets the entry (the default applies).
- * PCT_ERR_ARG if rows is not 0 and outside [16, PCT_MAX_STRIP_ROWS];
- * PCT_ERR_CAPACITY if strips that short would need more than 2^30
- * wavefronts for this map.  No device work. */
+/* Records a strip shape (rows, waves as in the autotuner) for the
+ * evaluation of maps of this shape (nx, ny, slice count) and this robot's
+ * inflation radius, as the autotuner does with the fastest candidate: for
+ * tuning results kept between processes, or to pin a shape.  rows = 0
+ * forgets the entry (the default applies).  PCT_ERR_ARG if rows is not 0
+ * and outside [16, PCT_MAX_STRIP_ROWS], or waves is not 1, 2 or
+ * PCT_STRIP_WAVES; PCT_ERR_CAPACITY if strips that short would need more
+ * than 2^30 wavefronts for this map.  No device work. */
 #define PCT_MAX_STRIP_ROWS 4096
 pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_extent* extent, const pct_robot* h_robot,
-                                           int32_t rows);
+                                           int32_t rows, int32_t waves);
 
 /* ---------------------------------------------------------------------- */
 /* Trajectory cost sampling (Sec. III-E) and adjoints                     */

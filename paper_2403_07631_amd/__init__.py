@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpct.so")
 
 from .abi import (PCT_ACCUMULATE, PCT_DESCRIPTORS_RESIDENT, PCT_ERR_ARG, PCT_ERR_CAPACITY,  # noqa: F401
-                  PCT_ERR_DEVICE, PCT_ERR_WORKSPACE, PCT_MAX_SLICES, PCT_OK, _ROBOT_FIELDS, pct_extent, pct_grid,
+                  PCT_ERR_DEVICE, PCT_ERR_WORKSPACE, PCT_MAX_SLICES, PCT_OK, PCT_STRIP_WAVES, _ROBOT_FIELDS,
+                  pct_extent, pct_grid,
                   pct_item, pct_robot)
 from . import abi as _abi
 
@@ -241,33 +242,36 @@ def pct_eval_traversability_static(ground, ceil, grid, extent: pct_extent, robot
 
 
 def pct_autotune_traversability(ground, ceil, grid, extent, robot, scratch=None):
-    """Tune the evaluation's strip height for this map shape (synchronous).
-    Returns (best_rows, {rows: ms}); best_rows is 0 when the robot's
-    evaluation does not use strips."""
+    """Tune the evaluation's strip shape for this map shape (synchronous).
+    Returns ((best_rows, best_waves), {(rows, waves): ms}); best_rows is 0
+    when the robot's evaluation does not use strips.  waves = 1: one
+    wavefront per strip; waves = PCT_STRIP_WAVES: a workgroup per strip."""
     g, rb = grid_struct(grid), robot_struct(robot)
     N = extent.n_slices
     cost = scratch if scratch is not None else torch.empty((max(N, 1), g.ny, g.nx), dtype=torch.float32,
                                                            device=ground.device)
-    best, count = C.c_int32(), C.c_int32()
-    rows = (C.c_int32 * 8)()
-    ms = (C.c_float * 8)()
+    best, bw, count = C.c_int32(), C.c_int32(), C.c_int32()
+    rows = (C.c_int32 * 24)()
+    waves = (C.c_int32 * 24)()
+    ms = (C.c_float * 24)()
     _check("pct_autotune_traversability",
            lib().pct_autotune_traversability(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(rb),
-                                             _ptr(cost), C.byref(best), rows, ms, 8, C.byref(count),
-                                             _stream(ground.device)))
-    return int(best.value), {int(rows[i]): float(ms[i]) for i in range(count.value)}
+                                             _ptr(cost), C.byref(best), C.byref(bw), rows, waves, ms, 24,
+                                             C.byref(count), _stream(ground.device)))
+    return ((int(best.value), int(bw.value)),
+            {(int(rows[i]), int(waves[i])): float(ms[i]) for i in range(count.value)})
 
 
 def pct_autotune_reset():
     _check("pct_autotune_reset", lib().pct_autotune_reset())
 
 
-def pct_autotune_set_traversability(grid, extent, robot, rows: int):
-    """Record (rows > 0) or forget (rows = 0) the strip height used for
-    maps of this shape and this robot's inflation radius."""
+def pct_autotune_set_traversability(grid, extent, robot, rows: int, waves: int = PCT_STRIP_WAVES):
+    """Record (rows > 0) or forget (rows = 0) the strip shape used for maps
+    of this shape and this robot's inflation radius."""
     g, rb = grid_struct(grid), robot_struct(robot)
     _check("pct_autotune_set_traversability",
-           lib().pct_autotune_set_traversability(C.byref(g), C.byref(extent), C.byref(rb), int(rows)))
+           lib().pct_autotune_set_traversability(C.byref(g), C.byref(extent), C.byref(rb), int(rows), int(waves)))
 
 
 # --------------------------------------------------------------------- path search

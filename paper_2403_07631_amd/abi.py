@@ -11,6 +11,7 @@ PCT_MAX_PIECES = 64
 PCT_MAX_TRAJ_SAMPLES = 64
 PCT_ACCUMULATE = 1
 PCT_DESCRIPTORS_RESIDENT = 2
+PCT_STRIP_WAVES = 4
 
 
 class pct_grid(C.Structure):
@@ -70,10 +71,10 @@ def load(path):
         "pct_eval_workspace_bytes": ([G, E, i32], sz),
         "pct_eval_traversability": ([vp, vp, G, E, Rb, i32, vp, vp, vp, sz, vp], i32),
         "pct_eval_traversability_static": ([vp, vp, G, E, Rb, i32, vp, vp, vp], i32),
-        "pct_autotune_traversability": ([vp, vp, G, E, Rb, vp, C.POINTER(i32), vp, vp, i32, C.POINTER(i32), vp],
-                                        i32),
+        "pct_autotune_traversability": ([vp, vp, G, E, Rb, vp, C.POINTER(i32), C.POINTER(i32), vp, vp, vp, i32,
+                                         C.POINTER(i32), vp], i32),
         "pct_autotune_reset": ([], i32),
-        "pct_autotune_set_traversability": ([G, E, Rb, i32], i32),
+        "pct_autotune_set_traversability": ([G, E, Rb, i32, i32], i32),
         "pct_sample_cost_fwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp], i32),
         "pct_sample_cost_bwd": ([vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, vp, vp, vp, i32, vp], i32),
         "pct_eval_traversability_bwd": ([vp, vp, G, E, Rb, vp, vp, vp, i32, vp], i32),

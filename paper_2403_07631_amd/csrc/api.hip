@@ -408,8 +408,8 @@ pct_status pct_eval_traversability_static(const float* d_ground, const float* d_
 
 pct_status pct_autotune_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
                                        const pct_extent* extent, const pct_robot* h_robot, float* d_cost,
-                                       int32_t* h_best_rows, int32_t* h_rows, float* h_ms, int32_t n_max,
-                                       int32_t* h_count, void* stream) {
+                                       int32_t* h_best_rows, int32_t* h_best_waves, int32_t* h_rows,
+                                       int32_t* h_waves, float* h_ms, int32_t n_max, int32_t* h_count, void* stream) {
     clear_error();
     pct_status st = check_grid(grid);
     if (st != PCT_OK) return st;
@@ -421,6 +421,7 @@ pct_status pct_autotune_traversability(const float* d_ground, const float* d_cei
     if (!h_best_rows || !h_count) return fail(PCT_ERR_ARG, "h_best_rows and h_count are required");
     if (n_max < 0) return fail(PCT_ERR_ARG, "n_max must be >= 0");
     *h_best_rows = 0;
+    if (h_best_waves) *h_best_waves = 0;
     *h_count = 0;
     const int N = extent->n_slices;
     if (N == 0) return PCT_OK;
@@ -428,10 +429,18 @@ pct_status pct_autotune_traversability(const float* d_ground, const float* d_cei
     EvalParams p;
     st = make_eval_params(*h_robot, *grid, N, &p);
     if (st != PCT_OK) return st;
-    int best = 0, count = 0;
-    st = autotune_eval(d_ground, d_ceil, p, d_cost, (hipStream_t)stream, &best, h_rows, h_ms, n_max, &count);
+    EvalShape best{0, 0}, cand[24];
+    float ms[24];
+    int count = 0;
+    st = autotune_eval(d_ground, d_ceil, p, d_cost, (hipStream_t)stream, &best, cand, ms, 24, &count);
     if (st != PCT_OK) return st;
-    *h_best_rows = best;
+    for (int i = 0; i < count && i < n_max; ++i) {
+        if (h_rows) h_rows[i] = cand[i].rows;
+        if (h_waves) h_waves[i] = cand[i].nw;
+        if (h_ms) h_ms[i] = ms[i];
+    }
+    *h_best_rows = best.rows;
+    if (h_best_waves) *h_best_waves = best.nw;
     *h_count = count;
     return PCT_OK;
 }
@@ -443,7 +452,7 @@ pct_status pct_autotune_reset(void) {
 }
 
 pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_extent* extent, const pct_robot* h_robot,
-                                           int32_t rows) {
+                                           int32_t rows, int32_t waves) {
     clear_error();
     pct_status st = check_grid(grid);
     if (st != PCT_OK) return st;
@@ -452,14 +461,16 @@ pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_exten
     if (!h_robot) return fail(PCT_ERR_ARG, "h_robot is null");
     st = check_robot(h_robot, grid->res);
     if (st != PCT_OK) return st;
-    if (rows < 0 || rows > PCT_MAX_STRIP_ROWS) return fail(PCT_ERR_ARG, "rows %d outside [0, %d]", rows, PCT_MAX_STRIP_ROWS);
+    if (rows != 0 && (rows < 16 || rows > PCT_MAX_STRIP_ROWS))
+        return fail(PCT_ERR_ARG, "rows %d is neither 0 nor in [16, %d]", rows, PCT_MAX_STRIP_ROWS);
+    if (rows != 0 && waves != 1 && waves != 2 && waves != PCT_STRIP_WAVES)
+        return fail(PCT_ERR_ARG, "waves %d is not 1, 2 or %d", waves, PCT_STRIP_WAVES);
     EvalParams p;
     st = make_eval_params(*h_robot, *grid, std::max(1, (int)extent->n_slices), &p);
     if (st != PCT_OK) return st;
-    if (rows > 0 && rows < 16) return fail(PCT_ERR_ARG, "rows %d below 16", rows);
-    if (rows > 0 && p.rp == 1 && p.R <= 8 && !strip_rows_fit(p, rows))
+    if (rows > 0 && p.rp == 1 && p.R <= 8 && !strip_shape_fits(p, EvalShape{rows, waves}))
         return fail(PCT_ERR_CAPACITY, "strips of %d rows give too many wavefronts for this map", rows);
-    autotune_set(p, rows);
+    autotune_set(p, EvalShape{rows, waves});
     return PCT_OK;
 }
 

@@ -135,19 +135,25 @@ __global__ __launch_bounds__(kBlock) void k_eval(const float* __restrict__ groun
     }
 }
 
-// ------------------------------------------------------------ strip kernel
+// ------------------------------------------------------------ strip kernels
 //
-// The common case (patch radius 1, inflation radius <= 8): each wavefront
-// owns a strip of 64 columns of one slice and walks down its rows, keeping
-// the rows it still needs in registers:
-//   ground rows  y+R-1 .. y+R+2   (stencils of the flags and of c^init),
+// The common case (patch radius 1, inflation radius <= 8).  A workgroup of
+// NW wavefronts (1, 2 or 4) walks down the rows of one slice over a band
+// of columns, each wavefront over 64 adjacent columns, keeping the rows it
+// still needs in registers:
+//   ground rows  y+R .. y+R+2     (the stencil of the newest flag row),
 //   gentle flags y+R-1 .. y+R+1   (the 3x3 patch count),
 //   c^init rows  y-R   .. y+R     (the column pass of the inflation).
-// Horizontal neighbours come from adjacent lanes (DPP shifts by one lane,
-// ds_bpermute for the row pass).  The 2 (R+2) edge lanes are halo: they
-// compute but do not store, so a strip writes 64 - 2 (R+2) columns.
-// Per element the arithmetic is the same sequence of FP32 operations as in
-// the tiled kernel above, so both give identical bits.
+// The central differences of a row are formed once, for its gentle flag,
+// and kept for its c^init one step later.  Horizontal neighbours of the
+// stencils and the patch count come from adjacent lanes (DPP shifts by one
+// lane), so the two lanes at each side of a wavefront only complete the
+// stencils of the middle kWgOwn, its own columns.  The row pass of the
+// inflation reads the column-pass maxima of the neighbouring columns from
+// LDS, where every wavefront leaves those of its own columns; only the
+// outer R own columns of the workgroup are halo.  Per element the
+// arithmetic is the same sequence of FP32 operations as in the tiled kernel
+// above, so both give identical bits.
 
 // bound_ctrl: the edge lane (no source lane) reads 0, so no old value has
 // to be copied into the destination first.
@@ -172,6 +178,7 @@ constexpr int kStripRows = PCT_EVAL_STRIP_ROWS; // output rows per strip (upper 
 struct StripGeom {
     int rows;   // output rows per strip
     int n_sx, n_sy, n_work;
+    int nw;     // wavefronts per workgroup (1, 2 or kDefaultWaves)
 };
 
 // Max of two non-negative floats (+0 included, no NaN) on their bit patterns:
@@ -181,179 +188,248 @@ __device__ __forceinline__ float maxnn(float a, float b) {
     return __builtin_bit_cast(float, max(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)));
 }
 
-// One wavefront's strip: work index w of a map with parameters p and strip
-// geometry sg (ground/ceil/cost already point at the map's first slice).
-//
-// The rows a lane keeps live (4 ground rows, 3 flag rows, 2R+1 c^init rows,
-// kPrefetch raw rows of each input) sit in rings of S slots indexed by the
-// step number modulo S; the row loop is unrolled S times so that every slot
-// index is a compile-time constant and no row is ever moved between
-// registers.  Step t handles output row y = Y0 - 2 HX + t.
 // Tap weights known at compile time: weight exactly 1 where a^2 + j^2 <= Q1
 // and exactly 0 where a^2 + j^2 >= Q0 (Q1 < 0 and Q0 = kNoZeroTaps: none
 // known).  1 * c = c and 0 * c = 0 exactly for the finite c^init >= 0, so
 // skipping those multiplies leaves every maximum unchanged.
 constexpr int kNoZeroTaps = 1 << 20;
 
-template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
-__device__ __forceinline__ void eval_strip_wave(const float* __restrict__ ground, const float* __restrict__ ceil,
+constexpr int kWgOwn = 60;                        // own columns of a wavefront
+constexpr int kDefaultWaves = PCT_STRIP_WAVES;    // wavefronts of the widest workgroup strip
+static_assert(64 * kDefaultWaves == kBlock, "batched jobs run in blocks of kBlock threads");
+
+// V_a of own column i at v[set][row][i * R + a - 1]: the 2R reads of a row
+// pass lie within 2R^2 + R words of one address (ds_read2 offsets), and
+// lanes R words apart touch distinct banks.  Two rows are exchanged per
+// barrier, in two alternating sets.
+template <int R, int NW>
+struct WgLds {
+    float v[2][2][(R > 0 ? R : 1) * kWgOwn * NW];
+};
+
+// Raw buffer access to one slice plane (fewer than 2^29 cells): a scalar
+// descriptor, the row's byte offset in a scalar register and the lane's
+// column offset in a vector register, so that a row step spends no vector
+// instruction on addresses.
+constexpr int kBufferDword3 = 0x00020000;   // 32-bit elements, gfx9 buffer format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, long long plane) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(plane * 4), kBufferDword3);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// Orders the LDS exchange of one row pass: a workgroup barrier, or for a
+// single wavefront (whose LDS operations complete in issue order) only a
+// fence that keeps the compiler from moving them.
+template <int NW>
+__device__ __forceinline__ void row_exchange_sync() {
+    if constexpr (NW > 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// One workgroup strip: work item w of a map with parameters p and strip
+// geometry sg (ground/ceil/cost already point at the map's first slice).
+// The live rows sit in rings of S slots indexed by the step number modulo
+// S; the row loop is unrolled S times so that every slot index is a
+// compile-time constant and no row is ever moved between registers.  Step t
+// handles output row y = Y0 - 2 (R + 2) + t.
+template <int R, int Q1, int Q0, int NW>
+__device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                 const EvalParams& p, float* __restrict__ cost, const StripGeom& sg,
-                                                int w) {
-    constexpr int HX = R + 2;            // halo columns: inflation R, patch 1, stencil 1
-    constexpr int OUTW = 64 - 2 * HX;
+                                                int w, WgLds<R, NW>& lds) {
+    constexpr int HX = R + 2;
+    constexpr int SPAN = kWgOwn * NW;       // own columns of the workgroup
+    constexpr int OUTW = SPAN - 2 * R;      // columns it stores
     constexpr int S0 = 2 * R + 1 > 4 ? 2 * R + 1 : 4;
-    constexpr int S = S0 > kPrefetch ? S0 : kPrefetch;   // ring length
-    const int sx = w % sg.n_sx;
+    constexpr int S1 = S0 > kPrefetch ? S0 : kPrefetch;
+    constexpr int S = (S1 + 3) / 4 * 4;     // a multiple of 4: the LDS set of step t is (ph >> 1) & 1
+    const int gx = w % sg.n_sx;
     const int t0 = w / sg.n_sx;
     const int sy = t0 % sg.n_sy;
     const int k = t0 / sg.n_sy;
+    const int wave = NW > 1 ? (int)(threadIdx.x >> 6) : 0;
     const int lane = threadIdx.x & 63;
     const int nx = p.nx, ny = p.ny;
-    const int x = p.wx0 + sx * OUTW - HX + lane;
+    const int X0 = p.wx0 + gx * OUTW;               // first stored column
+    const int i = kWgOwn * wave + lane - 2;         // own-column index (lanes 2 .. 61)
+    const int x = X0 - R + i;
+    const bool own = lane >= 2 && lane < 2 + kWgOwn;
+    const bool xout = own && i >= R && i < SPAN - R && x < p.wx1;
+    const int ir = min(max(i, R), SPAN - R - 1);    // row-pass reads stay inside the buffer
     const bool xin = x >= 0 && x < nx;
-    const unsigned xc = (unsigned)min(max(x, 0), nx - 1);
-    const bool xout = lane >= HX && lane < HX + OUTW && x < p.wx1;
+    const int voff = min(max(x, 0), nx - 1) * 4;    // the lane's column, in bytes
     const int Y0 = p.wy0 + sy * sg.rows, Y1 = min(p.wy1, Y0 + sg.rows);
-    const float* gk = ground + (long long)k * p.plane;
-    const float* ck = ceil + (long long)k * p.plane;
-    float* ok = cost + (long long)k * p.plane;
+    const __amdgpu_buffer_rsrc_t rG = plane_rsrc(ground + (long long)k * p.plane, p.plane);
+    const __amdgpu_buffer_rsrc_t rC = plane_rsrc(ceil + (long long)k * p.plane, p.plane);
+    const __amdgpu_buffer_rsrc_t rO = plane_rsrc(cost + (long long)k * p.plane, p.plane);
+    const int row_bytes = nx * 4;
+    auto row_off = [&](int row) { return min(max(row, 0), ny - 1) * row_bytes; };
 
-    // Loads use clamped addresses; the raw value of a row is fetched
-    // kPrefetch steps ahead and masked (outside the grid: no ground) when
-    // consumed, so the load latency overlaps several steps.
-    auto addr = [&](int row) { return (unsigned)min(max(row, 0), ny - 1) * (unsigned)nx + xc; };
-
-    float gS[S];   // ground row y+HX-j at slot (t-j) mod S ... (rows y+R-1 .. y+R+2 live)
-    int fS[S];     // gentle flags, row y+R+1 written at slot t mod S
-    float cS[S];   // c^init, row y+R written at slot t mod S
+    float gS[S];   // ground, row y+R+2 (newest) at slot ph, row y+R+2-j at slot ph-j
+    int fS[S];     // gentle flags, row y+R+1 at slot ph
+    float cS[S];   // c^init, row y+R at slot ph
     float gRaw[S], cRaw[S];
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-        gS[i] = -INFINITY;
-        fS[i] = 0;
-        cS[i] = 0.0f;
+    for (int q = 0; q < S; ++q) {
+        gS[q] = -INFINITY;
+        fS[q] = 0;
+        cS[q] = 0.0f;
     }
-    const int ys = Y0 - 2 * HX;   // row of step 0
+    // central differences of the row whose c^init is formed next, and
+    // whether that row has ground
+    float sdx = 0.0f, sdy = 0.0f, ss2 = 0.0f;
+    bool sfin = false;
+    float h0_even = 0.0f;
+    const int ys = Y0 - 2 * HX;
 #pragma unroll
     for (int d = 0; d < kPrefetch; ++d) {
-        gRaw[d % S] = gk[addr(ys + HX + d)];
-        cRaw[d % S] = ck[addr(ys + R + d)];
+        gRaw[d % S] = buf_load(rG, voff, row_off(ys + HX + d));
+        cRaw[d % S] = buf_load(rC, voff, row_off(ys + R + d));
     }
     const int n_steps = Y1 - ys;
     for (int tb = 0; tb < n_steps; tb += S) {
 #pragma unroll
         for (int ph = 0; ph < S; ++ph) {
             const int t = tb + ph;
-            if (t < n_steps) {
+            if (t < n_steps) {   // uniform over the workgroup
                 const int y = ys + t;
                 const int rg = y + HX, rc = y + R;
-                // step t consumes raw slot ph and refills it kPrefetch rows ahead
+                // step t consumes raw slot ph and refills it kPrefetch rows ahead;
+                // outside the grid there is no ground
                 const float gIn = (xin & (rg >= 0) & (rg < ny)) ? gRaw[ph] : -INFINITY;
                 const float cIn = cRaw[ph];
                 const bool crow = xin & (rc >= 0) & (rc < ny);
-                gRaw[(ph + kPrefetch) % S] = gk[addr(rg + kPrefetch)];
-                cRaw[(ph + kPrefetch) % S] = ck[addr(rc + kPrefetch)];
-                // ground ring: row y+R+2 (newest) at slot ph, row y+R+2-j at slot ph-j
+                gRaw[(ph + kPrefetch) % S] = buf_load(rG, voff, row_off(rg + kPrefetch));
+                cRaw[(ph + kPrefetch) % S] = buf_load(rC, voff, row_off(rc + kPrefetch));
                 gS[ph] = gIn;
-                const float g3 = gS[ph], g2 = gS[(ph + S - 1) % S], g1 = gS[(ph + S - 2) % S],
-                            g0 = gS[(ph + S - 3) % S];   // rows y+R+2, y+R+1, y+R, y+R-1
+                const float g3 = gS[ph], g2 = gS[(ph + S - 1) % S], g1 = gS[(ph + S - 2) % S];   // rows y+R+2, +1, +0
 
                 // Ground values are finite or -inf.  A difference of two
                 // such values is finite only when both are finite (else it
                 // is +-inf or NaN), so a test that fails on inf and NaN
-                // (s2 < Ts2, max|d| <= Tb with Tb finite) already carries
-                // the finiteness of the four stencil neighbours.
+                // (s2 < Ts2, |d| <= Tb with Tb finite) already carries the
+                // finiteness of the stencil neighbours.
 
-                // gentle flag of row y+R+1
-                {
-                    const float Gc = g2, Gd = g1, Gu = g3;
-                    const float Gl = from_prev(Gc), Gr = from_next(Gc);
-                    const float s2 = sumsq(Gr - Gl, Gu - Gd);
-                    fS[ph] = (isfinite(Gc) & (s2 < p.Ts2)) ? 1 : 0;
-                }
-                const int f2 = fS[ph], f1 = fS[(ph + S - 1) % S], f0 = fS[(ph + S - 2) % S];  // rows y+R+1, y+R, y+R-1
+                // stencil and gentle flag of row y+R+1
+                const float ndx = from_next(g2) - from_prev(g2), ndy = g3 - g1;
+                const float ns2 = sumsq(ndx, ndy);
+                const bool nfin = isfinite(g2);
+                fS[ph] = (nfin & (ns2 < p.Ts2)) ? 1 : 0;
+                const int f2 = fS[ph], f1 = fS[(ph + S - 1) % S], f0 = fS[(ph + S - 2) % S];  // rows y+R+1, +0, -1
 
-                // c^init of row y+R, Eqs. (1)-(5), computed without branches
+                // c^init of row y+R, Eqs. (1)-(5), without branches, from the
+                // stencil formed one step earlier
                 {
-                    const float G = g1, Gd = g0, Gu = g2;
-                    const float Gl = from_prev(G), Gr = from_next(G);
+                    const float G = g1;
                     const int colsum = f0 + f1 + f2;
                     const int cnt = colsum + from_prev_i(colsum) + from_next_i(colsum) - f1;
                     const float dI = cIn - G;
                     const float cI = dI < p.d_min ? p.cB : fmaxf(0.0f, p.alpha_d * (p.d_ref - dI));
-                    const float dx = Gr - Gl, dy = Gu - Gd;
-                    const float s2 = sumsq(dx, dy);
-                    const float c_gentle = p.As * s2;
-                    const float c_edge = p.Ab * maxnn(dx * dx, dy * dy);
+                    const float c_gentle = p.As * ss2;
+                    // max(dx^2, dy^2) = max(|dx|, |dy|)^2: squaring is monotone in |d|
+                    const float m = fmaxf(fabsf(sdx), fabsf(sdy));
+                    const float c_edge = p.Ab * (m * m);
                     const float c_step = cnt > p.kp ? c_edge : p.cB;
-                    float cG = s2 < p.Ts2 ? c_gentle : c_step;
-                    // |dx|, |dy| >= 0 or NaN (positive, so above +inf in maxnn's order)
-                    const bool passable = maxnn(fabsf(dx), fabsf(dy)) <= p.Tb;
+                    float cG = ss2 < p.Ts2 ? c_gentle : c_step;
+                    // both differences within the step bound (false for inf and NaN)
+                    const bool passable = (fabsf(sdx) <= p.Tb) & (fabsf(sdy) <= p.Tb);
                     cG = passable ? cG : p.cB;
-                    float ci = isfinite(G) ? fminf(p.cB, cI + cG) : p.cB;
+                    const float ci = sfin ? fminf(p.cB, cI + cG) : p.cB;
                     cS[ph] = crow ? ci : 0.0f;
                 }
+                sdx = ndx;
+                sdy = ndy;
+                ss2 = ns2;
+                sfin = nfin;
 
                 // inflation of row y: c^init rows y-R .. y+R are slots ph-2R .. ph
-                // (column pass from registers, row pass across lanes; all
-                // operands are >= 0)
+                // (column pass from registers; all operands are >= 0)
                 float P[R + 1];
                 P[0] = cS[(ph + S - R) % S];
 #pragma unroll
                 for (int jj = 1; jj <= R; ++jj)
                     P[jj] = maxnn(cS[(ph + S - R - jj) % S], cS[(ph + S - R + jj) % S]);
-                float v = 0.0f;
+                float h[R + 1];
 #pragma unroll
                 for (int a = 0; a <= R; ++a) {
-                    float h = 0.0f;
+                    float v = 0.0f;
 #pragma unroll
                     for (int jj = 0; jj <= R; ++jj) {
                         const int q = a * a + jj * jj;
-                        if (q <= Q1) h = maxnn(h, P[jj]);                      // weight 1
-                        else if (q < Q0) h = maxnn(h, p.K[a][jj] * P[jj]);     // weight in (0, 1)
+                        if (q <= Q1) v = maxnn(v, P[jj]);                      // weight 1
+                        else if (q < Q0) v = maxnn(v, p.K[a][jj] * P[jj]);     // weight in (0, 1)
                     }
-                    if (a == 0) v = h;
-                    else v = maxnn(v, maxnn(__shfl(h, lane - a, 64), __shfl(h, lane + a, 64)));
+                    h[a] = v;
                 }
-                if (y >= Y0 && xout) ok[(unsigned)y * (unsigned)nx + (unsigned)x] = v;
+                // row pass: rows of even and odd steps go to the two rows of a
+                // set; the exchange and the row passes follow the odd step (or
+                // the last one)
+                float* buf = lds.v[(ph >> 1) & 1][ph & 1];
+                if (own) {
+#pragma unroll
+                    for (int a = 1; a <= R; ++a) buf[i * R + a - 1] = h[a];
+                }
+                if ((ph & 1) == 0) h0_even = h[0];
+                if ((ph & 1) == 1 || t == n_steps - 1) {
+                    row_exchange_sync<NW>();
+#pragma unroll
+                    for (int r2 = 0; r2 < 2; ++r2) {
+                        if (r2 == 0 && (ph & 1) == 0) continue;   // a lone even step: its row only
+                        const int yy = r2 == 0 ? y - 1 : y;
+                        const float* rb = lds.v[(ph >> 1) & 1][r2 == 0 ? 0 : (ph & 1)] + (ir - R) * R;
+                        float v = r2 == 0 ? h0_even : h[0];
+#pragma unroll
+                        for (int a = 1; a <= R; ++a)
+                            v = maxnn(v, maxnn(rb[(R - a) * R + a - 1], rb[(R + a) * R + a - 1]));
+                        if (yy >= Y0 && xout) buf_store(v, rO, voff, yy * row_bytes);
+                    }
+                }
             }
         }
     }
 }
 
-// XCD-aware order: workgroups are dealt to the 8 XCDs round-robin; give
-// each XCD a contiguous range of strips so that neighbours share an L2.
-__device__ __forceinline__ int xcd_wave_index() {
+template <int R, int Q1, int Q0, int NW>
+__global__ __launch_bounds__(64 * NW) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
+                                                        const EvalParams p, float* __restrict__ cost,
+                                                        const StripGeom sg) {
+    __shared__ WgLds<R, NW> lds;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin; each
+    // XCD gets a contiguous range of strips, so neighbours share an L2
     const int per_xcd = gridDim.x / 8;
-    const int wb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    return wb * (kBlock / 64) + (int)(threadIdx.x / 64);
-}
-
-template <int R, int Q1, int Q0>
-__global__ __launch_bounds__(kBlock) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
-                                                       const EvalParams p, float* __restrict__ cost, const StripGeom sg) {
-    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_index());   // uniform: row logic stays scalar
-    if (w >= sg.n_work) return;
-    eval_strip_wave<R, Q1, Q0>(ground, ceil, p, cost, sg, w);
+    const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= sg.n_work) return;   // the whole workgroup
+    eval_strip_item<R, Q1, Q0, NW>(ground, ceil, p, cost, sg, w, lds);
 }
 
 // A batch: jobs are (map, robot) pairs with their own parameters, strip
-// geometry and offsets; one launch covers every job's strips.
+// geometry and offsets; one launch covers every job's strips.  A block of
+// kBlock threads is one strip of a job whose workgroups have kDefaultWaves
+// wavefronts, or kBlock / 64 strips of one wavefront each.
 struct EvalJob {
     EvalParams p;
     StripGeom sg;
     long long in_off, out_off, keep_off;   // element offsets of ground/ceil, cost, keep
     long long cell_base;                   // first global cell of the job (slice test)
     long long ws_off;                      // byte offset of the job's slice-test scratch
-    int work_base;                         // first global strip of the job
-    int pad;
+    int block_base;                        // first global block of the job
+    int n_blocks;
 };
 
-__device__ __forceinline__ int find_job_work(const EvalJob* __restrict__ jobs, int n_jobs, int w) {
+__device__ __forceinline__ int find_job_block(const EvalJob* __restrict__ jobs, int n_jobs, int b) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
-        if (jobs[mid].work_base <= w) lo = mid;
+        if (jobs[mid].block_base <= b) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -362,16 +438,29 @@ __device__ __forceinline__ int find_job_work(const EvalJob* __restrict__ jobs, i
 template <int R, int Q1, int Q0>
 __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restrict__ ground,
                                                             const float* __restrict__ ceil,
-                                                            const EvalJob* __restrict__ jobs, int n_jobs, int n_work,
+                                                            const EvalJob* __restrict__ jobs, int n_jobs, int n_blocks,
                                                             float* __restrict__ cost) {
-    const int w = __builtin_amdgcn_readfirstlane(xcd_wave_index());
-    if (w >= n_work) return;
-    const int j = __builtin_amdgcn_readfirstlane(find_job_work(jobs, n_jobs, w));
+    static_assert(sizeof(WgLds<R, kDefaultWaves>) == (kBlock / 64) * sizeof(WgLds<R, 1>), "LDS of one-wave strips");
+    __shared__ WgLds<R, kDefaultWaves> lds;
+    const int per_xcd = gridDim.x / 8;
+    const int b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= n_blocks) return;   // the whole workgroup
+    const int j = __builtin_amdgcn_readfirstlane(find_job_block(jobs, n_jobs, b));
     const EvalJob& jb = jobs[j];
-    eval_strip_wave<R, Q1, Q0>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w - jb.work_base);
+    if (jb.sg.nw > 1) {
+        eval_strip_item<R, Q1, Q0, kDefaultWaves>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off,
+                                                  jb.sg, b - jb.block_base, lds);
+    } else {
+        const int wave = (int)(threadIdx.x >> 6);
+        const int w = (b - jb.block_base) * (kBlock / 64) + wave;
+        WgLds<R, 1>& mine = reinterpret_cast<WgLds<R, 1>*>(&lds)[wave];
+        if (w < jb.sg.n_work)
+            eval_strip_item<R, Q1, Q0, 1>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w,
+                                          mine);
+    }
 }
 
-// Strip heights chosen by the autotuner, per map shape and kernel radius.
+// Strip shapes chosen by the autotuner, per map shape and kernel radius.
 struct TuneKey {
     int nx, ny, N, R;
     bool operator<(const TuneKey& o) const {
@@ -379,28 +468,40 @@ struct TuneKey {
     }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune_rows;
+std::map<TuneKey, EvalShape> g_tune;
 
-int tuned_rows(const EvalParams& p) {
+EvalShape tuned_shape(const EvalParams& p) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_rows.find(TuneKey{p.nx, p.ny, p.N, p.R});
-    return it == g_tune_rows.end() ? 0 : it->second;
+    auto it = g_tune.find(TuneKey{p.nx, p.ny, p.N, p.R});
+    return it == g_tune.end() ? EvalShape{0, 0} : it->second;
 }
 
-// rows = 0: the tuned height if one is recorded, else the default (256,
-// halved while the strips give fewer than 16384 wavefronts, down to 32).
-StripGeom strip_geom(const EvalParams& p, int rows = 0) {
-    const int outw = 64 - 2 * (p.R + 2);
+int strip_outw(int R, int nw) { return kWgOwn * std::max(1, nw) - 2 * R; }
+
+// shape.rows = 0: the tuned shape if one is recorded, else the default
+// (workgroup or wavefront strips as the columns fit best, 256 rows halved
+// while there are fewer than 16384 wavefronts, down to 32).
+StripGeom strip_geom(const EvalParams& p, EvalShape shape = EvalShape{0, 0}, bool two_wave = true) {
+    if (shape.rows <= 0) shape = tuned_shape(p);
     const int wnx = p.wx1 - p.wx0, wny = p.wy1 - p.wy0;
+    // default: the kind that spends fewer lanes on the window's columns
+    // (workgroup strips on a tie)
+    auto lanes = [&](int w) { return (long long)(wnx + strip_outw(p.R, w) - 1) / strip_outw(p.R, w) * 64 * w; };
+    int nw = shape.rows > 0 ? std::max(1, shape.nw) : kDefaultWaves;
+    if (shape.rows <= 0)
+        for (int w : {2, 1})
+            if ((w != 2 || two_wave) && lanes(w) < lanes(nw)) nw = w;
+    if (nw == 2 && !two_wave) nw = kDefaultWaves;
+    const int outw = strip_outw(p.R, nw);
     StripGeom g{};
+    g.nw = nw;
     g.n_sx = (wnx + outw - 1) / outw;
     auto work = [&](int r) { return (long long)p.N * g.n_sx * ((wny + r - 1) / r); };
-    if (rows <= 0) rows = tuned_rows(p);
-    if (rows > 0) {
-        g.rows = rows;
+    if (shape.rows > 0) {
+        g.rows = shape.rows;
     } else {
         g.rows = kStripRows;
-        while (g.rows > 32 && work(g.rows) < 16384) g.rows /= 2;
+        while (g.rows > 32 && work(g.rows) * nw < 16384) g.rows /= 2;
     }
     g.n_sy = (wny + g.rows - 1) / g.rows;
     g.n_work = (int)work(g.rows);
@@ -409,12 +510,16 @@ StripGeom strip_geom(const EvalParams& p, int rows = 0) {
 
 template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
 pct_status launch_eval_strip(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                             int rows = 0) {
-    const StripGeom sg = strip_geom(p, rows);
-    const int waves_per_block = kBlock / 64;
-    int blocks = (sg.n_work + waves_per_block - 1) / waves_per_block;
-    blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0>), dim3(blocks), dim3(kBlock), 0, s, ground, ceil, p, cost, sg);
+                             EvalShape shape) {
+    const StripGeom sg = strip_geom(p, shape);
+    const int blocks = (sg.n_work + 7) / 8 * 8;
+    if (sg.nw == kDefaultWaves)
+        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, kDefaultWaves>), dim3(blocks), dim3(64 * kDefaultWaves), 0, s,
+                           ground, ceil, p, cost, sg);
+    else if (sg.nw == 2)
+        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, 2>), dim3(blocks), dim3(128), 0, s, ground, ceil, p, cost, sg);
+    else
+        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, 1>), dim3(blocks), dim3(64), 0, s, ground, ceil, p, cost, sg);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -663,19 +768,23 @@ static bool weights_follow_pattern(const EvalParams& p) {
     return true;
 }
 
+// Strip kernels: patch radius 1, inflation radius <= 8, and slice planes
+// small enough for 32-bit buffer offsets.
+bool strip_kernel_applies(const EvalParams& p) { return p.rp == 1 && p.R <= 8 && p.plane < (1LL << 29); }
+
 pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                       int rows) {
-    if (p.rp == 1 && p.R <= 8) {
+                       EvalShape shape) {
+    if (strip_kernel_applies(p)) {
         if (weights_follow_pattern(p)) {
             switch (p.R) {
-#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s, rows);
+#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s, shape);
                 PCT_P(2) PCT_P(3) PCT_P(4) PCT_P(5) PCT_P(6) PCT_P(7) PCT_P(8)
 #undef PCT_P
                 default: break;
             }
         }
         switch (p.R) {
-#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s, rows);
+#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s, shape);
             PCT_S(0) PCT_S(1) PCT_S(2) PCT_S(3) PCT_S(4) PCT_S(5) PCT_S(6) PCT_S(7) PCT_S(8)
 #undef PCT_S
             default: break;
@@ -690,28 +799,32 @@ pct_status launch_eval(const float* ground, const float* ceil, const EvalParams&
     }
 }
 
-// Times the strip evaluation of this map shape for each candidate strip
-// height and records the fastest in the tuning table (synchronous).
+// Times the strip evaluation of this map shape for each candidate shape
+// (one wavefront per strip, or kDefaultWaves per workgroup, by strip
+// height) and records the fastest in the tuning table (synchronous).
 pct_status autotune_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                         int* best_rows, int* cand_rows, float* cand_ms, int n_max, int* n_cand) {
-    *best_rows = 0;
+                         EvalShape* best_shape, EvalShape* cand, float* cand_ms, int n_max, int* n_cand) {
+    *best_shape = EvalShape{0, 0};
     *n_cand = 0;
-    if (!(p.rp == 1 && p.R <= 8)) return PCT_OK;   // the tiled kernel has no strip height
-    int rows[8], nc = 0;
-    for (int r = 32; r <= 1024 && nc < 8; r *= 2) {
-        rows[nc++] = r;
-        if (r >= p.ny) break;
-    }
+    if (!strip_kernel_applies(p)) return PCT_OK;   // the tiled kernel has no strip shape
+    EvalShape shapes[24];
+    int nc = 0;
+    for (int nw : {kDefaultWaves, 2, 1})
+        for (int r = 32; r <= 1024 && nc < 24; r *= 2) {
+            if (!strip_shape_fits(p, EvalShape{r, nw})) continue;
+            shapes[nc++] = EvalShape{r, nw};
+            if (r >= p.ny) break;
+        }
     hipEvent_t e0, e1;
     PCT_HIP(hipEventCreate(&e0));
     PCT_HIP(hipEventCreate(&e1));
     float best = INFINITY;
     pct_status st = PCT_OK;
     for (int i = 0; i < nc && st == PCT_OK; ++i) {
-        st = launch_eval(ground, ceil, p, cost, s, rows[i]);   // warm-up
+        st = launch_eval(ground, ceil, p, cost, s, shapes[i]);   // warm-up
         if (st != PCT_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PCT_ERR_DEVICE, "hipEventRecord failed"); break; }
-        for (int rep = 0; rep < 3 && st == PCT_OK; ++rep) st = launch_eval(ground, ceil, p, cost, s, rows[i]);
+        for (int rep = 0; rep < 3 && st == PCT_OK; ++rep) st = launch_eval(ground, ceil, p, cost, s, shapes[i]);
         if (st != PCT_OK) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -721,12 +834,12 @@ pct_status autotune_eval(const float* ground, const float* ceil, const EvalParam
         }
         ms /= 3.0f;
         if (i < n_max) {
-            if (cand_rows) cand_rows[i] = rows[i];
+            if (cand) cand[i] = shapes[i];
             if (cand_ms) cand_ms[i] = ms;
         }
         if (ms < best) {
             best = ms;
-            *best_rows = rows[i];
+            *best_shape = shapes[i];
         }
     }
     (void)hipEventDestroy(e0);
@@ -734,27 +847,27 @@ pct_status autotune_eval(const float* ground, const float* ceil, const EvalParam
     if (st != PCT_OK) return st;
     *n_cand = nc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_rows[TuneKey{p.nx, p.ny, p.N, p.R}] = *best_rows;
+    g_tune[TuneKey{p.nx, p.ny, p.N, p.R}] = *best_shape;
     return PCT_OK;
 }
 
 void autotune_reset() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_rows.clear();
+    g_tune.clear();
 }
 
-bool strip_rows_fit(const EvalParams& p, int rows) {
-    const long long outw = 64 - 2 * (p.R + 2);
-    if (outw <= 0 || rows <= 0) return false;
+bool strip_shape_fits(const EvalParams& p, EvalShape shape) {
+    const long long outw = strip_outw(p.R, shape.nw);
+    if (outw <= 0 || shape.rows <= 0) return false;
     const long long wnx = p.wx1 - p.wx0, wny = p.wy1 - p.wy0;
-    const long long work = (long long)p.N * ((wnx + outw - 1) / outw) * ((wny + rows - 1) / rows);
-    return work <= (1LL << 30);
+    const long long work = (long long)p.N * ((wnx + outw - 1) / outw) * ((wny + shape.rows - 1) / shape.rows);
+    return work * std::max(1, shape.nw) <= (1LL << 30);
 }
 
-void autotune_set(const EvalParams& p, int rows) {
+void autotune_set(const EvalParams& p, EvalShape shape) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (rows > 0) g_tune_rows[TuneKey{p.nx, p.ny, p.N, p.R}] = rows;
-    else g_tune_rows.erase(TuneKey{p.nx, p.ny, p.N, p.R});
+    if (shape.rows > 0) g_tune[TuneKey{p.nx, p.ny, p.N, p.R}] = shape;
+    else g_tune.erase(TuneKey{p.nx, p.ny, p.N, p.R});
 }
 
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep, void* ws,
@@ -780,7 +893,7 @@ namespace {
 
 struct JobPlan {
     std::vector<EvalJob> jobs;
-    int n_work = 0;
+    int n_blocks = 0;
     long long cells = 0;     // padded cells of all jobs
     size_t scratch = 0;      // bytes of slice-test scratch
     int R = -1;
@@ -802,18 +915,19 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
             EvalJob jb{};
             pct_status st = make_eval_params(robots[r], items[i].grid, N, &jb.p);
             if (st != PCT_OK) return st;
-            jb.sg = strip_geom(jb.p);
+            jb.sg = strip_geom(jb.p, EvalShape{0, 0}, false);   // blocks of kBlock threads: 1 or 4 wavefronts
             jb.in_off = items[i].out_offset;
             jb.out_off = (long long)r * total_cells + items[i].out_offset;
             jb.keep_off = (long long)r * total_slices + items[i].keep_offset;
             jb.cell_base = jp->cells;
             jb.ws_off = (long long)jp->scratch;
-            jb.work_base = jp->n_work;
+            jb.block_base = jp->n_blocks;
+            jb.n_blocks = jb.sg.nw > 1 ? jb.sg.n_work : (jb.sg.n_work + kBlock / 64 - 1) / (kBlock / 64);
             jp->cells += (jb.p.plane + 64 * kSimpCells - 1) / (64 * kSimpCells) * (64 * kSimpCells);
             jp->scratch += align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * ((N + 31) / 32));
-            jp->n_work += jb.sg.n_work;
+            jp->n_blocks += jb.n_blocks;
             if (jp->R < 0) jp->R = jb.p.R;
-            if (jb.p.R != jp->R || jb.p.rp != 1 || jb.p.R > 8) jp->strip = false;
+            if (jb.p.R != jp->R || !strip_kernel_applies(jb.p)) jp->strip = false;
             if (!weights_follow_pattern(jb.p)) jp->pattern = false;
             jp->jobs.push_back(jb);
         }
@@ -821,12 +935,11 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
 }
 
 template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
-pct_status launch_jobs_r(const float* ground, const float* ceil, const EvalJob* d_jobs, int n_jobs, int n_work,
+pct_status launch_jobs_r(const float* ground, const float* ceil, const EvalJob* d_jobs, int n_jobs, int n_blocks,
                          float* cost, hipStream_t s) {
-    int blocks = (n_work + kBlock / 64 - 1) / (kBlock / 64);
-    blocks = (blocks + 7) / 8 * 8;
+    const int blocks = (n_blocks + 7) / 8 * 8;
     hipLaunchKernelGGL((k_eval_strip_jobs<R, Q1, Q0>), dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_jobs, n_jobs,
-                       n_work, cost);
+                       n_blocks, cost);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -868,8 +981,8 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
 #define PCT_J(r)                                                                                       \
     case r:                                                                                            \
         st = (jp.pattern && r >= 2)                                                                    \
-                 ? launch_jobs_r<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s) \
-                 : launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_work, cost, s);                 \
+                 ? launch_jobs_r<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, d_jobs, n_jobs, jp.n_blocks, cost, s) \
+                 : launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_blocks, cost, s);                 \
         break;
             PCT_J(0) PCT_J(1) PCT_J(2) PCT_J(3) PCT_J(4) PCT_J(5) PCT_J(6) PCT_J(7) PCT_J(8)
 #undef PCT_J

@@ -123,13 +123,19 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
                         hipStream_t s, bool merge = false, int id_base = 0);
 
 size_t eval_ws_bytes(int N, int n_robots);
+// Strip shape of the evaluation: output rows per strip and wavefronts per
+// workgroup sharing one strip (1: each wavefront its own strip);
+// rows = 0: the tuned shape for the map if recorded, else the default.
+struct EvalShape {
+    int rows, nw;
+};
 pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                       int rows = 0);
+                       EvalShape shape = EvalShape{0, 0});
 pct_status autotune_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                         int* best_rows, int* cand_rows, float* cand_ms, int n_max, int* n_cand);
+                         EvalShape* best, EvalShape* cand, float* cand_ms, int n_max, int* n_cand);
 void autotune_reset();
-void autotune_set(const EvalParams& p, int rows);
-bool strip_rows_fit(const EvalParams& p, int rows);
+void autotune_set(const EvalParams& p, EvalShape shape);
+bool strip_shape_fits(const EvalParams& p, EvalShape shape);
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
                            void* ws, hipStream_t s);
 

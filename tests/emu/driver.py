@@ -261,16 +261,23 @@ def case_autotune():
     g = grid_s(sc.grid)
     rb = robot_s(r)
     scratch = Buf(4 * e.n_slices * sc.grid["nx"] * sc.grid["ny"])
-    best, count = C.c_int32(), C.c_int32()
-    rows, ms = (C.c_int32 * 8)(), (C.c_float * 8)()
+    best, bw, count = C.c_int32(), C.c_int32(), C.c_int32()
+    rows, waves, ms = (C.c_int32 * 24)(), (C.c_int32 * 24)(), (C.c_float * 24)()
     check("autotune", L.pct_autotune_traversability(P(G), P(Cc), C.byref(g), C.byref(e), C.byref(rb), P(scratch),
-                                                    C.byref(best), rows, ms, 8, C.byref(count), None))
-    cands = [rows[i] for i in range(count.value)]
-    assert count.value >= 2 and best.value in cands, (best.value, cands)
+                                                    C.byref(best), C.byref(bw), rows, waves, ms, 24, C.byref(count),
+                                                    None))
+    cands = [(rows[i], waves[i]) for i in range(count.value)]
+    assert count.value >= 4 and (best.value, bw.value) in cands, (best.value, bw.value, cands)
+    assert {w for _, w in cands} == {1, 2, 4}
     after = evaluate(G, Cc, sc.grid, e, [r])[0].get(e.n_slices * sc.grid["nx"] * sc.grid["ny"], np.float32)
     np.testing.assert_array_equal(bits(after), bits(before))
+    # every candidate shape gives the same bits
+    for rr, ww in cands:
+        check("set", L.pct_autotune_set_traversability(C.byref(g), C.byref(e), C.byref(rb), rr, ww))
+        got = evaluate(G, Cc, sc.grid, e, [r])[0].get(e.n_slices * sc.grid["nx"] * sc.grid["ny"], np.float32)
+        np.testing.assert_array_equal(bits(got), bits(before))
     check("reset", L.pct_autotune_reset())
-    say(f"autotune: candidates {cands}, chose {best.value}; evaluation unchanged")
+    say(f"autotune: candidates {cands}, chose {(best.value, bw.value)}; evaluation unchanged at every shape")
 
 
 # ----------------------------------------------------------------- batches

@@ -167,6 +167,44 @@ inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 #define __builtin_nontemporal_store(v, p) (void)(*(p) = (v))
 #define __builtin_amdgcn_readfirstlane emu_readfirstlane
 
+// Raw buffer access (stride 0): offset = voffset + soffset bytes from the
+// descriptor's base.  The hardware returns 0 for reads and drops writes
+// beyond num_records; the library never relies on that, so here such an
+// access aborts.
+struct emu_buffer_rsrc {
+    char* base;
+    unsigned num;
+};
+typedef emu_buffer_rsrc __amdgpu_buffer_rsrc_t;
+inline emu_buffer_rsrc emu_make_buffer_rsrc(void* p, short stride, int num, int flags) {
+    (void)flags;
+    if (stride != 0) __builtin_trap();
+    return emu_buffer_rsrc{(char*)p, (unsigned)num};
+}
+inline char* emu_buffer_addr(emu_buffer_rsrc r, int voff, int soff) {
+    const unsigned long long off = (unsigned long long)(unsigned)voff + (unsigned)soff;
+    if (off + 4 > r.num) __builtin_trap();
+    return r.base + off;
+}
+inline unsigned emu_raw_buffer_load_b32(emu_buffer_rsrc r, int voff, int soff, int aux) {
+    (void)aux;
+    unsigned v;
+    memcpy(&v, emu_buffer_addr(r, voff, soff), 4);
+    return v;
+}
+inline void emu_raw_buffer_store_b32(unsigned v, emu_buffer_rsrc r, int voff, int soff, int aux) {
+    (void)aux;
+    memcpy(emu_buffer_addr(r, voff, soff), &v, 4);
+}
+#define __builtin_amdgcn_make_buffer_rsrc emu_make_buffer_rsrc
+#define __builtin_amdgcn_raw_buffer_load_b32 emu_raw_buffer_load_b32
+#define __builtin_amdgcn_raw_buffer_store_b32 emu_raw_buffer_store_b32
+// A wavefront barrier: every live lane of the wavefront arrives before any
+// continues (the fences around it need nothing more here).
+inline void emu_wave_barrier() { (void)emu::wave_op(emu::OP_BALLOT, 1u, 0, 0); }
+#define __builtin_amdgcn_wave_barrier emu_wave_barrier
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
+
 // Fibers switch only at the operations above, so read-modify-write needs no
 // further protection.
 template <class T>

@@ -228,7 +228,7 @@ def test_autotune_keeps_results(P):
     after, ka = P.pct_eval_traversability(g, c, sc.grid, ext, [rb])
     torch.cuda.synchronize()
     P.pct_autotune_reset()
-    assert best in cands and len(cands) >= 3
+    assert best in cands and len(cands) >= 6
     assert int((before < rb.c_barrier).sum()) > 1000
     np.testing.assert_array_equal(bits(after.cpu().numpy()), bits(before.cpu().numpy()))
     np.testing.assert_array_equal(ka.cpu().numpy(), kb.cpu().numpy())
@@ -275,9 +275,10 @@ def test_building_every_strip_height(P, oracle_lib):
             wins.append((wx0, wy0, wn, lo[inner], hi[inner]))
         first = None
         try:
-            for rows in (32, 64, 128, 256, 512, 1024, 100, 1000):
-                P.pct_autotune_set_traversability(grid, ext, rb, rows)
-                say(f"building, {rname}: strips of {rows} rows")
+            for rows, waves in [(r_, w_) for w_ in (P.PCT_STRIP_WAVES, 2, 1)
+                                for r_ in (32, 64, 128, 256, 512, 1024, 100, 1000)]:
+                P.pct_autotune_set_traversability(grid, ext, rb, rows, waves)
+                say(f"building, {rname}: strips of {rows} rows, {waves} wavefronts")
                 cost, keep = P.pct_eval_traversability(g, c, grid, ext, [rb])
                 torch.cuda.synchronize()
                 for wx0, wy0, wn, lo, hi in wins:
@@ -290,8 +291,8 @@ def test_building_every_strip_height(P, oracle_lib):
                     assert 0 < int(keep.sum()) < ext.n_slices
                     del cT
                 else:
-                    assert torch.equal(cost.view(torch.int32), first[0].view(torch.int32)), (rname, rows)
-                    assert torch.equal(keep, first[1]), (rname, rows)
+                    assert torch.equal(cost.view(torch.int32), first[0].view(torch.int32)), (rname, rows, waves)
+                    assert torch.equal(keep, first[1]), (rname, rows, waves)
         finally:
             P.pct_autotune_reset()
 
