@@ -56,6 +56,7 @@ def lib():
         f32p, f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
         i32p, u8p = C.POINTER(C.c_int32), C.POINTER(C.c_uint8)
         L.o_omp_threads.restype = C.c_int
+        L.o_set_threads.argtypes = [C.c_int]
         L.o_extent.argtypes = [f32p, C.c_int64, C.POINTER(Grid), f32p, f32p]
         L.o_extent.restype = C.c_int64
         L.o_planes.argtypes = [C.c_float, C.c_float, C.c_float, C.c_int, f32p]
@@ -109,6 +110,11 @@ def _register_grad(L):
 
 def threads() -> int:
     return int(lib().o_omp_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().o_set_threads(int(n))
 
 
 def grid_struct(g: dict) -> Grid:

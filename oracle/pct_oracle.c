@@ -45,6 +45,17 @@ int o_omp_threads(void) {
 #endif
 }
 
+/* Sets the number of threads of the parallel loops (for timing the oracle on
+ * one core as well as on all); no effect on any result. */
+void o_set_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. III-A: rasterize.  The paper names the step but not the rule.
  * Reading: cell (i, j) of a grid with origin (x0, y0) and resolution r holds

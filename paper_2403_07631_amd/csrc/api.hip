@@ -158,14 +158,9 @@ pct_status eval_traversability(const float* d_ground, const float* d_ceil, const
         pct_status st = make_eval_params(h_robots[i], *grid, N, &p);
         if (st != PCT_OK) return st;
         float* cost = d_cost + per_robot * i;
-        st = launch_eval(d_ground, d_ceil, p, cost, s);
+        st = launch_eval_simplify(d_ground, d_ceil, p, cost, d_keep ? d_keep + (size_t)N * i : nullptr, d_ws, ws_bytes, s);
         if (st != PCT_OK) return st;
-        if (d_keep) {
-            st = launch_simplify(d_ground, cost, p, d_keep + (size_t)N * i, d_ws, s);
-            if (st != PCT_OK) return st;
-        }
     }
-    (void)ws_bytes;
     return PCT_OK;
 }
 

@@ -242,10 +242,14 @@ __device__ __forceinline__ void row_exchange_sync() {
 // S; the row loop is unrolled S times so that every slot index is a
 // compile-time constant and no row is ever moved between registers.  Step t
 // handles output row y = Y0 - 2 (R + 2) + t.
+// With slice_bits non-null the strip also sets bit k of slice_bits (bit
+// k % 32 of word k / 32) when one of its stored costs is traversable
+// (c^T < c^B), so that the slice test can pass over slices without any.
 template <int R, int Q1, int Q0, int NW>
 __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                 const EvalParams& p, float* __restrict__ cost, const StripGeom& sg,
-                                                int w, WgLds<R, NW>& lds) {
+                                                int w, WgLds<R, NW>& lds,
+                                                unsigned* __restrict__ slice_bits = nullptr) {
     constexpr int HX = R + 2;
     constexpr int SPAN = kWgOwn * NW;       // own columns of the workgroup
     constexpr int OUTW = SPAN - 2 * R;      // columns it stores
@@ -289,6 +293,7 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
     float sdx = 0.0f, sdy = 0.0f, ss2 = 0.0f;
     bool sfin = false;
     float h0_even = 0.0f;
+    bool any_trav = false;   // a stored cost of this wavefront is below c^B (uniform)
     const int ys = Y0 - 2 * HX;
 #pragma unroll
     for (int d = 0; d < kPrefetch; ++d) {
@@ -391,24 +396,27 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
                         for (int a = 1; a <= R; ++a)
                             v = maxnn(v, maxnn(rb[(R - a) * R + a - 1], rb[(R + a) * R + a - 1]));
                         if (yy >= Y0 && xout) buf_store(v, rO, voff, yy * row_bytes);
+                        if (slice_bits && yy >= Y0 && !any_trav)   // uniform
+                            any_trav = __ballot(xout && v < p.cB) != 0ull;
                     }
                 }
             }
         }
     }
+    if (any_trav && lane == 0) atomicOr(&slice_bits[k >> 5], 1u << (k & 31));
 }
 
 template <int R, int Q1, int Q0, int NW>
 __global__ __launch_bounds__(64 * NW) void k_eval_strip(const float* __restrict__ ground, const float* __restrict__ ceil,
                                                         const EvalParams p, float* __restrict__ cost,
-                                                        const StripGeom sg) {
+                                                        const StripGeom sg, unsigned* __restrict__ slice_bits) {
     __shared__ WgLds<R, NW> lds;
     // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin; each
     // XCD gets a contiguous range of strips, so neighbours share an L2
     const int per_xcd = gridDim.x / 8;
     const int w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= sg.n_work) return;   // the whole workgroup
-    eval_strip_item<R, Q1, Q0, NW>(ground, ceil, p, cost, sg, w, lds);
+    eval_strip_item<R, Q1, Q0, NW>(ground, ceil, p, cost, sg, w, lds, slice_bits);
 }
 
 // A batch: jobs are (map, robot) pairs with their own parameters, strip
@@ -510,16 +518,17 @@ StripGeom strip_geom(const EvalParams& p, EvalShape shape = EvalShape{0, 0}, boo
 
 template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
 pct_status launch_eval_strip(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                             EvalShape shape) {
-    const StripGeom sg = strip_geom(p, shape);
+                             const StripGeom& sg, unsigned* slice_bits) {
     const int blocks = (sg.n_work + 7) / 8 * 8;
     if (sg.nw == kDefaultWaves)
         hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, kDefaultWaves>), dim3(blocks), dim3(64 * kDefaultWaves), 0, s,
-                           ground, ceil, p, cost, sg);
+                           ground, ceil, p, cost, sg, slice_bits);
     else if (sg.nw == 2)
-        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, 2>), dim3(blocks), dim3(128), 0, s, ground, ceil, p, cost, sg);
+        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, 2>), dim3(blocks), dim3(128), 0, s, ground, ceil, p, cost, sg,
+                           slice_bits);
     else
-        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, 1>), dim3(blocks), dim3(64), 0, s, ground, ceil, p, cost, sg);
+        hipLaunchKernelGGL((k_eval_strip<R, Q1, Q0, 1>), dim3(blocks), dim3(64), 0, s, ground, ceil, p, cost, sg,
+                           slice_bits);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -570,106 +579,197 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
     return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, unsigned* __restrict__ urun, int N, int W) {
+__global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, unsigned* __restrict__ urun,
+                                                      unsigned* __restrict__ slice_bits, int N, int W) {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N * W; i += gridDim.x * kBlock) urun[i] = 0u;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) maxp0[i] = -1;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < W; i += gridDim.x * kBlock) slice_bits[i] = 0u;
 }
 
-// Slice-test flags of kSimpCells consecutive cells per lane, cells cell0 ..
-// cell0 + nact - 1 (all lanes of a wavefront must call it together; lanes
-// without cells pass nact = 0).  Several cells per lane divide the
-// wavefront reductions and atomics per cell.
+// Slice-test flags of kSimpCells cells per lane, cells cell0 + c * STRIDE
+// for c < nact (nact <= kSimpCells; all lanes of a wavefront must call it
+// together, lanes without cells pass nact = 0).  Several cells per lane
+// divide the wavefront reductions and atomics per cell; STRIDE = 64
+// interleaves the lanes of a wavefront, so that each load instruction reads
+// 256 contiguous bytes.
+//
+// slice_bits (nullable): bit k set when slice k has a traversable cell.  A
+// slice without one has no cell that Eqs. (8)-(9) can make unique, so it
+// is passed over without reading; the cells' run starts are then followed
+// across it lazily: a later slice with the ground of the last slice read
+// continues that run (ground is non-decreasing in k), any other starts a
+// run whose start is found, if a kept-slice test needs it, by reading the
+// ground below.
 constexpr int kSimpCells = 4;
 
-// A lane's cells are cell0 + c * STRIDE for c < nact (nact <= kSimpCells).
-// STRIDE = 64 interleaves the lanes of a wavefront, so that each load
-// instruction reads 256 contiguous bytes.
 template <int STRIDE>
 __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ ground, const float* __restrict__ cost,
                                                  long long plane, int N, float cB, int W, int* __restrict__ maxp0,
-                                                 unsigned* __restrict__ urun, long long cell0, int nact) {
+                                                 unsigned* __restrict__ urun, long long cell0, int nact,
+                                                 const unsigned* __restrict__ slice_bits = nullptr) {
     constexpr int CPT = kSimpCells;
     const int lane = threadIdx.x & 63;
-    float ek[CPT], ck[CPT], eprev[CPT];
+    // bit j of sb0 / sb1: slice 32 * (k / 32) + j / + 32 + j holds a traversable cell
+    auto bits_word = [&](int w) -> unsigned {   // uniform
+        if (!slice_bits) return ~0u;
+        return w < W ? slice_bits[w] : 0u;
+    };
+    unsigned sb0 = bits_word(0), sb1 = bits_word(1);
+    // slice j is read when bit j is set; j < 32 (k / 32) + 64
+    auto bit_of = [&](int j, int kw) -> bool {   // uniform; kw = 32 (k / 32)
+        if (j >= N) return false;
+        const int o = j - kw;
+        return ((o < 32 ? sb0 >> o : sb1 >> (o - 32)) & 1u) != 0u;
+    };
+    // ring of the slices read ahead: slot j % Q holds ground and cost of
+    // slice j at the lane's cells, loaded Q - 1 slices before slice j is
+    // tested, so that loads of several slices are in flight.  The loads are
+    // unconditional (clamped addresses, masks applied where the values are
+    // used), so each step issues the same number and a wait for an older
+    // slot need not drain the newer ones.
+    constexpr int Q = 4;
+    float eQ[Q][CPT], cQ[Q][CPT];
+    long long cidx[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) cidx[c] = min(cell0 + (long long)c * STRIDE, plane - 1);
+    auto load_slot = [&](int slot, int j) {
+        const long long base = (long long)min(j, N - 1) * plane;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            eQ[slot][c] = ground[base + cidx[c]];
+            cQ[slot][c] = cost[base + cidx[c]];
+        }
+    };
+    if (slice_bits) {   // uniform: no marked slice at all
+        unsigned any = 0u;
+        for (int w = 0; w < W; ++w) any |= slice_bits[w];
+        if (any == 0u) return;
+    }
+#pragma unroll
+    for (int q = 0; q < Q - 1; ++q) load_slot(q, q);
+    // per cell: ground of the last slice read, start of its run (-1: below
+    // k, not known), and the largest cost of the run's slices below k (an
+    // in-run slice can only make k unique where it costs more than c_k)
+    float eprev[CPT], rmax[CPT];
     int p0[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const bool act = c < nact;
-        ek[c] = act ? ground[cell0 + c * STRIDE] : -INFINITY;
-        ck[c] = act ? cost[cell0 + c * STRIDE] : cB;
         eprev[c] = -INFINITY;
+        rmax[c] = -INFINITY;
         p0[c] = 0;
     }
-    for (int k = 0; k < N; ++k) {
-        float ek1[CPT], ck1[CPT];
-        const long long nb = (long long)(k + 1) * plane + cell0;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const bool ld = k + 1 < N && c < nact;
-            ek1[c] = ld ? ground[nb + c * STRIDE] : -INFINITY;
-            ck1[c] = ld ? cost[nb + c * STRIDE] : cB;
+    bool prev_read = false;   // slice k-1 was read (uniform)
+    for (int kb = 0; kb < N; kb += Q) {
+        if ((kb & 31) == 0 && kb > 0) {   // the next pair of words
+            sb0 = sb1;
+            sb1 = bits_word((kb >> 5) + 1);
         }
-        int mloc = -1, pminloc = 0x7fffffff;
-        bool runA[CPT];
+        const int kw = kb & ~31;
+        if ((kb & 31) == 0 && sb0 == 0u) {   // uniform: no traversable cell in these 32 slices
+            prev_read = false;
+            if (sb1 != 0u) {   // the ring for the next word
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            if (k > 0 && ek[c] != eprev[c]) p0[c] = k;
-            const bool trav = c < nact && ck[c] < cB;
-            const bool upper = (k == N - 1) || (ek1[c] > ek[c]) || (ck[c] < ck1[c]);
-            const bool A = trav && upper;
-            if (A) mloc = max(mloc, p0[c]);
-            runA[c] = A && p0[c] < k;
-            if (runA[c]) pminloc = min(pminloc, p0[c]);
-        }
-        const int m = wave_max_i(mloc);
-        if (lane == 0 && m >= 0) atomicMax(&maxp0[k], m);
-        if (__ballot(pminloc != 0x7fffffff)) {
-            const int pmin = wave_min_i(pminloc);
-            for (int w = pmin / 32; w <= (k - 1) / 32; ++w) {
-                unsigned bits = 0;
-                const int pb = max(pmin, w * 32), pe = min(k, w * 32 + 32);
-                // eight earlier slices at a time, their loads issued together
-                for (int pp0 = pb; pp0 < pe; pp0 += 8) {
-                    float cv[8][CPT];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int pp = pp0 + u;
-#pragma unroll
-                        for (int c = 0; c < CPT; ++c)
-                            cv[u][c] = (pp < pe && runA[c] && pp >= p0[c])
-                                           ? cost[(long long)pp * plane + cell0 + c * STRIDE]
-                                           : -INFINITY;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-#pragma unroll
-                        for (int c = 0; c < CPT; ++c)
-                            if (cv[u][c] > ck[c]) bits |= 1u << (pp0 + u - w * 32);
-                    }
-                }
-                bits = wave_or(bits);
-                if (lane == 0 && bits) atomicOr(&urun[(long long)k * W + w], bits);
+                for (int q = 0; q < Q - 1; ++q) load_slot(q, kb + 32 + q);
             }
+            kb += 32 - Q;
+            continue;
         }
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            eprev[c] = ek[c];
-            ek[c] = ek1[c];
-            ck[c] = ck1[c];
+        for (int ph = 0; ph < Q; ++ph) {
+            const int k = kb + ph;
+            if (k >= N) break;   // uniform
+            load_slot((ph + Q - 1) % Q, k + Q - 1);   // slice k + Q - 1 into the slot of slice k - 1
+            if (!bit_of(k, kw)) {   // uniform: no traversable cell in slice k
+                prev_read = false;
+                continue;
+            }
+            float ek[CPT], ck[CPT], ek1[CPT], ck1[CPT];
+            // slice k+1 (Eq. (9)); without a traversable cell its costs are c^B
+            const bool rk1 = bit_of(k + 1, kw);
+            const int s1 = (ph + 1) % Q;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const bool act = c < nact;
+                ek[c] = act ? eQ[ph][c] : -INFINITY;
+                ck[c] = act ? cQ[ph][c] : cB;
+                ek1[c] = act && rk1 ? eQ[s1][c] : -INFINITY;
+                ck1[c] = act && rk1 ? cQ[s1][c] : cB;
+            }
+            int mloc = -1, pminloc = 0x7fffffff;
+            bool runA[CPT];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (k > 0 && ek[c] != eprev[c]) {
+                    // a new run: it starts at k when slice k-1 was read, else
+                    // below k at a slice not known yet, whose costs are not known
+                    p0[c] = prev_read ? k : -1;
+                    rmax[c] = prev_read ? -INFINITY : cB;
+                } else if (!prev_read && k > 0) {
+                    rmax[c] = cB;   // the run continues over slices without a traversable cell (cost c^B)
+                }
+                const bool trav = c < nact && ck[c] < cB;
+                const bool upper = (k == N - 1) || !rk1 || (ek1[c] > ek[c]) || (ck[c] < ck1[c]);
+                const bool A = trav && upper;
+                if (A && p0[c] < 0) {   // the run start: the lowest slice with this ground
+                    int q = k;
+                    while (q > 0 && ground[(long long)(q - 1) * plane + cell0 + c * STRIDE] == ek[c]) --q;
+                    p0[c] = q;
+                }
+                if (A) mloc = max(mloc, p0[c]);
+                runA[c] = A && p0[c] < k && rmax[c] > ck[c];
+                if (runA[c]) pminloc = min(pminloc, p0[c]);
+                rmax[c] = fmaxf(rmax[c], ck[c]);
+            }
+            if (__ballot(mloc >= 0)) {
+                const int m = wave_max_i(mloc);
+                if (lane == 0) atomicMax(&maxp0[k], m);
+            }
+            if (__ballot(pminloc != 0x7fffffff)) {
+                const int pmin = wave_min_i(pminloc);
+                for (int w = pmin / 32; w <= (k - 1) / 32; ++w) {
+                    unsigned bits = 0;
+                    const int pb = max(pmin, w * 32), pe = min(k, w * 32 + 32);
+                    // eight earlier slices at a time, their loads issued together
+                    for (int pp0 = pb; pp0 < pe; pp0 += 8) {
+                        float cv[8][CPT];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int pp = pp0 + u;
+#pragma unroll
+                            for (int c = 0; c < CPT; ++c)
+                                cv[u][c] = (pp < pe && runA[c] && pp >= p0[c])
+                                               ? cost[(long long)pp * plane + cell0 + c * STRIDE]
+                                               : -INFINITY;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                            for (int c = 0; c < CPT; ++c)
+                                if (cv[u][c] > ck[c]) bits |= 1u << (pp0 + u - w * 32);
+                        }
+                    }
+                    bits = wave_or(bits);
+                    if (lane == 0 && bits) atomicOr(&urun[(long long)k * W + w], bits);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) eprev[c] = ek[c];
+            prev_read = true;
         }
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__ ground, const float* __restrict__ cost,
                                                        const int nx, const int ny, const int N, const float cB,
-                                                       const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun) {
+                                                       const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun,
+                                                       const unsigned* __restrict__ slice_bits) {
     const long long plane = (long long)nx * ny;
     // the wavefront's 64 x kSimpCells cells, lane-interleaved
     const long long wave0 = ((long long)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kSimpCells;
     const long long cell0 = wave0 + (threadIdx.x & 63);
     const long long left = plane - cell0;
     const int nact = left <= 0 ? 0 : (int)std::min<long long>(kSimpCells, (left + 63) / 64);
-    simp_flags_cells<64>(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact);
+    simp_flags_cells<64>(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact, slice_bits);
 }
 
 __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
@@ -748,7 +848,8 @@ __global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, 
 
 size_t eval_ws_bytes(int N, int) {
     const int W = (N + 31) / 32;
-    return align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * W);
+    return align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * W) +
+           align_up(sizeof(unsigned) * (size_t)W);
 }
 
 // The compiled tap-weight patterns: for radius R >= 2, weight exactly 1 for
@@ -772,19 +873,24 @@ static bool weights_follow_pattern(const EvalParams& p) {
 // small enough for 32-bit buffer offsets.
 bool strip_kernel_applies(const EvalParams& p) { return p.rp == 1 && p.R <= 8 && p.plane < (1LL << 29); }
 
-pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
-                       EvalShape shape) {
+namespace {
+
+// The strip evaluation with geometry sg (slice_bits: nullable, the slices
+// with a traversable cell), or the tiled kernel where the strips do not
+// apply (which leaves slice_bits alone).
+pct_status launch_eval_geom(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                            const StripGeom& sg, unsigned* slice_bits) {
     if (strip_kernel_applies(p)) {
         if (weights_follow_pattern(p)) {
             switch (p.R) {
-#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s, shape);
+#define PCT_P(r) case r: return launch_eval_strip<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, p, cost, s, sg, slice_bits);
                 PCT_P(2) PCT_P(3) PCT_P(4) PCT_P(5) PCT_P(6) PCT_P(7) PCT_P(8)
 #undef PCT_P
                 default: break;
             }
         }
         switch (p.R) {
-#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s, shape);
+#define PCT_S(r) case r: return launch_eval_strip<r>(ground, ceil, p, cost, s, sg, slice_bits);
             PCT_S(0) PCT_S(1) PCT_S(2) PCT_S(3) PCT_S(4) PCT_S(5) PCT_S(6) PCT_S(7) PCT_S(8)
 #undef PCT_S
             default: break;
@@ -797,6 +903,14 @@ pct_status launch_eval(const float* ground, const float* ceil, const EvalParams&
 #undef PCT_R
         default: return fail(PCT_ERR_CAPACITY, "inflation radius %d exceeds %d", p.R, PCT_MAX_KERNEL_RADIUS);
     }
+}
+
+}  // namespace
+
+pct_status launch_eval(const float* ground, const float* ceil, const EvalParams& p, float* cost, hipStream_t s,
+                       EvalShape shape) {
+    const StripGeom sg = strip_kernel_applies(p) ? strip_geom(p, shape) : StripGeom{};
+    return launch_eval_geom(ground, ceil, p, cost, s, sg, nullptr);
 }
 
 // Times the strip evaluation of this map shape for each candidate shape
@@ -870,21 +984,71 @@ void autotune_set(const EvalParams& p, EvalShape shape) {
     else g_tune.erase(TuneKey{p.nx, p.ny, p.N, p.R});
 }
 
-pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep, void* ws,
-                           hipStream_t s) {
-    const int W = (p.N + 31) / 32;
-    int* maxp0 = (int*)ws;
-    unsigned* urun = (unsigned*)((char*)ws + align_up(sizeof(int) * (size_t)p.N));
-    hipLaunchKernelGGL(k_simp_init, dim3(std::max(1, std::min(1024, (p.N * W + kBlock - 1) / kBlock))), dim3(kBlock), 0, s,
-                       maxp0, urun, p.N, W);
-    PCT_LAUNCH_CHECK();
+namespace {
+
+// The slice test's scratch: per-slice largest run start, the N x N bit
+// matrix (W words per slice) and the bits of the slices with a traversable
+// cell.
+struct SimpScratch {
+    int* maxp0;
+    unsigned* urun;
+    unsigned* slice_bits;
+    int W;
+};
+
+SimpScratch simp_scratch(void* ws, int N) {
+    SimpScratch sc;
+    sc.W = (N + 31) / 32;
+    sc.maxp0 = (int*)ws;
+    sc.urun = (unsigned*)((char*)ws + align_up(sizeof(int) * (size_t)N));
+    sc.slice_bits = (unsigned*)((char*)sc.urun + align_up(sizeof(unsigned) * (size_t)N * sc.W));
+    return sc;
+}
+
+// Flags and chain over a cleared scratch (slice_bits: nullable).
+pct_status launch_simp_flags(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
+                             const SimpScratch& sc, const unsigned* slice_bits, hipStream_t s) {
     const long long blocks = (p.plane + (long long)kBlock * kSimpCells - 1) / ((long long)kBlock * kSimpCells);
-    hipLaunchKernelGGL(k_simp_flags, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny, p.N, p.cB, W,
-                       maxp0, urun);
+    hipLaunchKernelGGL(k_simp_flags, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny, p.N, p.cB,
+                       sc.W, sc.maxp0, sc.urun, slice_bits);
     PCT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_keep_chain, dim3(1), dim3(64), 0, s, maxp0, urun, p.N, W, keep);
+    hipLaunchKernelGGL(k_keep_chain, dim3(1), dim3(64), 0, s, sc.maxp0, sc.urun, p.N, sc.W, keep);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
+}
+
+}  // namespace
+
+pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep, void* ws,
+                           hipStream_t s) {
+    SimpScratch sc = simp_scratch(ws, p.N);
+    hipLaunchKernelGGL(k_simp_init, dim3(std::max(1, std::min(1024, (p.N * sc.W + kBlock - 1) / kBlock))), dim3(kBlock),
+                       0, s, sc.maxp0, sc.urun, sc.slice_bits, p.N, sc.W);
+    PCT_LAUNCH_CHECK();
+    return launch_simp_flags(ground, cost, p, keep, sc, nullptr, s);
+}
+
+// Evaluation of one robot on the whole map or a window, then (keep
+// non-null) the slice test.  On a whole map the strip kernels mark the
+// slices that hold a traversable cell, and the slice test passes over the
+// others without reading them.
+pct_status launch_eval_simplify(const float* ground, const float* ceil, const EvalParams& p, float* cost, uint8_t* keep,
+                                void* ws, size_t ws_bytes, hipStream_t s) {
+    (void)ws_bytes;
+    if (!keep) return launch_eval(ground, ceil, p, cost, s);
+    const bool whole = p.wx0 == 0 && p.wy0 == 0 && p.wx1 == p.nx && p.wy1 == p.ny;
+    if (!(strip_kernel_applies(p) && whole)) {
+        pct_status st = launch_eval(ground, ceil, p, cost, s);
+        if (st != PCT_OK) return st;
+        return launch_simplify(ground, cost, p, keep, ws, s);
+    }
+    SimpScratch sc = simp_scratch(ws, p.N);
+    hipLaunchKernelGGL(k_simp_init, dim3(std::max(1, std::min(1024, (p.N * sc.W + kBlock - 1) / kBlock))), dim3(kBlock),
+                       0, s, sc.maxp0, sc.urun, sc.slice_bits, p.N, sc.W);
+    PCT_LAUNCH_CHECK();
+    pct_status st = launch_eval_geom(ground, ceil, p, cost, s, strip_geom(p), sc.slice_bits);
+    if (st != PCT_OK) return st;
+    return launch_simp_flags(ground, cost, p, keep, sc, sc.slice_bits, s);
 }
 
 // ------------------------------------------------------------ batches (host)

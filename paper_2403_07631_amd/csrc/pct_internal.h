@@ -136,6 +136,8 @@ pct_status autotune_eval(const float* ground, const float* ceil, const EvalParam
 void autotune_reset();
 void autotune_set(const EvalParams& p, EvalShape shape);
 bool strip_shape_fits(const EvalParams& p, EvalShape shape);
+pct_status launch_eval_simplify(const float* ground, const float* ceil, const EvalParams& p, float* cost, uint8_t* keep,
+                                void* ws, size_t ws_bytes, hipStream_t s);
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
                            void* ws, hipStream_t s);
 

@@ -147,6 +147,22 @@ def tomogram_case(pts, grid, ids=True, label=""):
     return e, tm, (G, Cc)
 
 
+def evaluate_window_whole(G, Cc, grid, e, r):
+    """Evaluation of one robot through the window entry point with the whole
+    map as the window: the same kernels, and a slice test that reads every
+    slice (no slice marks)."""
+    g = grid_s(grid)
+    cells = e.n_slices * grid["nx"] * grid["ny"]
+    cost = Buf(4 * cells)
+    kp = Buf(e.n_slices)
+    ws = Buf(L.pct_eval_workspace_bytes(C.byref(g), C.byref(e), 1))
+    rb = robot_s(r)
+    check("eval window", L.pct_eval_traversability_window(P(G), P(Cc), C.byref(g), C.byref(e), C.byref(rb), 0, 0,
+                                                          grid["nx"], grid["ny"], P(cost), P(kp), P(ws), ws.nbytes,
+                                                          None))
+    return cost, kp
+
+
 def eval_case(pts, grid, robots, label=""):
     e, tm, dev = tomogram_case(pts, grid, ids=False, label=label)
     cost, kp = evaluate(dev[0], dev[1], grid, e, robots)
@@ -192,6 +208,59 @@ def case_edges():
     pts = np.concatenate([spread[:4000], huge, junk, spread[4000:]])
     tomogram_case(pts, grid, True, "huge cell")
     tomogram_case(pts, grid, False, "huge cell")
+
+
+def case_slice_runs():
+    """The slice test that passes over slices without a traversable cell
+    equals the slice test that reads every slice (the window entry point over
+    the whole map) on the same costs: a floor beside a ramp under fine slices
+    (runs of equal ground longer than 64 slices whose costs take many values
+    as the ramp's cells gain ground slice by slice, and slices high above
+    the ramp with no traversable cell between slices that have one), and a
+    multi-storey map."""
+    ramp = scenes.dense_surface_scene(70, 50, 0.1, lambda x, y: np.where(x < 2.5, 0.0, 0.55 * (x - 2.5)),
+                                      per_cell=4, slice_dz=0.04,
+                                      extra=[np.array([[0.05, 0.05, 6.2], [6.95, 4.95, -0.3]], np.float32)])
+    ms = scenes.multistorey_scene(35, 6.1, 4.3, 200_000, n_floors=3)
+    # a floor, a solid block from 1 m to 2 m over most of it (its slices hold
+    # no traversable cell) and a slab at 3.2 m over half: runs on the block's
+    # top start after slices that are passed over
+    xs, ys = np.meshgrid((np.arange(48) + 0.5) * 0.1, (np.arange(36) + 0.5) * 0.1)
+    inside = (xs > 0.6) & (xs < 4.2) & (ys > 0.5) & (ys < 3.1)
+    block = np.concatenate([np.column_stack([xs[inside], ys[inside], np.full(inside.sum(), z)])
+                            for z in np.arange(1.0, 2.001, 0.05)])
+    half = xs < 2.4
+    slab = np.column_stack([xs[half], ys[half], np.full(half.sum(), 3.2)])
+    blk = scenes.dense_surface_scene(48, 36, 0.1, lambda x, y: np.zeros_like(x), per_cell=4, slice_dz=0.1,
+                                     extra=[block.astype(np.float32), slab.astype(np.float32)])
+    for sc, rs, label in ((ramp, [robot(), robot(theta_s=0.7, d_inf=0.5, d_sm=0.7)], "floor and ramp"),
+                          (ms, [robot(), dict(scenes.ROBOT_TABLE1)], "three storeys"),
+                          (blk, [robot(), robot(d_min=0.3, d_inf=0.1, d_sm=0.3)], "floor, block and slab")):
+        e, tm, dev = tomogram_case(sc.points, sc.grid, ids=False, label=label)
+        shape = (len(rs), e.n_slices, sc.grid["ny"], sc.grid["nx"])
+        cost, kp = evaluate(dev[0], dev[1], sc.grid, e, rs)
+        c = cost.get(shape, np.float32)
+        k1 = kp.get((len(rs), e.n_slices), np.uint8)
+        for i, r in enumerate(rs):
+            cost2, kp2 = evaluate_window_whole(dev[0], dev[1], sc.grid, e, r)
+            c2 = cost2.get(shape[1:], np.float32)
+            k2 = kp2.get((e.n_slices,), np.uint8)
+            np.testing.assert_array_equal(bits(c[i]), bits(c2))
+            np.testing.assert_array_equal(k1[i], k2)
+            lo, hi, _ = oracle.envelope(tm["ground"], tm["ceil"], sc.grid["res"], r)
+            ci = c[i].astype(np.float64)
+            assert np.all(ci >= lo - TOL) and np.all(ci <= hi + TOL)
+            assert oracle.simplify_check(tm["ground"], ci, ci, r["c_barrier"], 0.0, k1[i]) == -1
+            trav = c[i] < r["c_barrier"]
+            empty = int((~trav.reshape(e.n_slices, -1).any(axis=1)).sum())
+            g = tm["ground"]
+            run = np.ones(g.shape[1:], np.int32)
+            longest = 1
+            for k in range(1, e.n_slices):
+                run = np.where(g[k] == g[k - 1], run + 1, 1)
+                longest = max(longest, int(run[trav[k]].max(initial=0)))
+            say(f"slice runs {label} robot {i}: N={e.n_slices}, {empty} slices without a traversable cell, "
+                f"longest run over a traversable cell {longest}, {int(k1[i].sum())} kept; both slice tests agree")
 
 
 def case_multirobot():

@@ -192,12 +192,21 @@ inline unsigned emu_raw_buffer_load_b32(emu_buffer_rsrc r, int voff, int soff, i
     memcpy(&v, emu_buffer_addr(r, voff, soff), 4);
     return v;
 }
+inline unsigned long long emu_raw_buffer_load_b64(emu_buffer_rsrc r, int voff, int soff, int aux) {
+    (void)aux;
+    const unsigned long long off = (unsigned long long)(unsigned)voff + (unsigned)soff;
+    if (off + 8 > r.num) __builtin_trap();
+    unsigned long long v;
+    memcpy(&v, r.base + off, 8);
+    return v;
+}
 inline void emu_raw_buffer_store_b32(unsigned v, emu_buffer_rsrc r, int voff, int soff, int aux) {
     (void)aux;
     memcpy(emu_buffer_addr(r, voff, soff), &v, 4);
 }
 #define __builtin_amdgcn_make_buffer_rsrc emu_make_buffer_rsrc
 #define __builtin_amdgcn_raw_buffer_load_b32 emu_raw_buffer_load_b32
+#define __builtin_amdgcn_raw_buffer_load_b64 emu_raw_buffer_load_b64
 #define __builtin_amdgcn_raw_buffer_store_b32 emu_raw_buffer_store_b32
 // A wavefront barrier: every live lane of the wavefront arrives before any
 // continues (the fences around it need nothing more here).
