@@ -263,6 +263,22 @@ def case_slice_runs():
                 f"longest run over a traversable cell {longest}, {int(k1[i].sum())} kept; both slice tests agree")
 
 
+def case_crowded_cells():
+    """Four adjacent cells whose records fit in the tile reduce's LDS one by
+    one but not together (1500 points each), beside ordinary cells, on a
+    grid whose rows are 16-byte aligned and one whose rows are not."""
+    rng = np.random.default_rng(17)
+    for nx in (64, 61):
+        grid = dict(x0=0.0, y0=0.0, res=0.1, nx=nx, ny=9, slice_dz=0.25)
+        crowd = np.column_stack([rng.uniform(0.4, 0.8, 6000), rng.uniform(0.5, 0.6, 6000),
+                                 np.round(rng.uniform(0.0, 3.0, 6000), 2)])
+        rest = np.column_stack([rng.uniform(0.0, nx * 0.1, 4000), rng.uniform(0.0, 0.9, 4000),
+                                rng.uniform(0.0, 3.0, 4000)])
+        pts = np.concatenate([crowd, rest]).astype(np.float32)
+        tomogram_case(pts, grid, True, f"crowded cells nx={nx}")
+        tomogram_case(pts, grid, False, f"crowded cells nx={nx}")
+
+
 def case_multirobot():
     sc = scenes.multistorey_scene(33, 4.3, 3.1, 60_000, n_floors=2)
     rs = [robot(), robot(d_min=0.7, theta_s=0.3), robot(d_inf=0.5, d_sm=0.7)]
