@@ -14,8 +14,12 @@ namespace pct {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kReduceCapIds = 4096;   // LDS record capacity of the tile reduce (with ids)
-constexpr int kReduceCap = 6144;      // ... without ids
+// LDS record capacity of the tile reduce: at least these (with point ids,
+// without), raised per launch towards the mean records per tile, up to
+// kReduceCapMax, so that a dense map reduces each tile in one pass.
+constexpr int kReduceCapIds = 4096;
+constexpr int kReduceCap = 6144;
+constexpr int kReduceCapMax = 16384;
 
 __device__ __forceinline__ float wave_min(float v) {
     for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
@@ -706,8 +710,7 @@ template <bool IDS, bool MERGE = false>
 __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, const float* __restrict__ rz,
                             const unsigned* __restrict__ rmeta, const int* __restrict__ rid, const GridDev& g,
                             float zmin, float ds, int N, float* __restrict__ ground, float* __restrict__ ceil,
-                            int* __restrict__ ag, int* __restrict__ ac, int id_base = 0) {
-    constexpr int CAP = IDS ? kReduceCapIds : kReduceCap;
+                            int* __restrict__ ag, int* __restrict__ ac, int CAP, int id_base = 0) {
     extern __shared__ unsigned s_mem[];
     const int cells = kBuildTileW * g.th;
     unsigned* s_cnt = s_mem;                 // cells
@@ -800,14 +803,31 @@ __global__ __launch_bounds__(kReduceBlock) void k_tile_reduce(const unsigned* __
                                                         const int* __restrict__ rid, GridDev g, float zmin,
                                                         float ds, int N, float* __restrict__ ground,
                                                         float* __restrict__ ceil, int* __restrict__ ag,
-                                                        int* __restrict__ ac, int id_base) {
+                                                        int* __restrict__ ac, int cap, int id_base) {
     reduce_tile<IDS, MERGE>((int)blockIdx.x, (int)blockIdx.x, off, rz, rmeta, rid, g, zmin, ds, N, ground, ceil, ag,
-                            ac, id_base);
+                            ac, cap, id_base);
 }
 
-inline size_t reduce_lds_bytes(const GridDev& g, bool ids) {
+// Record capacity for n points over the grid's tiles: the floor, or 1.25x
+// the mean per tile (rounded up to 1024) when that is larger, up to the cap.
+inline int reduce_cap(int64_t n, const GridDev& g, bool ids) {
+    const int64_t mean = g.ntiles > 0 ? n / g.ntiles : 0;
+    const int64_t want = (mean + mean / 4 + 1023) / 1024 * 1024;
+    return (int)std::min<int64_t>(kReduceCapMax, std::max<int64_t>(ids ? kReduceCapIds : kReduceCap, want));
+}
+
+inline size_t reduce_lds_bytes(const GridDev& g, bool ids, int cap) {
     const int cells = kBuildTileW * g.th;
-    return sizeof(unsigned) * (2 * cells + 1) + (ids ? (size_t)kReduceCapIds * 8 : (size_t)kReduceCap * 4);
+    return sizeof(unsigned) * (2 * cells + 1) + (size_t)cap * (ids ? 8 : 4);
+}
+
+// Kernels may take more than 64 KB of LDS only once asked for.
+pct_status allow_lds(const void* fn, size_t bytes) {
+    if (bytes <= 64 * 1024) return PCT_OK;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return fail(PCT_ERR_DEVICE, "tile reduce LDS request of %zu bytes refused: %s", bytes,
+                                     hipGetErrorString(e));
+    return PCT_OK;
 }
 
 struct BuildWs {
@@ -1030,14 +1050,14 @@ __global__ __launch_bounds__(kReduceBlock) void k_breduce(const unsigned* __rest
                                                     const unsigned* __restrict__ rmeta, const int* __restrict__ rid,
                                                     const BuildItemDev* __restrict__ items, int n_items,
                                                     float* __restrict__ ground, float* __restrict__ ceil,
-                                                    int* __restrict__ ag, int* __restrict__ ac) {
+                                                    int* __restrict__ ag, int* __restrict__ ac, int cap) {
     const int tg = blockIdx.x;
     const int it = find_base(items, n_items, tg, 1);
     const BuildItemDev& d = items[it];
     if (d.N <= 0) return;
     const long long o = d.out_off;
     reduce_tile<IDS>(tg, tg - d.tile_base, off, rz, rmeta, rid, d.g, d.zmin, d.ds, d.N, ground + o, ceil + o,
-                     IDS ? ag + o : nullptr, IDS ? ac + o : nullptr);
+                     IDS ? ag + o : nullptr, IDS ? ac + o : nullptr, cap);
 }
 
 struct BatchWs {
@@ -1221,19 +1241,25 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
             PCT_LAUNCH_CHECK();
         }
     }
-    const size_t rl = reduce_lds_bytes(g, ids);
-    if (ids && merge)
+    const int cap = reduce_cap(n, g, ids);
+    const size_t rl = reduce_lds_bytes(g, ids, cap);
+    if (ids && merge) {
+        if (pct_status st = allow_lds((const void*)k_tile_reduce<true, true>, rl)) return st;
         hipLaunchKernelGGL((k_tile_reduce<true, true>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta,
-                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, id_base);
-    else if (merge)
+                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, cap, id_base);
+    } else if (merge) {
+        if (pct_status st = allow_lds((const void*)k_tile_reduce<false, true>, rl)) return st;
         hipLaunchKernelGGL((k_tile_reduce<false, true>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta,
-                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, id_base);
-    else if (ids)
+                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, cap, id_base);
+    } else if (ids) {
+        if (pct_status st = allow_lds((const void*)k_tile_reduce<true, false>, rl)) return st;
         hipLaunchKernelGGL((k_tile_reduce<true, false>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz, w.rmeta,
-                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, 0);
-    else
+                           w.rid, g, zmin, ds, N, ground, ceil, ag, ac, cap, 0);
+    } else {
+        if (pct_status st = allow_lds((const void*)k_tile_reduce<false, false>, rl)) return st;
         hipLaunchKernelGGL((k_tile_reduce<false, false>), dim3(g.ntiles), dim3(kReduceBlock), rl, s, w.off, w.rz,
-                           w.rmeta, w.rid, g, zmin, ds, N, ground, ceil, ag, ac, 0);
+                           w.rmeta, w.rid, g, zmin, ds, N, ground, ceil, ag, ac, cap, 0);
+    }
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -1372,12 +1398,18 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
         PCT_HIP(hipMemcpyAsync(w.items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
         PCT_HIP(hipStreamSynchronize(s));
     }
-    int max_tiles_lds = 0;
-    size_t max_reduce_lds = 0;
+    int max_tiles_lds = 0, max_th = 1, cap = 0;
     for (int i = 0; i < n_items; ++i) {
         if (h_items[i].g.ntiles <= kMaxLdsTiles) max_tiles_lds = std::max(max_tiles_lds, h_items[i].g.ntiles);
-        max_reduce_lds = std::max(max_reduce_lds, reduce_lds_bytes(h_items[i].g, ids));
+        max_th = std::max(max_th, h_items[i].g.th);
+        cap = std::max(cap, reduce_cap(h_items[i].n, h_items[i].g, ids));
     }
+    cap = std::max(cap, ids ? kReduceCapIds : kReduceCap);
+    GridDev g_lds{};
+    g_lds.th = max_th;
+    const size_t max_reduce_lds = reduce_lds_bytes(g_lds, ids, cap);
+    if (pct_status st = allow_lds(ids ? (const void*)k_breduce<true> : (const void*)k_breduce<false>, max_reduce_lds))
+        return st;
     hipLaunchKernelGGL(k_fill_u32, dim3(std::min(1024, w.total_tiles / kBlock + 1)), dim3(kBlock), 0, s, w.count,
                        (int64_t)w.total_tiles + 1, 0u);
     PCT_LAUNCH_CHECK();
@@ -1401,10 +1433,10 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
     if (w.total_tiles > 0) {
         if (ids)
             hipLaunchKernelGGL(k_breduce<true>, dim3(w.total_tiles), dim3(kReduceBlock), max_reduce_lds, s, w.off, w.rz, w.rmeta,
-                               w.rid, w.items, n_items, ground, ceil, ag, ac);
+                               w.rid, w.items, n_items, ground, ceil, ag, ac, cap);
         else
             hipLaunchKernelGGL(k_breduce<false>, dim3(w.total_tiles), dim3(kReduceBlock), max_reduce_lds, s, w.off, w.rz,
-                               w.rmeta, w.rid, w.items, n_items, ground, ceil, ag, ac);
+                               w.rmeta, w.rid, w.items, n_items, ground, ceil, ag, ac, cap);
         PCT_LAUNCH_CHECK();
     }
     return PCT_OK;

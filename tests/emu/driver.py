@@ -279,6 +279,31 @@ def case_crowded_cells():
         tomogram_case(pts, grid, False, f"crowded cells nx={nx}")
 
 
+def case_dense_tiles():
+    """Tiles with more records on average than the tile reduce's floor
+    capacity, so that the launch raises it (above 64 KB of LDS): 12 000
+    points a tile (one pass) and 20 000 (above the largest capacity, two
+    passes), as one map and in a batch beside a sparse submap."""
+    rng = np.random.default_rng(23)
+    grid = dict(x0=0.0, y0=0.0, res=0.1, nx=40, ny=6, slice_dz=0.3)
+    maps = []
+    for n in (36_000, 60_000):
+        pts = np.column_stack([rng.uniform(0.0, 4.0, n), rng.uniform(0.0, 0.6, n),
+                               rng.uniform(0.0, 3.0, n)]).astype(np.float32)
+        tomogram_case(pts, grid, True, f"dense tiles, {n} points")
+        tomogram_case(pts, grid, False, f"dense tiles, {n} points")
+        maps.append(scenes.Scene(pts, grid))
+    maps.append(scenes.multistorey_scene(24, 4.1, 3.3, 20_000, n_floors=2))
+    pts, specs, off = [], [], 0
+    for sc in maps:
+        specs.append(dict(xyz_offset=off, n_points=len(sc.points), grid=sc.grid))
+        pts.append(sc.points)
+        off += len(sc.points)
+    pts = np.ascontiguousarray(np.concatenate(pts))
+    for ids in (True, False):
+        check_batch(maps, pts, specs, [robot()], ids)
+
+
 def case_multirobot():
     sc = scenes.multistorey_scene(33, 4.3, 3.1, 60_000, n_floors=2)
     rs = [robot(), robot(d_min=0.7, theta_s=0.3), robot(d_inf=0.5, d_sm=0.7)]
@@ -578,6 +603,33 @@ def case_traj_value_grad():
     # float atomics add in a different order: a few ulps of the largest partial sums
     a, b = gz2.get(n, np.float32), gz1.get(n, np.float32)
     np.testing.assert_allclose(a, b, rtol=1e-5, atol=2e-5 * max(1.0, float(np.abs(b).max())))
+    # fixed-point sums: the per-profile loop and the one launch give the same
+    # integers whatever order the (shuffled) wavefronts add in
+    gz1x = Buf(8 * n)
+    for i, r in enumerate(profiles):
+        cost, _ = evaluate(G, Cc, grid, e, [r], keep=False)
+        wpb1, slb1, gfb1 = Buf.of(wp_all[i]), Buf.of(sl_all[i]), Buf.of(gf_all[i])
+        traj_bwd(G, Cc, cost, aG, aC, grid, e, r, w_z, wpb1, slb1, T, W, gfb1, n, gz1x,
+                 abi.PCT_FIXED_POINT | (abi.PCT_ACCUMULATE if i else 0))
+    f2x, gwp2x, gz2x = Buf(4 * len(profiles) * T), Buf(12 * wp_all[..., 0].size), Buf(8 * n)
+    gG2x, gC2x = Buf(8 * int(np.prod(shape))), Buf(8 * int(np.prod(shape)))
+    check("multi fixed", L.pct_trajectory_cost_multi(P(G), P(Cc), P(aG), P(aC), C.byref(g), C.byref(e), rs,
+                                                     len(profiles), w_z, P(wpb), P(slb), T, W, P(gfb), P(f2x),
+                                                     P(gwp2x), P(gG2x), P(gC2x), n, P(gz2x), abi.PCT_FIXED_POINT,
+                                                     P(ws), ws.nbytes, None))
+    q1, q2 = gz1x.get(n, np.int64), gz2x.get(n, np.int64)
+    np.testing.assert_array_equal(q1, q2)
+    assert np.count_nonzero(q2) > 20 and np.abs(q2).max() < 2 ** 53
+    np.testing.assert_array_equal(bits(gwp2x.get(wp_all.shape, np.float32)), bits(gwp2))
+    zf = Buf(4 * n)
+    check("fixed_to_float", L.pct_fixed_to_float(P(gz2x), n, P(zf), None))
+    zf = zf.get(n, np.float32)
+    np.testing.assert_array_equal(bits(zf), bits((q2.astype(np.float64) * 2.0 ** -32).astype(np.float32)))
+    np.testing.assert_allclose(zf, a, rtol=1e-5, atol=2e-5 * max(1.0, float(np.abs(a).max())))
+    for qx, fl in ((gG2x, gG2), (gC2x, gC2)):
+        qv, fv = qx.get(int(np.prod(shape)), np.int64), fl.get(int(np.prod(shape)), np.float32)
+        np.testing.assert_allclose(qv * 2.0 ** -32, fv, rtol=1e-5, atol=2e-5 * max(1.0, float(np.abs(fv).max())))
+    assert L.pct_fixed_to_float(P(gz2x), n, P(gz2x), None) == abi.PCT_ERR_ARG
     # values only: the same f, gradients untouched
     f3 = Buf(4 * len(profiles) * T)
     check("multi value", L.pct_trajectory_cost_multi(P(G), P(Cc), None, None, C.byref(g), C.byref(e), rs,
