@@ -164,7 +164,15 @@ def bench_profiles(P, torch, sc, xyz, dev, steps, warmup, n_profiles=64, n_walks
     gf = torch.ones((n_profiles, n_walks), device=dev)
     f1 = torch.empty((n_profiles, n_walks), device=dev)
     gwp1 = torch.empty_like(wp)
+    # point gradients are summed in fixed point (int64, 2^-32 units) and
+    # converted to float32 once: both paths give the same bits
+    gz1_acc = torch.empty(n, dtype=torch.int64, device=dev)
     gz1 = torch.empty(n, device=dev)
+
+    def to_float(acc, dst):
+        st = P.lib().pct_fixed_to_float(acc.data_ptr(), n, dst.data_ptr(), P._stream(dev))
+        if st != P.PCT_OK:
+            raise RuntimeError(P.lib().pct_last_error().decode())
 
     def plain():
         for i, rb in enumerate(rbs):
@@ -172,17 +180,20 @@ def bench_profiles(P, torch, sc, xyz, dev, steps, warmup, n_profiles=64, n_walks
             cost = cost[0]
             f1[i] = P.pct_sample_cost_fwd(cost, G, g, ext, rb, 1.0, wp[i], sl[i])
             P.pct_trajectory_cost_bwd(G, Cc, cost, aG, aC, g, ext, rb, 1.0, wp[i], sl[i], gf[i], n, gwp=gwp1[i],
-                                      gz=gz1, flags=P.PCT_ACCUMULATE if i else 0)
+                                      gz=gz1_acc, flags=P.PCT_ACCUMULATE if i else 0)
+        to_float(gz1_acc, gz1)
 
     f2 = torch.empty((n_profiles, n_walks), device=dev)
     gwp2 = torch.empty_like(wp)
+    gz2_acc = torch.empty(n, dtype=torch.int64, device=dev)
     gz2 = torch.empty(n, device=dev)
     ws = torch.empty(P.lib().pct_trajectory_multi_workspace_bytes(n_profiles), dtype=torch.uint8, device=dev)
-    out = (f2, gwp2, None, None, gz2)
+    out = (f2, gwp2, None, None, gz2_acc)
 
     def batched(flags=0):
         P.pct_trajectory_cost_multi(G, Cc, aG, aC, g, ext, rbs, 1.0, wp, sl, gf, n_points=n, flags=flags,
                                     workspace=ws, out=out)
+        to_float(gz2_acc, gz2)
 
     s = torch.cuda.current_stream(dev)
 
@@ -293,27 +304,49 @@ def bench_submaps(P, torch, dev, steps, warmup, n_items=512):
     for _ in range(max(1, warmup)):
         plain()
     ms_plain = timed(plain, steps)
-    log("submaps: batched path")
-    build_eval()
-    torch.cuda.synchronize()
-    cs = torch.cuda.Stream(device=dev)
-    cs.wait_stream(torch.cuda.current_stream(dev))
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(cs):
-        build_eval(P.PCT_DESCRIPTORS_RESIDENT)
+    def capture():
+        build_eval()                     # uploads the descriptor tables
         torch.cuda.synchronize()
-        with torch.cuda.graph(graph, stream=cs):
+        cs = torch.cuda.Stream(device=dev)
+        cs.wait_stream(torch.cuda.current_stream(dev))
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(cs):
             build_eval(P.PCT_DESCRIPTORS_RESIDENT)
-    torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(graph, stream=cs):
+                build_eval(P.PCT_DESCRIPTORS_RESIDENT)
+        torch.cuda.synchronize()
 
-    def batched():
-        P.pct_tomogram_extent_batched(b)
-        graph.replay()
+        def batched():
+            P.pct_tomogram_extent_batched(b)
+            graph.replay()
 
-    for _ in range(max(1, warmup)):
-        batched()
-    ms_batched = timed(batched, steps)
-    ms_graph = timed(graph.replay, steps)
+        for _ in range(max(1, warmup)):
+            batched()
+        return graph, timed(batched, steps), timed(graph.replay, steps)
+
+    log("submaps: batched path, default tile shapes")
+    P.pct_autotune_reset()
+    _, ms_default, ms_graph_default = capture()
+    log("submaps: tuning tile shapes per size class")
+    t0 = time.perf_counter()
+    ent = P.pct_autotune_batched(b, rb)
+    tune_s = time.perf_counter() - t0
+    classes = {}
+    for e in ent:
+        key = f"2^{e['class_x']} x 2^{e['class_y']}"
+        c = classes.setdefault(key, {"items": e["n_items"], "build_ms": {}, "eval_ms": {}})
+        if e["stage"] == "build":
+            c["build_ms"][f"th{e['rows']}"] = round(e["ms"], 4)
+            if e["chosen"]:
+                c["build_chosen"] = f"th{e['rows']}"
+        else:
+            name = "default" if e["rows"] == 0 else f"{e['rows']}x{e['waves']}"
+            c["eval_ms"][name] = round(e["ms"], 4)
+            if e["chosen"]:
+                c["eval_chosen"] = name
+    log("submaps: batched path, tuned tile shapes")
+    graph, ms_batched, ms_graph = capture()
     # outputs: the plain results of every item equal the batched ones
     outs = plain()
     torch.cuda.synchronize()
@@ -335,7 +368,11 @@ def bench_submaps(P, torch, dev, steps, warmup, n_items=512):
             "batched": "one extent pass with one read-back, then construction + evaluation of all submaps "
                        "as one graph replay",
             "plain_ms": ms_plain, "batched_ms": ms_batched, "ratio": ms_plain / ms_batched,
-            "graph_replay_ms": ms_graph, "identical": same}
+            "graph_replay_ms": ms_graph, "identical": same,
+            "batched_default_shapes_ms": ms_default, "graph_replay_default_shapes_ms": ms_graph_default,
+            "tuning": {"what": "per size class (ceil(log2 nx), ceil(log2 ny)): construction tile height 2/4/8 and "
+                               "evaluation strip rows x wavefronts, each timed on a batch of that class's items; "
+                               "batched_ms uses the chosen shapes", "seconds": tune_s, "classes": classes}}
 
 
 def bench_plan(P, torch, dev, steps, warmup, cpu=True):

@@ -237,7 +237,8 @@ pct_status pct_autotune_traversability(const float* d_ground, const float* d_cei
                                        int32_t* h_best_rows, int32_t* h_best_waves, int32_t* h_rows,
                                        int32_t* h_waves, float* h_ms, int32_t n_max, int32_t* h_count, void* stream);
 
-/* Forgets every height the autotuner recorded (defaults apply again). */
+/* Forgets every shape the autotuners recorded, single-map and per size
+ * class (defaults apply again). */
 pct_status pct_autotune_reset(void);
 
 /* Records a strip shape (rows, waves as in the autotuner) for the
@@ -258,6 +259,26 @@ pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_exten
 /* Flag for the gradient entry points: add into the gradient outputs instead
  * of overwriting them (without it the outputs are zero-filled first). */
 #define PCT_ACCUMULATE 1
+
+/* Flag for the gradient entry points: the summed gradient outputs (d_gcost,
+ * d_gground, d_gceil, d_gz; not d_gwp, which is written once per waypoint)
+ * are int64_t arrays in fixed point, value = integer * 2^-PCT_FIXED_FRAC_BITS,
+ * passed through the same float* parameters (8 bytes per element).  Each
+ * contribution is rounded to the nearest multiple of 2^-32 (ties to even)
+ * and added as an integer, so a sum is the same whatever the order in which
+ * its terms arrive, and the same when the work is split over several calls
+ * with PCT_ACCUMULATE: a per-profile loop and pct_trajectory_cost_multi
+ * give identical bits.  Without the flag the sums are float atomics whose
+ * last bits depend on that order.  Range: a contribution is clamped to
+ * +-2^30, NaN adds nothing, and a sum beyond +-2^31 wraps.  Convert with
+ * pct_fixed_to_float. */
+#define PCT_FIXED_POINT 4
+#define PCT_FIXED_FRAC_BITS 32
+
+/* d_out[i] = d_acc[i] * 2^-32 correctly rounded to float32, for i < n: the
+ * fixed-point gradient sums of PCT_FIXED_POINT as floats.  d_acc (int64_t
+ * [n]) and d_out (float32 [n]) must not overlap (PCT_ERR_ARG). */
+pct_status pct_fixed_to_float(const int64_t* d_acc, int64_t n, float* d_out, void* stream);
 
 /* The cost and height terms of the trajectory optimisation, Eq. (11):
  * travel cost C and preferred height Z_ref = e^G + d_ref along a trajectory.
@@ -382,6 +403,52 @@ pct_status pct_eval_traversability_batched(const float* d_ground, const float* d
                                            int32_t n_items, const pct_robot* h_robots, int32_t n_robots,
                                            float* d_cost, uint8_t* d_keep, int32_t flags, void* d_ws,
                                            size_t ws_bytes, void* stream);
+
+/* One timing of pct_autotune_batched: a construction tile height or an
+ * evaluation strip shape tried on the items of one size class. */
+typedef struct {
+    int32_t stage;     /* 0: construction tile height, 1: evaluation strip shape */
+    int32_t class_x;   /* ceil(log2 nx) of the class's items */
+    int32_t class_y;   /* ceil(log2 ny) */
+    int32_t radius;    /* the evaluation's inflation radius R in cells; -1 for the construction */
+    int32_t rows;      /* construction: tile height in cells; evaluation: strip rows (0: the default shape) */
+    int32_t waves;     /* evaluation: wavefronts per workgroup (1 or PCT_STRIP_WAVES); 0 for the construction */
+    int32_t n_items;   /* items in the class */
+    int32_t chosen;    /* 1 for the choice recorded for the class */
+    float ms;          /* mean time of one batched call over the class's items */
+} pct_tune_entry;
+
+/* Tile shapes for batches of submaps (the performance tuning of the batched
+ * Sec. III-A construction and Sec. III-B evaluation; results do not depend
+ * on them).  Items with slices are grouped into size classes
+ * (ceil(log2 nx), ceil(log2 ny), and R for h_robot); for each class the
+ * construction is timed at tile heights 2, 4 and 8 (those not below the
+ * default) and the evaluation (without slice test) at the default strip
+ * shape and at 32, 64, 128 and 256 rows with 1 or PCT_STRIP_WAVES
+ * wavefronts, each as a batch of only that class's items, and the fastest
+ * is recorded for the class.  Later batched calls use the recorded shapes
+ * (the construction never with more tiles than the default, so workspaces
+ * sized before tuning still suffice).  h_items must carry extents
+ * (pct_tomogram_extent_batched); d_xyz as for pct_build_tomogram_batched.
+ * The call allocates and frees its own device buffers and synchronises
+ * `stream`; the caller's workspaces are not touched, but their resident
+ * descriptor tables no longer match tuned classes: the next batched call on
+ * them must upload (no PCT_DESCRIPTORS_RESIDENT), and graphs captured before
+ * tuning keep replaying the shapes they captured.  Up to n_max timings go to
+ * h_out; *h_count = their number. */
+pct_status pct_autotune_batched(const float* d_xyz, int64_t n_total, const pct_item* h_items, int32_t n_items,
+                                const pct_robot* h_robot, pct_tune_entry* h_out, int32_t n_max, int32_t* h_count,
+                                void* stream);
+
+/* The tuning tables (single-map strip shapes of pct_autotune_traversability
+ * and pct_autotune_set_traversability, and the size-class tables of
+ * pct_autotune_batched) as a text file, one record a line, each tagged with
+ * the current device's architecture name.  pct_autotune_load adds the
+ * records of the current architecture to the tables (others are skipped;
+ * *n_applied, nullable, counts the added ones) and applies nothing if any
+ * line is malformed (PCT_ERR_ARG naming the line). */
+pct_status pct_autotune_save(const char* path);
+pct_status pct_autotune_load(const char* path, int32_t* n_applied);
 
 /* Workspace bytes for pct_trajectory_cost_multi with n_profiles profiles. */
 size_t pct_trajectory_multi_workspace_bytes(int32_t n_profiles);

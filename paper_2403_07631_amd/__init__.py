@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpct.so")
 
 from .abi import (PCT_ACCUMULATE, PCT_DESCRIPTORS_RESIDENT, PCT_ERR_ARG, PCT_ERR_CAPACITY,  # noqa: F401
-                  PCT_ERR_DEVICE, PCT_ERR_WORKSPACE, PCT_MAX_SLICES, PCT_OK, PCT_STRIP_WAVES, _ROBOT_FIELDS,
+                  PCT_ERR_DEVICE, PCT_ERR_WORKSPACE, PCT_FIXED_POINT, PCT_MAX_SLICES, PCT_OK, PCT_STRIP_WAVES,
+                  _ROBOT_FIELDS,
                   pct_extent, pct_grid,
                   pct_item, pct_robot)
 from . import abi as _abi
@@ -534,36 +535,69 @@ def pct_sample_cost_fwd(cost, ground, grid, extent, robot, w_z, wp, slices):
     return f
 
 
-def pct_sample_cost_bwd(cost, ground, grid, extent, robot, w_z, wp, slices, gf, grids=True):
+def pct_fixed_to_float(acc):
+    """Fixed-point gradient sums (int64, units of 2^-32) as float32."""
+    if not (acc.is_cuda and acc.dtype == torch.int64 and acc.is_contiguous()):
+        raise ValueError("acc must be a contiguous CUDA int64 tensor")
+    out = torch.empty(acc.shape, dtype=torch.float32, device=acc.device)
+    _check("pct_fixed_to_float", lib().pct_fixed_to_float(_ptr(acc), acc.numel(), _ptr(out), _stream(acc.device)))
+    return out
+
+
+def _sum_outputs(*ts):
+    """PCT_FIXED_POINT when the given gradient sums are int64, 0 when float32."""
+    kinds = {t.dtype for t in ts if t is not None}
+    if kinds <= {torch.float32}:
+        return 0
+    if kinds == {torch.int64}:
+        return PCT_FIXED_POINT
+    raise ValueError("gradient sums must all be float32 or all int64 (fixed point)")
+
+
+def _sum_dtype(deterministic):
+    return torch.int64 if deterministic else torch.float32
+
+
+def pct_sample_cost_bwd(cost, ground, grid, extent, robot, w_z, wp, slices, gf, grids=True, deterministic=True):
     """(gwp [T, W, 3], gcost, gground) - the grid gradients are [N, ny, nx]
-    (None unless ``grids``)."""
+    (None unless ``grids``), summed in fixed point unless not
+    ``deterministic`` (then float atomics, order-dependent in the last bits)."""
     wp, slices = _wp(wp, slices)
     g, rb = grid_struct(grid), robot_struct(robot)
     T, W = slices.shape
     dev = wp.device
     gwp = torch.empty_like(wp)
-    gcost = torch.empty_like(cost) if grids else None
-    gground = torch.empty_like(ground) if grids else None
+    dt = _sum_dtype(deterministic)
+    gcost = torch.empty(cost.shape, dtype=dt, device=dev) if grids else None
+    gground = torch.empty(ground.shape, dtype=dt, device=dev) if grids else None
     _check("pct_sample_cost_bwd",
            lib().pct_sample_cost_bwd(_ptr(cost), _ptr(ground), C.byref(g), C.byref(extent), C.byref(rb), float(w_z),
                                      _ptr(wp), _ptr(slices), T, W, _ptr(gf.contiguous()), _ptr(gwp), _ptr(gcost),
-                                     _ptr(gground), 0, _stream(dev)))
+                                     _ptr(gground), _sum_outputs(gcost, gground), _stream(dev)))
+    if deterministic and grids:
+        gcost, gground = pct_fixed_to_float(gcost), pct_fixed_to_float(gground)
     return gwp, gcost, gground
 
 
-def pct_eval_traversability_bwd(ground, ceil, grid, extent, robot, gcost):
-    """(dL/de^G, dL/de^C) [N, ny, nx] for dL/dc^T = gcost (one robot)."""
+def pct_eval_traversability_bwd(ground, ceil, grid, extent, robot, gcost, deterministic=True):
+    """(dL/de^G, dL/de^C) [N, ny, nx] for dL/dc^T = gcost (one robot),
+    summed in fixed point unless not ``deterministic``."""
     g, rb = grid_struct(grid), robot_struct(robot)
-    gG, gC = torch.empty_like(ground), torch.empty_like(ceil)
+    dt = _sum_dtype(deterministic)
+    gG = torch.empty(ground.shape, dtype=dt, device=ground.device)
+    gC = torch.empty(ceil.shape, dtype=dt, device=ground.device)
     _check("pct_eval_traversability_bwd",
            lib().pct_eval_traversability_bwd(_ptr(ground), _ptr(ceil), C.byref(g), C.byref(extent), C.byref(rb),
-                                             _ptr(gcost.contiguous()), _ptr(gG), _ptr(gC), 0,
+                                             _ptr(gcost.contiguous()), _ptr(gG), _ptr(gC), _sum_outputs(gG, gC),
                                              _stream(ground.device)))
+    if deterministic:
+        gG, gC = pct_fixed_to_float(gG), pct_fixed_to_float(gC)
     return gG, gC
 
 
 def pct_route_grad_to_points(gground, gceil, arg_ground, arg_ceil, grid, extent, n_points):
-    """dL/dz [n_points] from grid gradients and the recorded point ids."""
+    """dL/dz [n_points] from grid gradients and the recorded point ids (each
+    point's sum is formed by the one thread of its cell, in slice order)."""
     g = grid_struct(grid)
     gz = torch.empty(n_points, dtype=torch.float32, device=gground.device)
     _check("pct_route_grad_to_points",
@@ -573,30 +607,39 @@ def pct_route_grad_to_points(gground, gceil, arg_ground, arg_ceil, grid, extent,
 
 
 def pct_trajectory_cost_bwd(ground, ceil, cost, arg_ground, arg_ceil, grid, extent, robot, w_z, wp, slices, gf,
-                            n_points, gwp=None, gz=None, flags=0):
+                            n_points, gwp=None, gz=None, flags=0, deterministic=True):
     """(gwp [T, W, 3], gz [n_points]) in one pass (no dense gradient grids).
-    gwp/gz may be passed in; with ``flags=PCT_ACCUMULATE`` gz is added to."""
+    gwp/gz may be passed in; with ``flags=PCT_ACCUMULATE`` gz is added to.
+    A gz passed in as int64 holds fixed-point sums (units of 2^-32) and is
+    returned as it is, so that calls accumulate exactly; an allocated gz is
+    summed in fixed point and returned as float32 unless not
+    ``deterministic``."""
     wp, slices = _wp(wp, slices)
     g, rb = grid_struct(grid), robot_struct(robot)
     T, W = slices.shape
     gwp = torch.empty_like(wp) if gwp is None else gwp
-    gz = torch.empty(n_points, dtype=torch.float32, device=wp.device) if gz is None else gz
+    convert = gz is None and deterministic
+    if gz is None:
+        gz = torch.empty(n_points, dtype=_sum_dtype(deterministic), device=wp.device)
     _check("pct_trajectory_cost_bwd",
            lib().pct_trajectory_cost_bwd(_ptr(ground), _ptr(ceil), _ptr(cost), _ptr(arg_ground), _ptr(arg_ceil),
                                          C.byref(g), C.byref(extent), C.byref(rb), float(w_z), _ptr(wp),
                                          _ptr(slices), T, W, _ptr(gf.contiguous()), n_points, _ptr(gwp), _ptr(gz),
-                                         int(flags), _stream(wp.device)))
-    return gwp, gz
+                                         int(flags) | _sum_outputs(gz), _stream(wp.device)))
+    return gwp, (pct_fixed_to_float(gz) if convert else gz)
 
 
 def pct_trajectory_cost_multi(ground, ceil, arg_ground, arg_ceil, grid, extent, robots, w_z, wp, slices, gf=None,
-                              n_points=0, grids=False, flags=0, workspace=None, out=None):
+                              n_points=0, grids=False, flags=0, workspace=None, out=None, deterministic=True):
     """Several robot profiles on one map in one launch, c^T evaluated only at
     the sampled corners.  wp [P, T, W, 3], slices [P, T, W], gf [P, T] or
     None.  Returns (f [P, T], gwp [P, T, W, 3], gground, gceil, gz); the
     gradients are None without gf, the grids None unless ``grids``, gz None
     unless n_points > 0.  ``out`` passes preallocated (f, gwp, gground,
-    gceil, gz) and ``workspace`` a preallocated workspace (for graphs)."""
+    gceil, gz) and ``workspace`` a preallocated workspace (for graphs);
+    gradient sums passed in as int64 are fixed point (units of 2^-32) and
+    returned as they are.  Allocated sums are formed in fixed point and
+    returned as float32 unless not ``deterministic``."""
     if isinstance(robots, (pct_robot, dict)):
         robots = [robots]
     rs = (pct_robot * len(robots))(*[robot_struct(r) for r in robots])
@@ -613,12 +656,14 @@ def pct_trajectory_cost_multi(ground, ceil, arg_ground, arg_ceil, grid, extent, 
         gf = gf.contiguous()
         if tuple(gf.shape) != (Pn, T):
             raise ValueError("gf must be [P, T]")
+    convert = out is None and deterministic and gf is not None
     if out is None:
+        dt = _sum_dtype(deterministic)
         f = torch.empty((Pn, T), dtype=torch.float32, device=dev)
         gwp = torch.empty_like(wp) if gf is not None else None
-        gground = torch.empty_like(ground) if (gf is not None and grids) else None
-        gceil = torch.empty_like(ceil) if (gf is not None and grids) else None
-        gz = torch.empty(n_points, dtype=torch.float32, device=dev) if (gf is not None and n_points > 0) else None
+        gground = torch.empty(ground.shape, dtype=dt, device=dev) if (gf is not None and grids) else None
+        gceil = torch.empty(ceil.shape, dtype=dt, device=dev) if (gf is not None and grids) else None
+        gz = torch.empty(n_points, dtype=dt, device=dev) if (gf is not None and n_points > 0) else None
     else:
         f, gwp, gground, gceil, gz = out
     need = lib().pct_trajectory_multi_workspace_bytes(Pn)
@@ -627,7 +672,10 @@ def pct_trajectory_cost_multi(ground, ceil, arg_ground, arg_ceil, grid, extent, 
            lib().pct_trajectory_cost_multi(_ptr(ground), _ptr(ceil), _ptr(arg_ground), _ptr(arg_ceil), C.byref(g),
                                            C.byref(extent), rs, Pn, float(w_z), _ptr(wp), _ptr(slices), T, W,
                                            _ptr(gf), _ptr(f), _ptr(gwp), _ptr(gground), _ptr(gceil), int(n_points),
-                                           _ptr(gz), int(flags), _ptr(ws), ws.numel(), _stream(dev)))
+                                           _ptr(gz), int(flags) | _sum_outputs(gground, gceil, gz), _ptr(ws),
+                                           ws.numel(), _stream(dev)))
+    if convert:
+        gground, gceil, gz = (None if t is None else pct_fixed_to_float(t) for t in (gground, gceil, gz))
     return f, gwp, gground, gceil, gz
 
 
@@ -773,3 +821,38 @@ def pct_eval_traversability_batched(batch: Batch, ground, ceil, robots, keep=Tru
                                                  _ptr(cost), _ptr(kp), flags, _ptr(batch.ws), batch.ws.numel(),
                                                  _stream(dev)))
     return cost, kp
+
+
+def pct_autotune_batched(batch: Batch, robot, n_max=1024):
+    """Times construction tile heights and evaluation strip shapes per size
+    class of the batch's items (after pct_tomogram_extent_batched) and
+    records the fastest for later batched calls; returns the timings as
+    dicts (stage "build" or "eval", class_x, class_y, radius, rows, waves,
+    n_items, chosen, ms).  The batch's next calls must upload their
+    descriptor tables again (no PCT_DESCRIPTORS_RESIDENT)."""
+    rb = robot_struct(robot)
+    ent = (_abi.pct_tune_entry * n_max)()
+    cnt = C.c_int32()
+    _check("pct_autotune_batched",
+           lib().pct_autotune_batched(_ptr(batch.xyz), batch.xyz.shape[0], batch.items, batch.n, C.byref(rb), ent,
+                                      n_max, C.byref(cnt), _stream(batch.xyz.device)))
+    out = []
+    for e in ent[:min(cnt.value, n_max)]:
+        out.append(dict(stage="build" if e.stage == 0 else "eval", class_x=e.class_x, class_y=e.class_y,
+                        radius=e.radius, rows=e.rows, waves=e.waves, n_items=e.n_items, chosen=bool(e.chosen),
+                        ms=float(e.ms)))
+    return out
+
+
+def pct_autotune_save(path):
+    """Writes every recorded tuning shape to a text file (for this device's
+    architecture)."""
+    _check("pct_autotune_save", lib().pct_autotune_save(os.fsencode(path)))
+
+
+def pct_autotune_load(path):
+    """Adds the shapes a file records for this device's architecture;
+    returns how many were added."""
+    n = C.c_int32()
+    _check("pct_autotune_load", lib().pct_autotune_load(os.fsencode(path), C.byref(n)))
+    return int(n.value)

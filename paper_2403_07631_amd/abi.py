@@ -11,6 +11,8 @@ PCT_MAX_PIECES = 64
 PCT_MAX_TRAJ_SAMPLES = 64
 PCT_ACCUMULATE = 1
 PCT_DESCRIPTORS_RESIDENT = 2
+PCT_FIXED_POINT = 4
+PCT_FIXED_FRAC_BITS = 32
 PCT_STRIP_WAVES = 4
 
 
@@ -31,6 +33,11 @@ _ROBOT_FIELDS = ("d_min", "d_ref", "theta_b", "theta_s", "theta_p", "c_barrier",
 class pct_item(C.Structure):
     _fields_ = [("xyz_offset", C.c_int64), ("n_points", C.c_int64), ("grid", pct_grid), ("reserved", C.c_int32),
                 ("extent", pct_extent), ("out_offset", C.c_int64), ("keep_offset", C.c_int64)]
+
+
+class pct_tune_entry(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("stage", "class_x", "class_y", "radius", "rows", "waves", "n_items",
+                                         "chosen")] + [("ms", C.c_float)]
 
 
 class pct_robot(C.Structure):
@@ -81,6 +88,10 @@ def load(path):
         "pct_route_grad_to_points": ([vp, vp, vp, vp, G, E, i64, vp, i32, vp], i32),
         "pct_trajectory_cost_bwd": ([vp, vp, vp, vp, vp, G, E, Rb, f32, vp, vp, i32, i32, vp, i64, vp, vp, i32,
                                      vp], i32),
+        "pct_fixed_to_float": ([vp, i64, vp, vp], i32),
+        "pct_autotune_batched": ([vp, i64, It, i32, Rb, C.POINTER(pct_tune_entry), i32, C.POINTER(i32), vp], i32),
+        "pct_autotune_save": ([C.c_char_p], i32),
+        "pct_autotune_load": ([C.c_char_p, C.POINTER(i32)], i32),
         "pct_trajectory_multi_workspace_bytes": ([i32], sz),
         "pct_trajectory_cost_multi": ([vp, vp, vp, vp, G, E, Rb, i32, f32, vp, vp, i32, i32, vp, vp, vp, vp, vp, i64, vp,
                                        i32, vp, sz, vp], i32),

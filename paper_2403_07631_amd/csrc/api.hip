@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -146,6 +147,36 @@ pct_status make_eval_params(const pct_robot& r, const pct_grid& g, int N, EvalPa
 }  // namespace pct
 
 namespace pct {
+
+void digest_params(Digest& d, const EvalParams& p) {
+    d.add(p.nx), d.add(p.ny), d.add(p.N), d.add(p.R), d.add(p.plane);
+    d.add(p.d_min), d.add(p.d_ref), d.add(p.cB), d.add(p.alpha_d), d.add(p.Tb), d.add(p.Ts2), d.add(p.As), d.add(p.Ab);
+    d.add(p.rp), d.add(p.kp), d.add(p.wx0), d.add(p.wy0), d.add(p.wx1), d.add(p.wy1);
+    for (int a = 0; a < kKmax; ++a)
+        for (int j = 0; j < kKmax; ++j) d.add(p.K[a][j]);
+}
+
+namespace {
+std::mutex g_res_mu;
+std::map<std::pair<const void*, int>, uint64_t> g_resident;
+}  // namespace
+
+pct_status resident_tables(const void* region, int kind, uint64_t digest, bool upload) {
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    const auto key = std::make_pair(region, kind);
+    if (upload) {
+        g_resident[key] = digest;
+        return PCT_OK;
+    }
+    auto it = g_resident.find(key);
+    if (it == g_resident.end())
+        return fail(PCT_ERR_ARG, "PCT_DESCRIPTORS_RESIDENT: no descriptor tables were uploaded to this workspace");
+    if (it->second != digest)
+        return fail(PCT_ERR_ARG, "PCT_DESCRIPTORS_RESIDENT: the workspace holds the tables of other items, robots or "
+                                 "tile shapes (tuning changed them?): call once without the flag to upload them");
+    return PCT_OK;
+}
+
 namespace {
 
 pct_status eval_traversability(const float* d_ground, const float* d_ceil, const pct_grid* grid,
@@ -205,6 +236,52 @@ pct_status static_scratch(hipStream_t s, void** out) {
         g_scratch_addr[dev] = ptr;
     }
     *out = g_scratch_addr[dev];
+    return PCT_OK;
+}
+
+}  // namespace
+}  // namespace pct
+
+namespace pct {
+namespace {
+
+// Mean time of `reps` calls of fn (after one untimed call) on stream s.
+template <class F>
+pct_status time_calls(F fn, hipStream_t s, int reps, float* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(PCT_ERR_DEVICE, "hipEventCreate failed");
+    }
+    pct_status st = fn(0);
+    if (st == PCT_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(PCT_ERR_DEVICE, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == PCT_OK; ++r) st = fn(PCT_DESCRIPTORS_RESIDENT);
+    if (st == PCT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+        st = fail(PCT_ERR_DEVICE, "timing the candidates failed");
+    if (st == PCT_OK) *ms /= (float)reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+// Device buffers of one size class's trial runs, released on scope exit.
+struct TrialBuffers {
+    void* p[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~TrialBuffers() {
+        for (void* q : p)
+            if (q) (void)hipFree(q);
+    }
+};
+
+pct_status current_arch(char* out, size_t n) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(PCT_ERR_DEVICE, "hipGetDeviceProperties failed");
+    snprintf(out, n, "%s", prop.gcnArchName);
+    for (char* c = out; *c; ++c)
+        if (*c == ' ') *c = '_';
     return PCT_OK;
 }
 
@@ -469,6 +546,7 @@ pct_status pct_autotune_set_traversability(const pct_grid* grid, const pct_exten
     return PCT_OK;
 }
 
+
 namespace {
 
 pct_status check_sampling(const pct_grid* grid, const pct_extent* extent, const pct_robot* robot, int32_t T, int32_t W,
@@ -510,7 +588,8 @@ pct_status pct_sample_cost_bwd(const float* d_cost, const float* d_ground, const
     if (st != PCT_OK) return st;
     if (!isfinite(w_z)) return fail(PCT_ERR_ARG, "w_z must be finite");
     hipStream_t s = (hipStream_t)stream;
-    const long long cells = (long long)extent->n_slices * grid->nx * grid->ny;
+    const bool fixed = flags & PCT_FIXED_POINT;
+    const long long cells = (long long)extent->n_slices * grid->nx * grid->ny * (fixed ? 2 : 1);
     if (!(flags & PCT_ACCUMULATE)) {
         st = launch_zero(d_gcost, cells, s);
         if (st != PCT_OK) return st;
@@ -521,7 +600,8 @@ pct_status pct_sample_cost_bwd(const float* d_cost, const float* d_ground, const
     if (!d_gf || !d_gwp) return fail(PCT_ERR_ARG, "d_gf and d_gwp are required");
     if (extent->n_slices > 0 && (!d_cost || !d_ground)) return fail(PCT_ERR_ARG, "grid pointers are null");
     return launch_sample_bwd(d_cost, d_ground, nullptr, *grid, extent->n_slices, h_robot->d_ref, w_z, d_wp, d_wp_slice,
-                             n_traj, n_wp, d_gf, d_gwp, d_gcost, d_gground, nullptr, nullptr, nullptr, nullptr, 0, s);
+                             n_traj, n_wp, d_gf, d_gwp, d_gcost, d_gground, nullptr, nullptr, nullptr, nullptr, 0, fixed,
+                             s);
 }
 
 pct_status pct_eval_traversability_bwd(const float* d_ground, const float* d_ceil, const pct_grid* grid,
@@ -541,13 +621,14 @@ pct_status pct_eval_traversability_bwd(const float* d_ground, const float* d_cei
     st = make_eval_params(*h_robot, *grid, N, &p);
     if (st != PCT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    const bool fixed = flags & PCT_FIXED_POINT;
     if (!(flags & PCT_ACCUMULATE)) {
-        st = launch_zero(d_gground, p.plane * N, s);
+        st = launch_zero(d_gground, p.plane * N * (fixed ? 2 : 1), s);
         if (st != PCT_OK) return st;
-        st = launch_zero(d_gceil, p.plane * N, s);
+        st = launch_zero(d_gceil, p.plane * N * (fixed ? 2 : 1), s);
         if (st != PCT_OK) return st;
     }
-    return launch_eval_bwd(d_ground, d_ceil, d_gcost, p, d_gground, d_gceil, s);
+    return launch_eval_bwd(d_ground, d_ceil, d_gcost, p, d_gground, d_gceil, fixed, s);
 }
 
 pct_status pct_route_grad_to_points(const float* d_gground, const float* d_gceil, const int32_t* d_arg_ground,
@@ -560,15 +641,16 @@ pct_status pct_route_grad_to_points(const float* d_gground, const float* d_gceil
     if (st != PCT_OK) return st;
     if (n_points < 0) return fail(PCT_ERR_ARG, "n_points must be >= 0");
     hipStream_t s = (hipStream_t)stream;
+    const bool fixed = flags & PCT_FIXED_POINT;
     if (!(flags & PCT_ACCUMULATE)) {
-        st = launch_zero(d_gz, n_points, s);
+        st = launch_zero(d_gz, n_points * (fixed ? 2 : 1), s);
         if (st != PCT_OK) return st;
     }
     if (extent->n_slices == 0 || n_points == 0) return PCT_OK;
     if (!d_gz || !d_gground || !d_arg_ground) return fail(PCT_ERR_ARG, "device pointers are null");
     if (d_gceil && !d_arg_ceil) return fail(PCT_ERR_ARG, "d_arg_ceil is required with d_gceil");
     return launch_route(d_gground, d_gceil, d_arg_ground, d_arg_ceil, (long long)grid->nx * grid->ny,
-                        extent->n_slices, n_points, d_gz, s);
+                        extent->n_slices, n_points, d_gz, fixed, s);
 }
 
 pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, const float* d_cost,
@@ -582,8 +664,9 @@ pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, c
     if (!isfinite(w_z)) return fail(PCT_ERR_ARG, "w_z must be finite");
     if (n_points < 0) return fail(PCT_ERR_ARG, "n_points must be >= 0");
     hipStream_t s = (hipStream_t)stream;
+    const bool fixed = flags & PCT_FIXED_POINT;
     if (!(flags & PCT_ACCUMULATE)) {
-        st = launch_zero(d_gz, n_points, s);
+        st = launch_zero(d_gz, n_points * (fixed ? 2 : 1), s);
         if (st != PCT_OK) return st;
     }
     const int N = extent->n_slices;
@@ -596,13 +679,17 @@ pct_status pct_trajectory_cost_bwd(const float* d_ground, const float* d_ceil, c
     if (st != PCT_OK) return st;
     p.N = N;
     return launch_sample_bwd(d_cost, d_ground, d_ceil, *grid, N, h_robot->d_ref, w_z, d_wp, d_wp_slice, n_traj, n_wp,
-                             d_gf, d_gwp, nullptr, nullptr, &p, d_arg_ground, d_arg_ceil, d_gz, n_points, s);
+                             d_gf, d_gwp, nullptr, nullptr, &p, d_arg_ground, d_arg_ceil, d_gz, n_points, fixed, s);
 }
 
 namespace {
 
 // Host table of device item descriptors (grids tiled, bases assigned).
-pct_status make_items(const pct_item* h, int n_items, int64_t n_total, bool need_extent, std::vector<BuildItemDev>* out) {
+// `tuned`: construction tiles as tall as the size class's tuned height when
+// that is taller than the default (so never more tiles than the default,
+// which sizes the workspace).
+pct_status make_items(const pct_item* h, int n_items, int64_t n_total, bool need_extent, std::vector<BuildItemDev>* out,
+                      bool tuned = false) {
     if (n_items < 1 || !h) return fail(PCT_ERR_ARG, "a batch needs at least one item");
     out->resize(n_items);
     int tile_base = 0, chunk_base = 0, echunk_base = 0;
@@ -619,6 +706,14 @@ pct_status make_items(const pct_item* h, int n_items, int64_t n_total, bool need
         if (n_total > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count outside [0, 2^31)");
         BuildItemDev& d = (*out)[i];
         d.g = make_grid_dev(h[i].grid);
+        if (tuned) {
+            const int th = batch_build_th(size_class(h[i].grid.nx), size_class(h[i].grid.ny));
+            if (th > d.g.th) {
+                d.g.th = th;
+                d.g.nty = (d.g.ny + th - 1) / th;
+                d.g.ntiles = d.g.ntx * d.g.nty;
+            }
+        }
         d.xyz_off = h[i].xyz_offset;
         d.n = h[i].n_points;
         if (need_extent) {
@@ -724,7 +819,7 @@ pct_status pct_build_tomogram_batched(const float* d_xyz, int64_t n_total, const
                                       int32_t flags, void* d_ws, size_t ws_bytes, void* stream) {
     clear_error();
     std::vector<BuildItemDev> it;
-    pct_status st = make_items(h_items, n_items, n_total, true, &it);
+    pct_status st = make_items(h_items, n_items, n_total, true, &it, true);
     if (st != PCT_OK) return st;
     if ((d_arg_ground == nullptr) != (d_arg_ceil == nullptr))
         return fail(PCT_ERR_ARG, "d_arg_ground and d_arg_ceil must both be given or both be null");
@@ -759,6 +854,146 @@ pct_status pct_eval_traversability_batched(const float* d_ground, const float* d
     return launch_eval_batched(d_ground, d_ceil, h_items, n_items, h_robots, n_robots, d_cost, d_keep,
                                (char*)d_ws + eval_off, ws_bytes - eval_off, !(flags & PCT_DESCRIPTORS_RESIDENT),
                                (hipStream_t)stream);
+}
+
+pct_status pct_autotune_batched(const float* d_xyz, int64_t n_total, const pct_item* h_items, int32_t n_items,
+                                const pct_robot* h_robot, pct_tune_entry* h_out, int32_t n_max, int32_t* h_count,
+                                void* stream) {
+    clear_error();
+    std::vector<BuildItemDev> it;
+    pct_status st = make_items(h_items, n_items, n_total, true, &it);
+    if (st != PCT_OK) return st;
+    if (!h_robot) return fail(PCT_ERR_ARG, "h_robot is null");
+    for (int i = 0; i < n_items; ++i) {
+        st = check_robot(h_robot, h_items[i].grid.res);
+        if (st != PCT_OK) return st;
+    }
+    if (n_total > 0 && !d_xyz) return fail(PCT_ERR_ARG, "d_xyz is null");
+    if (n_max < 0 || (n_max > 0 && !h_out) || !h_count) return fail(PCT_ERR_ARG, "bad report arguments");
+    *h_count = 0;
+    hipStream_t s = (hipStream_t)stream;
+    // the items with slices, by (class x, class y, R)
+    std::map<std::vector<int>, std::vector<int>> groups;
+    for (int i = 0; i < n_items; ++i) {
+        if (h_items[i].extent.n_slices <= 0) continue;
+        EvalParams p;
+        st = make_eval_params(*h_robot, h_items[i].grid, h_items[i].extent.n_slices, &p);
+        if (st != PCT_OK) return st;
+        groups[{size_class(h_items[i].grid.nx), size_class(h_items[i].grid.ny), p.R}].push_back(i);
+    }
+    std::vector<pct_tune_entry> rep;
+    std::map<std::pair<int, int>, bool> built;
+    for (const auto& gkv : groups) {
+        const int cx = gkv.first[0], cy = gkv.first[1], R = gkv.first[2];
+        std::vector<pct_item> sub;
+        long long cells = 0, slices = 0;
+        for (int i : gkv.second) {
+            pct_item t = h_items[i];
+            t.out_offset = cells;
+            t.keep_offset = slices;
+            cells += (long long)t.extent.n_slices * t.grid.nx * t.grid.ny;
+            slices += t.extent.n_slices;
+            sub.push_back(t);
+        }
+        const int ns = (int)sub.size();
+        const size_t ws_bytes = pct_batch_workspace_bytes(sub.data(), ns, 1, 0);
+        if (ws_bytes == 0) return fail(PCT_ERR_ARG, "sizing the trial workspace failed");
+        TrialBuffers tb;
+        if (hipMalloc(&tb.p[0], sizeof(float) * cells) != hipSuccess ||
+            hipMalloc(&tb.p[1], sizeof(float) * cells) != hipSuccess ||
+            hipMalloc(&tb.p[2], sizeof(float) * cells) != hipSuccess || hipMalloc(&tb.p[3], ws_bytes) != hipSuccess)
+            return fail(PCT_ERR_DEVICE, "allocating the trial buffers failed");
+        float* G = (float*)tb.p[0];
+        float* Cc = (float*)tb.p[1];
+        float* cost = (float*)tb.p[2];
+        void* ws = tb.p[3];
+        auto build = [&](int flags) {
+            return pct_build_tomogram_batched(d_xyz, n_total, sub.data(), ns, G, Cc, nullptr, nullptr, flags, ws,
+                                              ws_bytes, s);
+        };
+        const int n_before = (int)rep.size();
+        // construction tile height, once per (class x, class y)
+        if (!built[{cx, cy}]) {
+            built[{cx, cy}] = true;
+            int th_min = 2;
+            for (const pct_item& t : sub) th_min = std::max(th_min, make_grid_dev(t.grid).th);
+            const int old = batch_build_th(cx, cy);
+            float best = INFINITY;
+            int best_th = 0;
+            for (int th = th_min; th <= 8; th *= 2) {
+                set_batch_build_th(cx, cy, th);
+                float ms = 0.0f;
+                st = time_calls(build, s, 3, &ms);
+                if (st != PCT_OK) {
+                    set_batch_build_th(cx, cy, old);
+                    return st;
+                }
+                rep.push_back(pct_tune_entry{0, cx, cy, -1, th, 0, ns, 0, ms});
+                if (ms < best) best = ms, best_th = th;
+            }
+            set_batch_build_th(cx, cy, best_th == th_min ? 0 : best_th);
+            for (size_t k = n_before; k < rep.size(); ++k) rep[k].chosen = rep[k].rows == best_th;
+        }
+        st = build(0);
+        if (st != PCT_OK) return st;
+        // evaluation strip shape
+        auto eval = [&](int flags) {
+            return pct_eval_traversability_batched(G, Cc, sub.data(), ns, h_robot, 1, cost, nullptr, flags, ws,
+                                                   ws_bytes, s);
+        };
+        EvalParams p0;
+        const EvalShape old = batch_eval_shape(cx, cy, R);
+        const EvalShape shapes[] = {{0, 0},  {32, 1},  {64, 1},  {128, 1}, {256, 1},
+                                    {32, 4}, {64, 4},  {128, 4}, {256, 4}};
+        const size_t e_before = rep.size();
+        float best = INFINITY;
+        EvalShape best_sh{0, 0};
+        for (const EvalShape& sh : shapes) {
+            bool fits = true;
+            for (const pct_item& t : sub) {
+                st = make_eval_params(*h_robot, t.grid, t.extent.n_slices, &p0);
+                if (st != PCT_OK) return st;
+                if (sh.rows > 0 && !strip_shape_fits(p0, sh)) fits = false;
+            }
+            if (!fits) continue;
+            set_batch_eval_shape(cx, cy, R, sh);
+            float ms = 0.0f;
+            st = time_calls(eval, s, 3, &ms);
+            if (st != PCT_OK) {
+                set_batch_eval_shape(cx, cy, R, old);
+                return st;
+            }
+            rep.push_back(pct_tune_entry{1, cx, cy, R, sh.rows, sh.nw, ns, 0, ms});
+            if (ms < best) best = ms, best_sh = sh;
+        }
+        set_batch_eval_shape(cx, cy, R, best_sh);
+        for (size_t k = e_before; k < rep.size(); ++k)
+            rep[k].chosen = rep[k].rows == best_sh.rows && rep[k].waves == best_sh.nw;
+    }
+    for (int k = 0; k < (int)rep.size() && k < n_max; ++k) h_out[k] = rep[k];
+    *h_count = (int32_t)rep.size();
+    return PCT_OK;
+}
+
+pct_status pct_autotune_save(const char* path) {
+    clear_error();
+    if (!path) return fail(PCT_ERR_ARG, "path is null");
+    char arch[256];
+    pct_status st = current_arch(arch, sizeof arch);
+    if (st != PCT_OK) return st;
+    return tune_save(path, arch);
+}
+
+pct_status pct_autotune_load(const char* path, int32_t* n_applied) {
+    clear_error();
+    if (!path) return fail(PCT_ERR_ARG, "path is null");
+    char arch[256];
+    pct_status st = current_arch(arch, sizeof arch);
+    if (st != PCT_OK) return st;
+    int n = 0;
+    st = tune_load(path, arch, &n);
+    if (st == PCT_OK && n_applied) *n_applied = n;
+    return st;
 }
 
 size_t pct_trajectory_multi_workspace_bytes(int32_t n_profiles) {
@@ -796,14 +1031,19 @@ pct_status pct_trajectory_cost_multi(const float* d_ground, const float* d_ceil,
         ps[i].N = N;
     }
     hipStream_t s = (hipStream_t)stream;
+    const bool fixed = flags & PCT_FIXED_POINT;
+    const int words = fixed ? 2 : 1;
     if (d_gf && !(flags & PCT_ACCUMULATE)) {
         const long long cells = (long long)N * grid->nx * grid->ny;
-        pct_status st = launch_zero(d_gground, cells, s);
-        if (st == PCT_OK) st = launch_zero(d_gceil, cells, s);
-        if (st == PCT_OK) st = launch_zero(d_gz, d_gz ? n_points : 0, s);
+        pct_status st = launch_zero(d_gground, cells * words, s);
+        if (st == PCT_OK) st = launch_zero(d_gceil, cells * words, s);
+        if (st == PCT_OK) st = launch_zero(d_gz, d_gz ? n_points * words : 0, s);
         if (st != PCT_OK) return st;
     }
     EvalParams* d_ps = (EvalParams*)d_ws;
+    Digest dg;
+    for (const EvalParams& p : ps) digest_params(dg, p);
+    if (pct_status st = resident_tables(d_ps, 2, dg.h, !(flags & PCT_DESCRIPTORS_RESIDENT))) return st;
     if (!(flags & PCT_DESCRIPTORS_RESIDENT)) {
         // ps is released on return: wait until the copy has read it
         PCT_HIP(hipMemcpyAsync(d_ps, ps.data(), sizeof(EvalParams) * n_profiles, hipMemcpyHostToDevice, s));
@@ -814,7 +1054,19 @@ pct_status pct_trajectory_cost_multi(const float* d_ground, const float* d_ceil,
         return PCT_OK;
     }
     return launch_traj_value_grad(d_ground, d_ceil, d_arg_ground, d_arg_ceil, *grid, N, d_ps, n_profiles, w_z, d_wp,
-                                  d_wp_slice, n_traj, n_wp, d_gf, d_f, d_gwp, d_gground, d_gceil, d_gz, n_points, s);
+                                  d_wp_slice, n_traj, n_wp, d_gf, d_f, d_gwp, d_gground, d_gceil, d_gz, n_points,
+                                  fixed, s);
+}
+
+pct_status pct_fixed_to_float(const int64_t* d_acc, int64_t n, float* d_out, void* stream) {
+    clear_error();
+    if (n < 0) return fail(PCT_ERR_ARG, "n must be >= 0");
+    if (n == 0) return PCT_OK;
+    if (!d_acc || !d_out) return fail(PCT_ERR_ARG, "device pointers are null");
+    const char* a = (const char*)d_acc;
+    const char* o = (const char*)d_out;
+    if (o < a + 8 * n && a < o + 4 * n) return fail(PCT_ERR_ARG, "d_out overlaps d_acc");
+    return launch_fixed_to_float(d_acc, n, d_out, (hipStream_t)stream);
 }
 
 size_t pct_plan_workspace_bytes(int32_t nx, int32_t ny, int32_t n_layers) {

@@ -1392,6 +1392,14 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
     const bool ids = ag != nullptr;
     BatchWs w = carve_batch_ws(ws, h_items, n_items, ids);
     if (w.bytes > ws_bytes) return fail(PCT_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", ws_bytes, w.bytes);
+    Digest dg;
+    for (int i = 0; i < n_items; ++i) {
+        const BuildItemDev& d = h_items[i];
+        dg.add(d.g.x0), dg.add(d.g.y0), dg.add(d.g.res), dg.add(d.g.nx), dg.add(d.g.ny), dg.add(d.g.th);
+        dg.add(d.g.ntiles), dg.add(d.xyz_off), dg.add(d.n), dg.add(d.zmin), dg.add(d.ds), dg.add(d.N);
+        dg.add(d.out_off), dg.add(d.tile_base), dg.add(d.chunk_base), dg.add(d.echunk_base);
+    }
+    if (pct_status st = resident_tables(w.items, 0, dg.h, upload != 0)) return st;
     if (upload) {
         // the table lives in pageable host memory that the caller releases
         // on return: wait until the copy has read it

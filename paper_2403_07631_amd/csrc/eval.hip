@@ -9,6 +9,9 @@
 //   c^T(x, y) = max_a max(V_a(x-a, y), V_a(x+a, y))             (row pass)
 // Each product K * c is the same FP32 multiply as in the direct 2-D window
 // and max is exact, so the result equals the direct FP32 window max.
+#include <stdio.h>
+#include <string.h>
+
 #include <map>
 #include <mutex>
 #include <vector>
@@ -456,6 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restr
     const int j = __builtin_amdgcn_readfirstlane(find_job_block(jobs, n_jobs, b));
     const EvalJob& jb = jobs[j];
     if (jb.sg.nw > 1) {
+        if (b - jb.block_base >= jb.n_blocks) return;
         eval_strip_item<R, Q1, Q0, kDefaultWaves>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off,
                                                   jb.sg, b - jb.block_base, lds);
     } else {
@@ -965,9 +969,133 @@ pct_status autotune_eval(const float* ground, const float* ceil, const EvalParam
     return PCT_OK;
 }
 
+// Batch tables, per size class (ceil(log2 nx), ceil(log2 ny)): the
+// evaluation's strip shape (and kernel radius) and the construction's tile
+// height.
+struct ClassKey {
+    int cx, cy, R;
+    bool operator<(const ClassKey& o) const {
+        return cx != o.cx ? cx < o.cx : cy != o.cy ? cy < o.cy : R < o.R;
+    }
+};
+std::map<ClassKey, EvalShape> g_batch_eval;
+std::map<ClassKey, int> g_batch_build;   // R = -1
+
+int size_class(int v) {
+    int c = 0;
+    while (c < 31 && (1 << c) < v) ++c;
+    return c;
+}
+
+EvalShape batch_eval_shape(int cx, int cy, int R) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_batch_eval.find(ClassKey{cx, cy, R});
+    return it == g_batch_eval.end() ? EvalShape{0, 0} : it->second;
+}
+
+void set_batch_eval_shape(int cx, int cy, int R, EvalShape shape) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (shape.rows > 0) g_batch_eval[ClassKey{cx, cy, R}] = shape;
+    else g_batch_eval.erase(ClassKey{cx, cy, R});
+}
+
+int batch_build_th(int cx, int cy) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_batch_build.find(ClassKey{cx, cy, -1});
+    return it == g_batch_build.end() ? 0 : it->second;
+}
+
+void set_batch_build_th(int cx, int cy, int th) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (th > 0) g_batch_build[ClassKey{cx, cy, -1}] = th;
+    else g_batch_build.erase(ClassKey{cx, cy, -1});
+}
+
 void autotune_reset() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+    g_batch_eval.clear();
+    g_batch_build.clear();
+}
+
+// Text form of the tables, one record a line, for the current device's
+// architecture `arch`:
+//   <arch> map <nx> <ny> <N> <R> <rows> <waves>
+//   <arch> batch_eval <cx> <cy> <R> <rows> <waves>
+//   <arch> batch_build <cx> <cy> <th>
+// Lines starting with '#' are comments.
+pct_status tune_save(const char* path, const char* arch) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE* fp = fopen(path, "w");
+    if (!fp) return fail(PCT_ERR_ARG, "cannot write %s", path);
+    fprintf(fp, "# libpct tuning tables v1\n");
+    for (const auto& kv : g_tune)
+        fprintf(fp, "%s map %d %d %d %d %d %d\n", arch, kv.first.nx, kv.first.ny, kv.first.N, kv.first.R,
+                kv.second.rows, kv.second.nw);
+    for (const auto& kv : g_batch_eval)
+        fprintf(fp, "%s batch_eval %d %d %d %d %d\n", arch, kv.first.cx, kv.first.cy, kv.first.R, kv.second.rows,
+                kv.second.nw);
+    for (const auto& kv : g_batch_build)
+        fprintf(fp, "%s batch_build %d %d %d\n", arch, kv.first.cx, kv.first.cy, kv.second);
+    const bool bad = ferror(fp) != 0;
+    if (fclose(fp) != 0 || bad) return fail(PCT_ERR_ARG, "writing %s failed", path);
+    return PCT_OK;
+}
+
+pct_status tune_load(const char* path, const char* arch, int* n_applied) {
+    FILE* fp = fopen(path, "r");
+    if (!fp) return fail(PCT_ERR_ARG, "cannot read %s", path);
+    std::map<TuneKey, EvalShape> m;
+    std::map<ClassKey, EvalShape> be;
+    std::map<ClassKey, int> bb;
+    char line[512];
+    int ln = 0;
+    pct_status st = PCT_OK;
+    while (fgets(line, sizeof line, fp)) {
+        ++ln;
+        char a[256], kind[32];
+        int v[6], used = 0;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        if (sscanf(line, "%255s %31s%n", a, kind, &used) != 2) { st = fail(PCT_ERR_ARG, "%s:%d: malformed", path, ln); break; }
+        const char* rest = line + used;
+        const bool mine = strcmp(a, arch) == 0;
+        if (strcmp(kind, "map") == 0) {
+            if (sscanf(rest, "%d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 6 || v[0] < 1 ||
+                v[1] < 1 || v[0] > PCT_MAX_GRID_SIDE || v[1] > PCT_MAX_GRID_SIDE || v[2] < 1 || v[2] > PCT_MAX_SLICES ||
+                v[3] < 0 || v[3] > PCT_MAX_KERNEL_RADIUS || v[4] < 16 || v[4] > PCT_MAX_STRIP_ROWS ||
+                (v[5] != 1 && v[5] != 2 && v[5] != 4)) {
+                st = fail(PCT_ERR_ARG, "%s:%d: bad map record", path, ln);
+                break;
+            }
+            if (mine) m[TuneKey{v[0], v[1], v[2], v[3]}] = EvalShape{v[4], v[5]};
+        } else if (strcmp(kind, "batch_eval") == 0) {
+            if (sscanf(rest, "%d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4]) != 5 || v[0] < 0 || v[0] > 16 ||
+                v[1] < 0 || v[1] > 16 || v[2] < 0 || v[2] > PCT_MAX_KERNEL_RADIUS || v[3] < 16 ||
+                v[3] > PCT_MAX_STRIP_ROWS || (v[4] != 1 && v[4] != 4)) {
+                st = fail(PCT_ERR_ARG, "%s:%d: bad batch_eval record", path, ln);
+                break;
+            }
+            if (mine) be[ClassKey{v[0], v[1], v[2]}] = EvalShape{v[3], v[4]};
+        } else if (strcmp(kind, "batch_build") == 0) {
+            if (sscanf(rest, "%d %d %d", &v[0], &v[1], &v[2]) != 3 || v[0] < 0 || v[0] > 16 || v[1] < 0 || v[1] > 16 ||
+                (v[2] != 2 && v[2] != 4 && v[2] != 8)) {
+                st = fail(PCT_ERR_ARG, "%s:%d: bad batch_build record", path, ln);
+                break;
+            }
+            if (mine) bb[ClassKey{v[0], v[1], -1}] = v[2];
+        } else {
+            st = fail(PCT_ERR_ARG, "%s:%d: unknown record '%s'", path, ln, kind);
+            break;
+        }
+    }
+    fclose(fp);
+    if (st != PCT_OK) return st;   // nothing applied
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : m) g_tune[kv.first] = kv.second;
+    for (const auto& kv : be) g_batch_eval[kv.first] = kv.second;
+    for (const auto& kv : bb) g_batch_build[kv.first] = kv.second;
+    if (n_applied) *n_applied = (int)(m.size() + be.size() + bb.size());
+    return PCT_OK;
 }
 
 bool strip_shape_fits(const EvalParams& p, EvalShape shape) {
@@ -1079,7 +1207,9 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
             EvalJob jb{};
             pct_status st = make_eval_params(robots[r], items[i].grid, N, &jb.p);
             if (st != PCT_OK) return st;
-            jb.sg = strip_geom(jb.p, EvalShape{0, 0}, false);   // blocks of kBlock threads: 1 or 4 wavefronts
+            // blocks of kBlock threads: 1 or 4 wavefronts; the size class's
+            // tuned shape if one is recorded
+            jb.sg = strip_geom(jb.p, batch_eval_shape(size_class(jb.p.nx), size_class(jb.p.ny), jb.p.R), false);
             jb.in_off = items[i].out_offset;
             jb.out_off = (long long)r * total_cells + items[i].out_offset;
             jb.keep_off = (long long)r * total_slices + items[i].keep_offset;
@@ -1135,6 +1265,15 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
     if (!ws || ws_bytes < need) return fail(PCT_ERR_WORKSPACE, "batch eval workspace too small: %zu < %zu", ws_bytes, need);
     EvalJob* d_jobs = (EvalJob*)ws;
     char* scratch = (char*)ws + align_up(sizeof(EvalJob) * n_jobs);
+    Digest dg;
+    for (const EvalJob& jb : jp.jobs) {
+        digest_params(dg, jb.p);
+        dg.add(jb.sg.rows), dg.add(jb.sg.n_sx), dg.add(jb.sg.n_sy), dg.add(jb.sg.n_work), dg.add(jb.sg.nw);
+        dg.add(jb.in_off), dg.add(jb.out_off), dg.add(jb.keep_off), dg.add(jb.cell_base), dg.add(jb.ws_off);
+        dg.add(jb.block_base), dg.add(jb.n_blocks);
+    }
+    st = resident_tables(ws, 1, dg.h, upload != 0);
+    if (st != PCT_OK) return st;
     if (upload) {
         // jp.jobs is released on return: wait until the copy has read it
         PCT_HIP(hipMemcpyAsync(d_jobs, jp.jobs.data(), sizeof(EvalJob) * n_jobs, hipMemcpyHostToDevice, s));

@@ -16,7 +16,12 @@
 // ground/ceiling gradient to the z of the point that holds the value.  The
 // maximising tap is found by recomputing c^init with the same FP32
 // operation sequence as the forward kernels, so it reproduces the forward
-// maximum exactly.  Gradient sums use float atomics.
+// maximum exactly.
+//
+// Gradient sums: float atomics by default, whose result depends on the
+// order in which the additions land; with PCT_FIXED_POINT, 64-bit integer
+// atomics on contributions rounded to multiples of 2^-32, whose sum does
+// not depend on that order (nor on how the work is split into launches).
 #include "pct_internal.h"
 
 namespace pct {
@@ -94,6 +99,22 @@ __device__ Cinit cinit_at(const float* __restrict__ gk, const float* __restrict_
     return o;
 }
 
+// A contribution in fixed point: v * 2^32 rounded to the nearest integer
+// (ties to even), clamped to +-2^62 so that the conversion is defined; NaN
+// adds nothing.
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+    const float q = rintf(v * 0x1p32f);
+    if (!(q == q)) return 0ull;
+    return (unsigned long long)(long long)fminf(fmaxf(q, -0x1p62f), 0x1p62f);
+}
+
+// Gradient sum: a float array, or with `fixed` an int64 array of 2^-32 units
+// (two's complement, so integer addition wraps to the signed sum).
+__device__ __forceinline__ void grad_add(float* p, long long i, float v, bool fixed) {
+    if (fixed) atomicAdd((unsigned long long*)p + i, to_fixed(v));
+    else atomicAdd(p + i, v);
+}
+
 // Gradient sink: dense grids (nullable) and/or point heights via the ids.
 struct Sink {
     float* gG;          // [N][ny][nx] or null
@@ -102,22 +123,23 @@ struct Sink {
     const int* aC;
     float* gz;
     long long n_points;
+    int fixed;          // the sums are int64 fixed point (gG, gC, gz)
 };
 
 __device__ __forceinline__ void add_ground(const Sink& s, long long i, float v) {
     if (v == 0.0f) return;
-    if (s.gG) atomicAdd(&s.gG[i], v);
+    if (s.gG) grad_add(s.gG, i, v, s.fixed);
     if (s.gz) {
         const int id = s.aG[i];
-        if (id >= 0 && id < s.n_points) atomicAdd(&s.gz[id], v);
+        if (id >= 0 && id < s.n_points) grad_add(s.gz, id, v, s.fixed);
     }
 }
 __device__ __forceinline__ void add_ceil(const Sink& s, long long i, float v) {
     if (v == 0.0f) return;
-    if (s.gC) atomicAdd(&s.gC[i], v);
+    if (s.gC) grad_add(s.gC, i, v, s.fixed);
     if (s.gz) {
         const int id = s.aC[i];
-        if (id >= 0 && id < s.n_points) atomicAdd(&s.gz[id], v);
+        if (id >= 0 && id < s.n_points) grad_add(s.gz, id, v, s.fixed);
     }
 }
 
@@ -432,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_bwd(const float* __restrict__
         }
         for (int c = 0; c < 4; ++c) {
             const float gc = g * ws[c];
-            if (gcost && gc != 0.0f) atomicAdd(&gcost[cs[c]], gc);
+            if (gcost && gc != 0.0f) grad_add(gcost, cs[c], gc, s.fixed);
             if (eval && gc != 0.0f) {
                 const long long local = cs[c] - (long long)k * a.plane;
                 eval_adjoint_cell(ground, ceil, k, (int)(local % a.nx), (int)(local / a.nx), gc, ep, s);
@@ -462,7 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_bwd(const float* __restrict__ g
 // values held by the same point in one atomic.
 __global__ __launch_bounds__(kBlock) void k_route(const float* __restrict__ gG, const float* __restrict__ gC,
                                                   const int* __restrict__ aG, const int* __restrict__ aC,
-                                                  long long plane, int N, long long n_points, float* __restrict__ gz) {
+                                                  long long plane, int N, long long n_points, float* __restrict__ gz,
+                                                  int fixed) {
     const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (c >= plane) return;
     for (int which = 0; which < 2; ++which) {
@@ -475,14 +498,21 @@ __global__ __launch_bounds__(kBlock) void k_route(const float* __restrict__ gG, 
             const long long i = (long long)k * plane + c;
             const int id = a[i];
             if (id != cur) {
-                if (cur >= 0 && cur < n_points && acc != 0.0f) atomicAdd(&gz[cur], acc);
+                if (cur >= 0 && cur < n_points && acc != 0.0f) grad_add(gz, cur, acc, fixed);
                 cur = id;
                 acc = 0.0f;
             }
             acc += g[i];
         }
-        if (cur >= 0 && cur < n_points && acc != 0.0f) atomicAdd(&gz[cur], acc);
+        if (cur >= 0 && cur < n_points && acc != 0.0f) grad_add(gz, cur, acc, fixed);
     }
+}
+
+// Fixed-point sums to float32: the integer correctly rounded, times 2^-32.
+__global__ __launch_bounds__(kBlock) void k_fixed_to_float(const long long* __restrict__ q, long long n,
+                                                           float* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = (float)q[i] * 0x1p-32f;
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(float* __restrict__ p, long long n) {
@@ -616,9 +646,10 @@ pct_status launch_sample_fwd(const float* cost, const float* ground, const pct_g
 pct_status launch_sample_bwd(const float* cost, const float* ground, const float* ceil, const pct_grid& g, int N,
                              float d_ref, float w_z, const float* wp, const int* slice, int T, int W, const float* gf,
                              float* gwp, float* gcost, float* gground, const EvalParams* ep, const int* aG,
-                             const int* aC, float* gz, long long n_points, hipStream_t s) {
+                             const int* aC, float* gz, long long n_points, bool fixed, hipStream_t s) {
     const SampleArgs a = make_sample_args(g, N, d_ref, w_z, T, W);
     Sink sk{};
+    sk.fixed = fixed;
     sk.gG = gground;
     sk.gC = nullptr;
     sk.aG = aG;
@@ -635,8 +666,9 @@ pct_status launch_sample_bwd(const float* cost, const float* ground, const float
 }
 
 pct_status launch_eval_bwd(const float* ground, const float* ceil, const float* gcost, const EvalParams& p,
-                           float* gground, float* gceil, hipStream_t s) {
+                           float* gground, float* gceil, bool fixed, hipStream_t s) {
     Sink sk{};
+    sk.fixed = fixed;
     sk.gG = gground;
     sk.gC = gceil;
     hipLaunchKernelGGL(k_eval_bwd, dim3(grid_for(p.plane * p.N)), dim3(kBlock), 0, s, ground, ceil, gcost, p, sk);
@@ -645,9 +677,16 @@ pct_status launch_eval_bwd(const float* ground, const float* ceil, const float* 
 }
 
 pct_status launch_route(const float* gG, const float* gC, const int* aG, const int* aC, long long plane, int N,
-                        long long n_points, float* gz, hipStream_t s) {
+                        long long n_points, float* gz, bool fixed, hipStream_t s) {
     hipLaunchKernelGGL(k_route, dim3((unsigned)((plane + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, gG, gC, aG, aC,
-                       plane, N, n_points, gz);
+                       plane, N, n_points, gz, fixed ? 1 : 0);
+    PCT_LAUNCH_CHECK();
+    return PCT_OK;
+}
+
+pct_status launch_fixed_to_float(const int64_t* q, long long n, float* out, hipStream_t s) {
+    if (n <= 0) return PCT_OK;
+    hipLaunchKernelGGL(k_fixed_to_float, dim3(grid_for(n)), dim3(kBlock), 0, s, (const long long*)q, n, out);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -656,9 +695,10 @@ pct_status launch_traj_value_grad(const float* ground, const float* ceil, const 
                                   const pct_grid& g, int N, const EvalParams* d_robots, int n_profiles, float w_z,
                                   const float* wp, const int* slice, int T, int W, const float* gf, float* f,
                                   float* gwp, float* gground, float* gceil, float* gz, long long n_points,
-                                  hipStream_t s) {
+                                  bool fixed, hipStream_t s) {
     const SampleArgs a = make_sample_args(g, N, 0.0f, w_z, T, W);
     Sink sk{};
+    sk.fixed = fixed;
     if (gf) {
         sk.gG = gground;
         sk.gC = gceil;

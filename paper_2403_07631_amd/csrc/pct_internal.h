@@ -138,6 +138,32 @@ void autotune_set(const EvalParams& p, EvalShape shape);
 bool strip_shape_fits(const EvalParams& p, EvalShape shape);
 pct_status launch_eval_simplify(const float* ground, const float* ceil, const EvalParams& p, float* cost, uint8_t* keep,
                                 void* ws, size_t ws_bytes, hipStream_t s);
+
+// Batch tuning tables, per size class (ceil(log2 nx), ceil(log2 ny)): the
+// evaluation's strip shape for a kernel radius ({0, 0}: default) and the
+// construction's tile height (0: default).  Saved and loaded as text with the
+// single-map table, for one device architecture.
+int size_class(int v);
+EvalShape batch_eval_shape(int cx, int cy, int R);
+void set_batch_eval_shape(int cx, int cy, int R, EvalShape shape);
+int batch_build_th(int cx, int cy);
+void set_batch_build_th(int cx, int cy, int th);
+pct_status tune_save(const char* path, const char* arch);
+pct_status tune_load(const char* path, const char* arch, int* n_applied);
+
+// Descriptor tables kept in a workspace region for PCT_DESCRIPTORS_RESIDENT
+// calls: an upload records a digest of the host plan (kind: which table);
+// a resident call fails unless its own plan has the recorded digest.
+struct Digest {
+    uint64_t h = 1469598103934665603ull;
+    template <class T>
+    void add(const T& v) {
+        const unsigned char* b = (const unsigned char*)&v;
+        for (size_t i = 0; i < sizeof(T); ++i) h = (h ^ b[i]) * 1099511628211ull;
+    }
+};
+void digest_params(Digest& d, const EvalParams& p);
+pct_status resident_tables(const void* region, int kind, uint64_t digest, bool upload);
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
                            void* ws, hipStream_t s);
 
@@ -160,15 +186,16 @@ pct_status launch_sample_fwd(const float* cost, const float* ground, const pct_g
 pct_status launch_sample_bwd(const float* cost, const float* ground, const float* ceil, const pct_grid& g, int N,
                              float d_ref, float w_z, const float* wp, const int* slice, int T, int W, const float* gf,
                              float* gwp, float* gcost, float* gground, const EvalParams* ep, const int* aG,
-                             const int* aC, float* gz, long long n_points, hipStream_t s);
+                             const int* aC, float* gz, long long n_points, bool fixed, hipStream_t s);
 pct_status launch_eval_bwd(const float* ground, const float* ceil, const float* gcost, const EvalParams& p,
-                           float* gground, float* gceil, hipStream_t s);
+                           float* gground, float* gceil, bool fixed, hipStream_t s);
 pct_status launch_traj_value_grad(const float* ground, const float* ceil, const int* aG, const int* aC,
                                   const pct_grid& g, int N, const EvalParams* d_robots, int n_profiles, float w_z,
                                   const float* wp, const int* slice, int T, int W, const float* gf, float* f,
                                   float* gwp, float* gground, float* gceil, float* gz, long long n_points,
-                                  hipStream_t s);
+                                  bool fixed, hipStream_t s);
 pct_status launch_route(const float* gG, const float* gC, const int* aG, const int* aC, long long plane, int N,
-                        long long n_points, float* gz, hipStream_t s);
+                        long long n_points, float* gz, bool fixed, hipStream_t s);
+pct_status launch_fixed_to_float(const int64_t* q, long long n, float* out, hipStream_t s);
 
 }  // namespace pct

@@ -515,6 +515,84 @@ def case_batch_mixed_radius():
     check_batch(items, pts, specs, [robot(), robot(d_inf=0.5, d_sm=0.7)], False)
 
 
+def case_batch_tune():
+    """The size-class tuner: every class gets one choice per stage, and
+    batched outputs after tuning (and after loading other shapes) equal
+    those before; resident tables of other shapes are refused; the tables
+    survive a save and load, and a malformed file applies nothing."""
+    import tempfile
+    items_sc, pts, specs = make_batch(64, 5, side_hi=90, pts_hi=25_000, extra_empty=True)
+    rb = robot()
+    L.pct_autotune_reset()
+    _, before = batch_run(pts, specs, [rb], True)
+    items, _ = batch_run(pts, specs, [rb], False)      # items with extents
+    xb = Buf.of(pts)
+    n_items = len(specs)
+    ent = (abi.pct_tune_entry * 256)()
+    cnt = C.c_int32()
+    rs = (abi.pct_robot * 1)(robot_s(rb))
+    check("autotune_batched", L.pct_autotune_batched(P(xb), len(pts), items, n_items, rs, ent, 256, C.byref(cnt),
+                                                     None))
+    es = list(ent[:cnt.value])
+    classes = {(e.stage, e.class_x, e.class_y, e.radius) for e in es}
+    assert cnt.value >= 2 * 3 and len(classes) >= 2
+    for c in classes:
+        assert sum(e.chosen for e in es if (e.stage, e.class_x, e.class_y, e.radius) == c) == 1, c
+        assert all(e.ms > 0 for e in es if (e.stage, e.class_x, e.class_y, e.radius) == c)
+    _, after = batch_run(pts, specs, [rb], True)
+    for k in before:
+        np.testing.assert_array_equal(bits(after[k]), bits(before[k]), err_msg=k)
+    say(f"batch tuner: {cnt.value} timings over {len(classes)} (stage, class) pairs, outputs unchanged")
+    # shapes unlike the defaults for every class, through a file
+    tmp = tempfile.mkdtemp()
+    path = os.path.join(tmp, "tune.txt")
+    lines = ["# shapes for the test"]
+    chosen = {(e.stage, e.class_x, e.class_y, e.radius): (e.rows, e.waves) for e in es if e.chosen}
+    for st_, cx, cy, R in sorted(classes):
+        ch = chosen[(st_, cx, cy, R)]
+        if st_ == 0:
+            lines.append(f"cpu-emulator batch_build {cx} {cy} {4 if ch[0] == 8 else 8}")
+        else:
+            lines.append(f"cpu-emulator batch_eval {cx} {cy} {R} {64 if ch == (32, 1) else 32} 1")
+    lines.append("otherarch batch_build 1 1 4")
+    with open(path, "w") as fp:
+        fp.write("\n".join(lines) + "\n")
+    ws = Buf(L.pct_batch_workspace_bytes(items, n_items, 1, 1))
+    tc = sum(it.extent.n_slices * it.grid.nx * it.grid.ny for it in items)
+    G, Cc, aG, aC = Buf(4 * tc), Buf(4 * tc), Buf(4 * tc), Buf(4 * tc)
+    build_args = lambda fl: (P(xb), len(pts), items, n_items, P(G), P(Cc), P(aG), P(aC), fl, P(ws), ws.nbytes, None)
+    check("build_batched", L.pct_build_tomogram_batched(*build_args(0)))
+    n_ap = C.c_int32()
+    check("autotune_load", L.pct_autotune_load(path.encode(), C.byref(n_ap)))
+    assert n_ap.value == len(classes)
+    assert L.pct_build_tomogram_batched(*build_args(abi.PCT_DESCRIPTORS_RESIDENT)) == abi.PCT_ERR_ARG
+    check("build_batched", L.pct_build_tomogram_batched(*build_args(0)))
+    check("build_batched", L.pct_build_tomogram_batched(*build_args(abi.PCT_DESCRIPTORS_RESIDENT)))
+    np.testing.assert_array_equal(bits(G.get(tc, np.float32)), bits(before["G"][:tc]))
+    np.testing.assert_array_equal(aG.get(tc, np.int32), before["aG"][:tc])
+    _, loaded = batch_run(pts, specs, [rb], True)
+    for k in before:
+        np.testing.assert_array_equal(bits(loaded[k]), bits(before[k]), err_msg=k)
+    # save, reset, load back: the same records
+    path2 = os.path.join(tmp, "saved.txt")
+    check("autotune_save", L.pct_autotune_save(path2.encode()))
+    L.pct_autotune_reset()
+    check("autotune_load", L.pct_autotune_load(path2.encode(), C.byref(n_ap)))
+    assert n_ap.value == len(classes), n_ap.value
+    with open(path2) as fp:
+        saved = sorted(l for l in fp.read().splitlines() if not l.startswith("#"))
+    assert saved == sorted(l for l in lines[1:] if l.startswith("cpu-emulator")), saved
+    with open(path, "a") as fp:
+        fp.write("cpu-emulator batch_eval 7 7 3 32 2\n")     # two-wave strips are not batch shapes
+    L.pct_autotune_reset()
+    assert L.pct_autotune_load(path.encode(), C.byref(n_ap)) == abi.PCT_ERR_ARG
+    check("autotune_save", L.pct_autotune_save(path2.encode()))
+    with open(path2) as fp:
+        assert not [l for l in fp.read().splitlines() if not l.startswith("#")]
+    L.pct_autotune_reset()
+    say("batch tuning tables: loaded shapes change no output, stale resident tables refused, save/load round trip")
+
+
 def case_config1_build():
     """The 20 M-point 2000 x 2000 map, tomogram with ids (slow: minutes)."""
     sc = scenes.config1_scene()

@@ -361,6 +361,19 @@ hipError_t hipGetDevice(int* device) {
     *device = 0;
     return hipSuccess;
 }
+hipError_t hipMalloc(void** ptr, size_t n) {
+    *ptr = calloc(n ? n : 1, 1);
+    return *ptr ? hipSuccess : hipErrorInvalidValue;
+}
+hipError_t hipFree(void* ptr) {
+    free(ptr);
+    return hipSuccess;
+}
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* prop, int device) {
+    if (device != 0) return hipErrorInvalidValue;
+    snprintf(prop->gcnArchName, sizeof prop->gcnArchName, "cpu-emulator");
+    return hipSuccess;
+}
 hipError_t hipStreamGetDevice(hipStream_t, hipDevice_t* device) {
     *device = 0;
     return hipSuccess;

@@ -70,6 +70,13 @@ hipError_t hipGetDevice(int* device);
 hipError_t hipStreamGetDevice(hipStream_t s, hipDevice_t* device);
 hipError_t hipGetSymbolAddress(void** ptr, const void* symbol);
 #define HIP_SYMBOL(x) ((const void*)&(x))
+// Device memory is host memory (calloc'd, so the sanitizer sees its bounds).
+hipError_t hipMalloc(void** ptr, size_t n);
+hipError_t hipFree(void* ptr);
+struct hipDeviceProp_t {
+    char gcnArchName[256];
+};
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* prop, int device);
 typedef struct emu_event* hipEvent_t;
 hipError_t hipEventCreate(hipEvent_t* e);
 hipError_t hipEventDestroy(hipEvent_t e);

@@ -63,7 +63,7 @@ GROUPS = [
     (("slice_runs", "crowded_cells", "dense_tiles"), "rand"),
     (("crop", "dense", "multirobot_large"), "rand"),
     (("many_chunks", "two_level"), "fwd"),
-    (("batch", "batch_resident", "batch_mixed_radius"), "rand"),
+    (("batch", "batch_resident", "batch_mixed_radius", "batch_tune"), "rand"),
     (("traj_value_grad", "autotune"), "fwd"),
     (("plan", "unique"), "rand"),
     (("plan_query",), "fwd"),

@@ -141,6 +141,90 @@ def test_graph_capture_replays(P):
         _ = (xyz * 2.0).sum().item()      # unrelated eager work between replays
 
 
+def test_batch_tuning_changes_no_output(P, tmp_path):
+    """The size-class tuner records one tile height and one strip shape per
+    class; the batched outputs (with ids and slice flags) after tuning, after
+    loading other shapes from a file and in a graph captured with the tuned
+    shapes are those before tuning, bit for bit; descriptor tables uploaded
+    with other shapes are refused for resident calls."""
+    import torch
+    items, pts, specs = make_batch(65, 24, side_hi=300, pts_hi=150_000)
+    xyz = torch.from_numpy(pts).cuda()
+    rb = P.robot_from_physical(scenes.ROBOT_CONFIG0, 0.1)
+    P.pct_autotune_reset()
+    b = P.Batch(xyz, specs, n_robots=1, with_ids=True)
+    P.pct_tomogram_extent_batched(b)
+
+    def run(flags=0, out=None):
+        G, Cc, aG, aC = P.pct_build_tomogram_batched(b, with_ids=True, flags=flags, out=out and out[:4])
+        cost, keep = P.pct_eval_traversability_batched(b, G, Cc, [rb], flags=flags, out=out and out[4:])
+        return [G, Cc, aG, aC, cost, keep]
+
+    ref = [t.clone() for t in run()]
+    torch.cuda.synchronize()
+    say(f"tuning a batch of {len(specs)} submaps")
+    ent = P.pct_autotune_batched(b, rb)
+    classes = {(e["stage"], e["class_x"], e["class_y"], e["radius"]) for e in ent}
+    assert {c[0] for c in classes} == {"build", "eval"} and len(classes) >= 4
+    chosen = {}
+    for c in classes:
+        ch = [e for e in ent if (e["stage"], e["class_x"], e["class_y"], e["radius"]) == c and e["chosen"]]
+        assert len(ch) == 1, c
+        chosen[c] = (ch[0]["rows"], ch[0]["waves"])
+    say(f"{len(ent)} timings over {len(classes)} (stage, class) pairs")
+
+    def same(outs, what):
+        torch.cuda.synchronize()
+        for a, r in zip(outs, ref):
+            assert torch.equal(a.view(torch.uint8), r.view(torch.uint8)), what
+
+    same(run(), "after tuning")
+    # other shapes for every class, from a file
+    it0 = next(it for it in b.items if it.extent.n_slices > 0)
+    P.pct_autotune_set_traversability(it0.grid, it0.extent, rb, 64, 1)   # at least one record
+    tuned = tmp_path / "tuned.txt"
+    P.pct_autotune_save(tuned)
+    recs = [l.split() for l in tuned.read_text().splitlines() if l and not l.startswith("#")]
+    assert recs, "the tuner recorded nothing"
+    arch = recs[0][0]       # the device's architecture tag
+    lines = []
+    for (st, cx, cy, R), ch in sorted(chosen.items()):
+        if st == "build":
+            lines.append(f"{arch} batch_build {cx} {cy} {4 if ch[0] == 8 else 8}")
+        else:
+            lines.append(f"{arch} batch_eval {cx} {cy} {R} {64 if ch == (32, 1) else 32} 1")
+    path = tmp_path / "tune.txt"
+    path.write_text("\n".join(lines) + "\n")
+    assert P.pct_autotune_load(path) == len(lines)
+    with pytest.raises(P.PctError):
+        run(P.PCT_DESCRIPTORS_RESIDENT, [torch.empty_like(t) for t in ref])
+    same(run(), "with loaded shapes")
+    # a graph captured with these shapes
+    outs = [torch.empty_like(t) for t in ref]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        run(0, outs)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            run(P.PCT_DESCRIPTORS_RESIDENT, outs)
+    for rep in range(2):
+        for t in outs:
+            t.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        same(outs, f"graph replay {rep}")
+    # save and load back
+    saved = tmp_path / "saved.txt"
+    P.pct_autotune_save(saved)
+    n_rec = len([l for l in saved.read_text().splitlines() if l and not l.startswith("#")])
+    assert n_rec >= len(lines) + 1
+    P.pct_autotune_reset()
+    assert P.pct_autotune_load(saved) == n_rec
+    P.pct_autotune_reset()
+
+
 def test_graph_capture_with_library_helpers(P):
     """The same capture through the C ABI's pct_graph_begin / pct_graph_end:
     every replay equals the eager run; an empty capture replays as a no-op."""
