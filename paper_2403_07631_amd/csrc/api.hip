@@ -943,19 +943,29 @@ pct_status pct_autotune_batched(const float* d_xyz, int64_t n_total, const pct_i
         };
         EvalParams p0;
         const EvalShape old = batch_eval_shape(cx, cy, R);
+        set_batch_eval_shape(cx, cy, R, EvalShape{0, 0});   // {0, 0} below: the default shape
         const EvalShape shapes[] = {{0, 0},  {32, 1},  {64, 1},  {128, 1}, {256, 1},
                                     {32, 4}, {64, 4},  {128, 4}, {256, 4}};
         const size_t e_before = rep.size();
         float best = INFINITY;
         EvalShape best_sh{0, 0};
+        std::vector<std::vector<int>> tried;   // launches already timed (a shape that changes nothing is skipped)
         for (const EvalShape& sh : shapes) {
             bool fits = true;
+            std::vector<int> sig;
             for (const pct_item& t : sub) {
                 st = make_eval_params(*h_robot, t.grid, t.extent.n_slices, &p0);
-                if (st != PCT_OK) return st;
+                if (st != PCT_OK) {
+                    set_batch_eval_shape(cx, cy, R, old);
+                    return st;
+                }
                 if (sh.rows > 0 && !strip_shape_fits(p0, sh)) fits = false;
+                int g4[4];
+                batch_strip_signature(p0, sh, g4);
+                sig.insert(sig.end(), g4, g4 + 4);
             }
-            if (!fits) continue;
+            if (!fits || std::find(tried.begin(), tried.end(), sig) != tried.end()) continue;
+            tried.push_back(sig);
             set_batch_eval_shape(cx, cy, R, sh);
             float ms = 0.0f;
             st = time_calls(eval, s, 3, &ms);

@@ -34,6 +34,42 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
+// Points 4q .. 4q+3 as three 16-byte loads (xyz 16-byte aligned): each
+// lane reads 48 contiguous bytes, a wavefront 3 KB, instead of three
+// 4-byte loads per point.
+typedef float pts_f4 __attribute__((vector_size(16)));
+__device__ __forceinline__ void load_quad(const float* __restrict__ xyz, int64_t q, float (&px)[4], float (&py)[4],
+                                          float (&pz)[4]) {
+    const pts_f4* p = (const pts_f4*)(xyz + 12 * q);
+    const pts_f4 a = p[0], b = p[1], c = p[2];
+    px[0] = a[0], py[0] = a[1], pz[0] = a[2];
+    px[1] = a[3], py[1] = b[0], pz[1] = b[1];
+    px[2] = b[2], py[2] = b[3], pz[2] = c[0];
+    px[3] = c[1], py[3] = c[2], pz[3] = c[3];
+}
+
+// Points [4q, 4q + 4) clipped to [.., n): x, y, z and whether each exists;
+// whole quads of an aligned array by load_quad, others point by point.
+__device__ __forceinline__ void load_points4(const float* __restrict__ xyz, int64_t n, int64_t q, bool vec,
+                                             float (&px)[4], float (&py)[4], float (&pz)[4], bool (&ok)[4]) {
+    if (vec && 4 * q + 3 < n) {
+        load_quad(xyz, q, px, py, pz);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ok[e] = true;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t i = 4 * q + e;
+        ok[e] = i < n;
+        px[e] = ok[e] ? xyz[3 * i] : 0.0f;
+        py[e] = ok[e] ? xyz[3 * i + 1] : 0.0f;
+        pz[e] = ok[e] ? xyz[3 * i + 2] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 // ------------------------------------------------------------------ extent
 __global__ __launch_bounds__(kBlock) void k_extent(const float* __restrict__ xyz, int64_t n, GridDev g,
                                                    float* __restrict__ pmin, float* __restrict__ pmax,
@@ -41,14 +77,21 @@ __global__ __launch_bounds__(kBlock) void k_extent(const float* __restrict__ xyz
     float lo = INFINITY, hi = -INFINITY;
     unsigned long long used = 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-        int ix, iy;
-        if (!isfinite(z) || !rasterize(x, y, g, ix, iy)) continue;
-        z = z + 0.0f;
-        lo = fminf(lo, z);
-        hi = fmaxf(hi, z);
-        ++used;
+    const bool vec = aligned16(xyz);
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; 4 * q < n; q += stride) {
+        float px[4], py[4], pz[4];
+        bool ok[4];
+        load_points4(xyz, n, q, vec, px, py, pz, ok);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float z = pz[e];
+            int ix, iy;
+            if (!ok[e] || !isfinite(z) || !rasterize(px[e], py[e], g, ix, iy)) continue;
+            z = z + 0.0f;
+            lo = fminf(lo, z);
+            hi = fmaxf(hi, z);
+            ++used;
+        }
     }
     __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
     __shared__ unsigned long long s_u[kBlock / 64];
@@ -112,6 +155,18 @@ __global__ __launch_bounds__(kBlock) void k_extent_final(const float* __restrict
 constexpr int kExtentBlocks = 2048;
 
 // ------------------------------------------------------------------ binning
+__device__ __forceinline__ bool bin_xyz(float x, float y, float zin, const GridDev& g, int& tile, unsigned& cell,
+                                        float& z) {
+    z = zin;
+    int ix, iy;
+    if (!isfinite(z) || !rasterize(x, y, g, ix, iy)) return false;
+    z = z + 0.0f;
+    int tx = ix / kBuildTileW, ty = iy / g.th;
+    tile = ty * g.ntx + tx;
+    cell = (unsigned)((iy - ty * g.th) * kBuildTileW + (ix - tx * kBuildTileW));
+    return true;
+}
+
 __device__ __forceinline__ bool bin_point(const float* __restrict__ xyz, int64_t i, const GridDev& g,
                                           int& tile, unsigned& cell, float& z) {
     float x = xyz[3 * i], y = xyz[3 * i + 1];
@@ -205,12 +260,20 @@ __global__ __launch_bounds__(kBinBlock) void k_bin1_hist(const float* __restrict
     extern __shared__ unsigned s_cnt[];
     for (int t = threadIdx.x; t < S1; t += kBinBlock) s_cnt[t] = 0;
     __syncthreads();
-    const int64_t b0 = (int64_t)blockIdx.x * kBinChunk, b1 = min(n, b0 + kBinChunk);
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kBinBlock) {
-        int tile;
-        unsigned cell;
-        float z;
-        if (bin_point(xyz, i, g, tile, cell, z)) atomicAdd(&s_cnt[tile / G], 1u);
+    // the chunk's points as quads (kBinChunk is a multiple of 4)
+    const int64_t q0 = (int64_t)blockIdx.x * (kBinChunk / 4), q1 = min((n + 3) / 4, q0 + kBinChunk / 4);
+    const bool vec = aligned16(xyz);
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBinBlock) {
+        float px[4], py[4], pz[4];
+        bool ok[4];
+        load_points4(xyz, n, q, vec, px, py, pz, ok);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int tile;
+            unsigned cell;
+            float z;
+            if (ok[e] && bin_xyz(px[e], py[e], pz[e], g, tile, cell, z)) atomicAdd(&s_cnt[tile / G], 1u);
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < S1; t += kBinBlock) cnt1[(int64_t)t * nb1 + blockIdx.x] = s_cnt[t];
@@ -404,19 +467,29 @@ __global__ __launch_bounds__(kBinBlock) void k_bin1_scatter_staged(const float* 
     float z[kBinPPT];
     unsigned key[kBinPPT], rank[kBinPPT];
     int id[kBinPPT], bk[kBinPPT];
-    const int64_t b0 = (int64_t)blockIdx.x * kBinChunk;
+    // quads m kBinBlock + threadIdx.x of the chunk: points 4 q .. 4 q + 3
+    static_assert(kBinPPT % 4 == 0, "whole quads per thread");
+    const int64_t q0 = (int64_t)blockIdx.x * (kBinChunk / 4);
+    const bool vec = aligned16(xyz);
 #pragma unroll
-    for (int j = 0; j < kBinPPT; ++j) {
-        const int64_t i = b0 + (int64_t)j * kBinBlock + threadIdx.x;
-        int tile;
-        unsigned cell;
-        bk[j] = -1;
-        id[j] = (int)i;
-        if (i < n && bin_point(xyz, i, g, tile, cell, z[j])) {
-            const int st = tile / G;
-            bk[j] = st;
-            key[j] = FINAL ? cell : (unsigned)(tile - st * G) * (unsigned)CT + cell;
-            rank[j] = atomicAdd(&s_cnt[st], 1u);
+    for (int m = 0; m < kBinPPT / 4; ++m) {
+        const int64_t q = q0 + (int64_t)m * kBinBlock + threadIdx.x;
+        float px[4], py[4], pz[4];
+        bool ok[4];
+        load_points4(xyz, n, q, vec, px, py, pz, ok);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * m + e;
+            int tile;
+            unsigned cell;
+            bk[j] = -1;
+            id[j] = (int)(4 * q + e);
+            if (ok[e] && bin_xyz(px[e], py[e], pz[e], g, tile, cell, z[j])) {
+                const int st = tile / G;
+                bk[j] = st;
+                key[j] = FINAL ? cell : (unsigned)(tile - st * G) * (unsigned)CT + cell;
+                rank[j] = atomicAdd(&s_cnt[st], 1u);
+            }
         }
     }
     __syncthreads();

@@ -1018,6 +1018,15 @@ void autotune_reset() {
     g_batch_build.clear();
 }
 
+void batch_strip_signature(const EvalParams& p, EvalShape shape, int out[4]) {
+    const StripGeom g = strip_geom(p, shape.rows > 0 ? shape : batch_eval_shape(size_class(p.nx), size_class(p.ny), p.R),
+                                   false);
+    out[0] = g.nw;
+    out[1] = g.n_sx;
+    out[2] = g.n_sy;
+    out[3] = g.n_sy > 1 ? g.rows : 0;   // one strip row: the height does not matter
+}
+
 // Text form of the tables, one record a line, for the current device's
 // architecture `arch`:
 //   <arch> map <nx> <ny> <N> <R> <rows> <waves>

@@ -148,6 +148,10 @@ EvalShape batch_eval_shape(int cx, int cy, int R);
 void set_batch_eval_shape(int cx, int cy, int R, EvalShape shape);
 int batch_build_th(int cx, int cy);
 void set_batch_build_th(int cx, int cy, int th);
+// What a batched launch of a job with parameters p does with strip shape
+// `shape` ({0, 0}: the shape batched calls use now): wavefronts per
+// workgroup, strips across and down, and the strip height when it matters.
+void batch_strip_signature(const EvalParams& p, EvalShape shape, int out[4]);
 pct_status tune_save(const char* path, const char* arch);
 pct_status tune_load(const char* path, const char* arch, int* n_applied);
 

@@ -279,6 +279,39 @@ def case_crowded_cells():
         tomogram_case(pts, grid, False, f"crowded cells nx={nx}")
 
 
+class _Offset:
+    """A view `off` bytes into a Buf (the Buf stays alive with it)."""
+
+    def __init__(self, base, off):
+        self.base, self.ptr, self.nbytes = base, base.ptr + off, base.nbytes - off
+
+
+def case_unaligned_points():
+    """Points whose array is not 16-byte aligned (the extent and binning
+    kernels then read them point by point) and an aligned array whose length
+    is not a multiple of four, over several binning chunks: the same
+    tomograms as the oracle's."""
+    rng = np.random.default_rng(29)
+    grid = dict(x0=0.0, y0=0.0, res=0.1, nx=70, ny=33, slice_dz=0.25)
+    n = 3 * 4096 + 1003
+    pts = np.column_stack([rng.uniform(-0.3, 7.3, n), rng.uniform(-0.2, 3.5, n),
+                           np.round(rng.uniform(0.0, 3.0, n), 2)]).astype(np.float32)
+    tm = oracle.tomogram(pts, grid)
+    for off in (4, 8, 0):
+        raw = Buf(pts.nbytes + off)
+        C.memmove(raw.ptr + off, pts.ctypes.data, pts.nbytes)
+        xb = _Offset(raw, off)
+        e = extent(xb, n, grid)
+        assert e.n_used == tm["n_used"] and e.n_slices == len(tm["h"])
+        G, Cc, aG, aC = build(xb, n, grid, e, True)
+        shape = (e.n_slices, grid["ny"], grid["nx"])
+        np.testing.assert_array_equal(bits(G.get(shape, np.float32)), bits(tm["ground"]))
+        np.testing.assert_array_equal(bits(Cc.get(shape, np.float32)), bits(tm["ceil"]))
+        np.testing.assert_array_equal(aG.get(shape, np.int32), tm["arg_ground"])
+        np.testing.assert_array_equal(aC.get(shape, np.int32), tm["arg_ceil"])
+        say(f"tomogram from points at byte offset {off}, n={n}: bit-exact")
+
+
 def case_dense_tiles():
     """Tiles with more records on average than the tile reduce's floor
     capacity, so that the launch raises it (above 64 KB of LDS): 12 000
@@ -521,7 +554,8 @@ def case_batch_tune():
     those before; resident tables of other shapes are refused; the tables
     survive a save and load, and a malformed file applies nothing."""
     import tempfile
-    items_sc, pts, specs = make_batch(64, 5, side_hi=90, pts_hi=25_000, extra_empty=True)
+    # small items: the tuner runs every distinct candidate four times per class
+    items_sc, pts, specs = make_batch(64, 2, side_hi=24, pts_hi=3_000, extra_empty=True)
     rb = robot()
     L.pct_autotune_reset()
     _, before = batch_run(pts, specs, [rb], True)
@@ -535,7 +569,9 @@ def case_batch_tune():
                                                      None))
     es = list(ent[:cnt.value])
     classes = {(e.stage, e.class_x, e.class_y, e.radius) for e in es}
-    assert cnt.value >= 2 * 3 and len(classes) >= 2
+    # three tile heights; strip shapes that launch the same strips are timed once
+    assert cnt.value >= 3 + 2 and len(classes) >= 2
+    assert len({(e.rows, e.waves) for e in es if e.stage == 1}) == sum(e.stage == 1 for e in es)
     for c in classes:
         assert sum(e.chosen for e in es if (e.stage, e.class_x, e.class_y, e.radius) == c) == 1, c
         assert all(e.ms > 0 for e in es if (e.stage, e.class_x, e.class_y, e.radius) == c)

@@ -65,6 +65,12 @@ def unwritten_vgprs(disasm):
                 r |= _regs(a)
             continue
         w |= _regs(ops[0])
+        if op.startswith(("v_mad_u64_u32", "v_mad_i64_i32")) and len(ops) >= 5:
+            # a 32-bit multiply-add done by the 64-bit instruction leaves the
+            # addend's high half undefined: only its low register is read
+            m = re.match(r"v\[(\d+):\d+\]", ops[4])
+            if m:
+                ops = ops[:4] + [f"v{m.group(1)}"] + ops[5:]
         for a in ops[1:]:
             r |= _regs(a)
     return {f: sorted(r - w - {0, 1, 2}) for f, (w, r) in res.items() if r - w - {0, 1, 2}}
@@ -125,3 +131,7 @@ def test_scan_finds_a_dropped_copy():
 """
     assert unwritten_vgprs(listing) == {"k_demo": [51]}
     assert unwritten_vgprs(listing.replace("v51", "v8")) == {}
+    # the high half of a 64-bit multiply-add's addend is not counted as read
+    mad = listing.replace("v_mov_b32_e32 v8, v7", "v_mad_u64_u32 v[8:9], s[0:1], v4, s2, v[6:7]")
+    mad = mad.replace("v51", "v4").replace("global_load_dwordx4 v[4:7]", "global_load_dwordx2 v[4:5]")
+    assert unwritten_vgprs(mad) == {"k_demo": [6]}

@@ -60,7 +60,7 @@ def run_cases(cases, order="fwd", timeout=900):
 
 GROUPS = [
     (("tiny", "edges", "config0", "multirobot", "fallback_eval"), "rev"),
-    (("slice_runs", "crowded_cells", "dense_tiles"), "rand"),
+    (("slice_runs", "crowded_cells", "dense_tiles", "unaligned_points"), "rand"),
     (("crop", "dense", "multirobot_large"), "rand"),
     (("many_chunks", "two_level"), "fwd"),
     (("batch", "batch_resident", "batch_mixed_radius", "batch_tune"), "rand"),
