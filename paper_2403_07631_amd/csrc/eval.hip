@@ -197,6 +197,13 @@ __device__ __forceinline__ float maxnn(float a, float b) {
 // skipping those multiplies leaves every maximum unchanged.
 constexpr int kNoZeroTaps = 1 << 20;
 
+// The largest j <= R with j^2 <= Q1 (0 when Q1 < 1): taps (0, j) up to it have weight 1.
+constexpr int weight1_reach(int Q1, int R) {
+    int j = 0;
+    while (j < R && (j + 1) * (j + 1) <= Q1) ++j;
+    return j;
+}
+
 constexpr int kWgOwn = 60;                        // own columns of a wavefront
 constexpr int kDefaultWaves = PCT_STRIP_WAVES;    // wavefronts of the widest workgroup strip
 static_assert(64 * kDefaultWaves == kBlock, "batched jobs run in blocks of kBlock threads");
@@ -259,6 +266,8 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
     constexpr int S0 = 2 * R + 1 > 4 ? 2 * R + 1 : 4;
     constexpr int S1 = S0 > kPrefetch ? S0 : kPrefetch;
     constexpr int S = (S1 + 3) / 4 * 4;     // a multiple of 4: the LDS set of step t is (ph >> 1) & 1
+    // vertical taps of weight exactly 1: |dy| <= JV (the centre alone when the pattern is not known)
+    constexpr int JV = weight1_reach(Q1, R);
     const int gx = w % sg.n_sx;
     const int t0 = w / sg.n_sx;
     const int sy = t0 % sg.n_sy;
@@ -295,7 +304,8 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
     // whether that row has ground
     float sdx = 0.0f, sdy = 0.0f, ss2 = 0.0f;
     bool sfin = false;
-    float h0_even = 0.0f;
+    float h0_even = 0.0f, h0_cur = 0.0f;
+    bool skip_even = false;  // the even step's row needs no window maxima (uniform)
     bool any_trav = false;   // a stored cost of this wavefront is below c^B (uniform)
     const int ys = Y0 - 2 * HX;
 #pragma unroll
@@ -366,6 +376,23 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
 #pragma unroll
                 for (int jj = 1; jj <= R; ++jj)
                     P[jj] = maxnn(cS[(ph + S - R - jj) % S], cS[(ph + S - R + jj) % S]);
+                // One-wavefront strips skip the window maxima of a row that is
+                // not stored (the rows before Y0 only fill the rings), and of a
+                // row whose every stored output is already known to be c^B:
+                // c^init <= c^B everywhere, so an output whose window holds a
+                // cell with c^init = c^B at a tap of weight exactly 1 (the
+                // vertical taps |dy| <= JV of its own column) is c^B.  The
+                // vote is the wavefront's own; its exchange buffer is read by
+                // its own lanes only.
+                bool skip = false;
+                if constexpr (NW == 1) {
+                    float vm = P[0];
+#pragma unroll
+                    for (int jj = 1; jj <= JV; ++jj) vm = maxnn(vm, P[jj]);
+                    skip = y < Y0 || __ballot(xout && vm < p.cB) == 0ull;
+                }
+                if ((ph & 1) == 0) skip_even = skip;
+                if (!skip) {
                 float h[R + 1];
 #pragma unroll
                 for (int a = 0; a <= R; ++a) {
@@ -387,17 +414,23 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
                     for (int a = 1; a <= R; ++a) buf[i * R + a - 1] = h[a];
                 }
                 if ((ph & 1) == 0) h0_even = h[0];
+                else h0_cur = h[0];
+                }
                 if ((ph & 1) == 1 || t == n_steps - 1) {
                     row_exchange_sync<NW>();
 #pragma unroll
                     for (int r2 = 0; r2 < 2; ++r2) {
                         if (r2 == 0 && (ph & 1) == 0) continue;   // a lone even step: its row only
                         const int yy = r2 == 0 ? y - 1 : y;
-                        const float* rb = lds.v[(ph >> 1) & 1][r2 == 0 ? 0 : (ph & 1)] + (ir - R) * R;
-                        float v = r2 == 0 ? h0_even : h[0];
+                        const bool even = r2 == 0 || (ph & 1) == 0;
+                        float v = p.cB;
+                        if (!(even ? skip_even : skip)) {
+                            const float* rb = lds.v[(ph >> 1) & 1][r2 == 0 ? 0 : (ph & 1)] + (ir - R) * R;
+                            v = even ? h0_even : h0_cur;
 #pragma unroll
-                        for (int a = 1; a <= R; ++a)
-                            v = maxnn(v, maxnn(rb[(R - a) * R + a - 1], rb[(R + a) * R + a - 1]));
+                            for (int a = 1; a <= R; ++a)
+                                v = maxnn(v, maxnn(rb[(R - a) * R + a - 1], rb[(R + a) * R + a - 1]));
+                        }
                         if (yy >= Y0 && xout) buf_store(v, rO, voff, yy * row_bytes);
                         if (slice_bits && yy >= Y0 && !any_trav)   // uniform
                             any_trav = __ballot(xout && v < p.cB) != 0ull;
