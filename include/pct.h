@@ -163,13 +163,12 @@ pct_status pct_build_tomogram(const float* d_xyz, int64_t n, const pct_grid* gri
 /* Traversability (Sec. III-B) and simplification (Sec. III-C)            */
 
 /* Workspace bytes for pct_eval_traversability (any number of robots: they
- * reuse it in turn).  The slice test needs at least its scratch (per-slice
- * run starts and an N x N bit matrix, 4 N + 4 N ceil(N / 32) bytes, each
- * part 256-byte aligned); the size returned here also holds one bit per
- * cell and slice of which cells are traversable, with which the slice test
- * reads only traversable cells (whole maps, patch radius 1, inflation
- * radius <= 8).  A workspace between the two sizes runs the slice test over
- * every cell. */
+ * reuse it in turn): the slice test's scratch, each part 256-byte aligned:
+ * an N x N bit matrix of in-run comparisons (4 N ceil(N / 32) bytes), one
+ * bit per slice marking the slices with a traversable cell (the slice test
+ * reads no other slice), and 16 copies of the per-slice largest run starts,
+ * 4 KB apart (the many wavefronts that reach a slice together spread their
+ * atomics over the copies).  Only d_keep needs it. */
 size_t pct_eval_workspace_bytes(const pct_grid* grid, const pct_extent* extent, int32_t n_robots);
 
 /* Eqs. (1)-(6) for every slice, then the slice test of Eqs. (7)-(9), for
@@ -198,10 +197,9 @@ pct_status pct_eval_traversability(const float* d_ground, const float* d_ceil, c
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * evaluation and slice test as pct_eval_traversability, with the slice
- * test's scratch (per-slice run starts and an N x N bit matrix, and the
- * traversability bits of the faster slice test when they fit) in a
- * library-owned static device array of PCT_STATIC_WORKSPACE_BYTES instead
- * of a caller workspace.  Each GPU the library runs on holds its own copy
+ * test's scratch (the N x N bit matrix, the slice marks and as many copies
+ * of the run starts as fit, at least one) in a library-owned static device
+ * array of PCT_STATIC_WORKSPACE_BYTES instead of a caller workspace.  Each GPU the library runs on holds its own copy
  * of that array until the process ends; the first call on a device finds
  * its address (with that device current).  The call allocates nothing and
  * clears the part of the array it uses before using it.  Every call on one

@@ -464,7 +464,7 @@ pct_status pct_eval_traversability_static(const float* d_ground, const float* d_
     if (st != PCT_OK) return st;
     const int N = extent->n_slices;
     if (N == 0) return PCT_OK;
-    const size_t need = eval_ws_bytes(N, n_robots);
+    const size_t need = eval_ws_min_bytes(N);
     if (d_keep && need > PCT_STATIC_WORKSPACE_BYTES)
         return fail(PCT_ERR_CAPACITY, "the slice test needs %zu bytes of scratch, the static array holds %u", need,
                     (unsigned)PCT_STATIC_WORKSPACE_BYTES);
@@ -1336,7 +1336,7 @@ pct_status pct_eval_traversability_window(const float* d_ground, const float* d_
         p.wx1 = grid->nx;
         p.wy1 = grid->ny;
     }
-    if (d_keep) return launch_simplify(d_ground, d_cost, p, d_keep, d_ws, s);
+    if (d_keep) return launch_simplify(d_ground, d_cost, p, d_keep, d_ws, ws_bytes, s);
     return PCT_OK;
 }
 

@@ -617,9 +617,10 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, unsigned* __restrict__ urun,
-                                                      unsigned* __restrict__ slice_bits, int N, int W) {
+                                                      unsigned* __restrict__ slice_bits, int N, int W,
+                                                      int copies, int cstride) {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N * W; i += gridDim.x * kBlock) urun[i] = 0u;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) maxp0[i] = -1;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < copies * cstride; i += gridDim.x * kBlock) maxp0[i] = -1;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < W; i += gridDim.x * kBlock) slice_bits[i] = 0u;
 }
 
@@ -643,9 +644,15 @@ template <int STRIDE>
 __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ ground, const float* __restrict__ cost,
                                                  long long plane, int N, float cB, int W, int* __restrict__ maxp0,
                                                  unsigned* __restrict__ urun, long long cell0, int nact,
-                                                 const unsigned* __restrict__ slice_bits = nullptr) {
+                                                 const unsigned* __restrict__ slice_bits = nullptr,
+                                                 int copies = 1, int cstride = 0) {
     constexpr int CPT = kSimpCells;
     const int lane = threadIdx.x & 63;
+    // the largest run starts go to one of `copies` copies of maxp0 (cstride
+    // ints apart, on separate cache lines), by wavefront: thousands of
+    // wavefronts reach each slice together, and atomics on one line queue
+    // behind each other
+    maxp0 += (int)((((long long)blockIdx.x * kBlock + threadIdx.x) >> 6) % copies) * cstride;
     // bit j of sb0 / sb1: slice 32 * (k / 32) + j / + 32 + j holds a traversable cell
     auto bits_word = [&](int w) -> unsigned {   // uniform
         if (!slice_bits) return ~0u;
@@ -799,14 +806,16 @@ __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ groun
 __global__ __launch_bounds__(kBlock) void k_simp_flags(const float* __restrict__ ground, const float* __restrict__ cost,
                                                        const int nx, const int ny, const int N, const float cB,
                                                        const int W, int* __restrict__ maxp0, unsigned* __restrict__ urun,
-                                                       const unsigned* __restrict__ slice_bits) {
+                                                       const unsigned* __restrict__ slice_bits, int copies,
+                                                       int cstride) {
     const long long plane = (long long)nx * ny;
     // the wavefront's 64 x kSimpCells cells, lane-interleaved
     const long long wave0 = ((long long)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kSimpCells;
     const long long cell0 = wave0 + (threadIdx.x & 63);
     const long long left = plane - cell0;
     const int nact = left <= 0 ? 0 : (int)std::min<long long>(kSimpCells, (left + 63) / 64);
-    simp_flags_cells<64>(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact, slice_bits);
+    simp_flags_cells<64>(ground, cost, plane, N, cB, W, maxp0, urun, nact > 0 ? cell0 : 0, nact, slice_bits, copies,
+                         cstride);
 }
 
 __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
@@ -822,10 +831,18 @@ __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __rest
     }
 }
 
-__global__ void k_keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun, int N, int W,
-                             uint8_t* __restrict__ keep) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    keep_chain(maxp0, urun, N, W, keep);
+// One workgroup of 64: the copies of the run starts merged per slice by
+// all lanes, then the chain on one lane.
+__global__ __launch_bounds__(64) void k_keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun,
+                                                   int N, int W, uint8_t* __restrict__ keep, int copies, int cstride) {
+    __shared__ int s_m[PCT_MAX_SLICES];
+    for (int k = threadIdx.x; k < N; k += 64) {
+        int m = maxp0[k];
+        for (int c = 1; c < copies; ++c) m = max(m, maxp0[c * cstride + k]);
+        s_m[k] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) keep_chain(s_m, urun, N, W, keep);
 }
 
 // ---- batched slice test: one workgroup per job for the init and chain,
@@ -883,11 +900,17 @@ __global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, 
 
 }  // namespace
 
-size_t eval_ws_bytes(int N, int) {
+// The single-map slice test's scratch: the N x N bit matrix, the slice
+// marks, then `copies` copies of the largest run starts, 4 KB apart.
+constexpr int kRunStartCopies = 16;
+inline size_t run_start_stride(int N) { return align_up(sizeof(int) * (size_t)N, 4096); }
+inline size_t simp_base_bytes(int N) {
     const int W = (N + 31) / 32;
-    return align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * W) +
-           align_up(sizeof(unsigned) * (size_t)W);
+    return align_up(sizeof(unsigned) * (size_t)N * W) + align_up(sizeof(unsigned) * (size_t)W);
 }
+
+size_t eval_ws_bytes(int N, int) { return simp_base_bytes(N) + kRunStartCopies * run_start_stride(N); }
+size_t eval_ws_min_bytes(int N) { return simp_base_bytes(N) + run_start_stride(N); }
 
 // The compiled tap-weight patterns: for radius R >= 2, weight exactly 1 for
 // a^2 + j^2 <= (R-2)^2 and exactly 0 for a^2 + j^2 >= (R+1)^2 (an inflation
@@ -1163,15 +1186,19 @@ struct SimpScratch {
     int* maxp0;
     unsigned* urun;
     unsigned* slice_bits;
-    int W;
+    int W, copies, cstride;
 };
 
-SimpScratch simp_scratch(void* ws, int N) {
+// ws_bytes >= eval_ws_min_bytes(N): as many copies of the run starts as fit, up to 16
+SimpScratch simp_scratch(void* ws, int N, size_t ws_bytes) {
     SimpScratch sc;
     sc.W = (N + 31) / 32;
-    sc.maxp0 = (int*)ws;
-    sc.urun = (unsigned*)((char*)ws + align_up(sizeof(int) * (size_t)N));
-    sc.slice_bits = (unsigned*)((char*)sc.urun + align_up(sizeof(unsigned) * (size_t)N * sc.W));
+    sc.urun = (unsigned*)ws;
+    sc.slice_bits = (unsigned*)((char*)ws + align_up(sizeof(unsigned) * (size_t)N * sc.W));
+    sc.maxp0 = (int*)((char*)ws + simp_base_bytes(N));
+    const size_t stride = run_start_stride(N);
+    sc.copies = (int)std::max<size_t>(1, std::min<size_t>(kRunStartCopies, (ws_bytes - simp_base_bytes(N)) / stride));
+    sc.cstride = (int)(stride / sizeof(int));
     return sc;
 }
 
@@ -1180,9 +1207,10 @@ pct_status launch_simp_flags(const float* ground, const float* cost, const EvalP
                              const SimpScratch& sc, const unsigned* slice_bits, hipStream_t s) {
     const long long blocks = (p.plane + (long long)kBlock * kSimpCells - 1) / ((long long)kBlock * kSimpCells);
     hipLaunchKernelGGL(k_simp_flags, dim3((unsigned)blocks), dim3(kBlock), 0, s, ground, cost, p.nx, p.ny, p.N, p.cB,
-                       sc.W, sc.maxp0, sc.urun, slice_bits);
+                       sc.W, sc.maxp0, sc.urun, slice_bits, sc.copies, sc.cstride);
     PCT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_keep_chain, dim3(1), dim3(64), 0, s, sc.maxp0, sc.urun, p.N, sc.W, keep);
+    hipLaunchKernelGGL(k_keep_chain, dim3(1), dim3(64), 0, s, sc.maxp0, sc.urun, p.N, sc.W, keep, sc.copies,
+                       sc.cstride);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -1190,10 +1218,10 @@ pct_status launch_simp_flags(const float* ground, const float* cost, const EvalP
 }  // namespace
 
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep, void* ws,
-                           hipStream_t s) {
-    SimpScratch sc = simp_scratch(ws, p.N);
+                           size_t ws_bytes, hipStream_t s) {
+    SimpScratch sc = simp_scratch(ws, p.N, ws_bytes);
     hipLaunchKernelGGL(k_simp_init, dim3(std::max(1, std::min(1024, (p.N * sc.W + kBlock - 1) / kBlock))), dim3(kBlock),
-                       0, s, sc.maxp0, sc.urun, sc.slice_bits, p.N, sc.W);
+                       0, s, sc.maxp0, sc.urun, sc.slice_bits, p.N, sc.W, sc.copies, sc.cstride);
     PCT_LAUNCH_CHECK();
     return launch_simp_flags(ground, cost, p, keep, sc, nullptr, s);
 }
@@ -1204,17 +1232,16 @@ pct_status launch_simplify(const float* ground, const float* cost, const EvalPar
 // others without reading them.
 pct_status launch_eval_simplify(const float* ground, const float* ceil, const EvalParams& p, float* cost, uint8_t* keep,
                                 void* ws, size_t ws_bytes, hipStream_t s) {
-    (void)ws_bytes;
     if (!keep) return launch_eval(ground, ceil, p, cost, s);
     const bool whole = p.wx0 == 0 && p.wy0 == 0 && p.wx1 == p.nx && p.wy1 == p.ny;
     if (!(strip_kernel_applies(p) && whole)) {
         pct_status st = launch_eval(ground, ceil, p, cost, s);
         if (st != PCT_OK) return st;
-        return launch_simplify(ground, cost, p, keep, ws, s);
+        return launch_simplify(ground, cost, p, keep, ws, ws_bytes, s);
     }
-    SimpScratch sc = simp_scratch(ws, p.N);
+    SimpScratch sc = simp_scratch(ws, p.N, ws_bytes);
     hipLaunchKernelGGL(k_simp_init, dim3(std::max(1, std::min(1024, (p.N * sc.W + kBlock - 1) / kBlock))), dim3(kBlock),
-                       0, s, sc.maxp0, sc.urun, sc.slice_bits, p.N, sc.W);
+                       0, s, sc.maxp0, sc.urun, sc.slice_bits, p.N, sc.W, sc.copies, sc.cstride);
     PCT_LAUNCH_CHECK();
     pct_status st = launch_eval_geom(ground, ceil, p, cost, s, strip_geom(p), sc.slice_bits);
     if (st != PCT_OK) return st;

@@ -22,6 +22,8 @@
 // order in which the additions land; with PCT_FIXED_POINT, 64-bit integer
 // atomics on contributions rounded to multiples of 2^-32, whose sum does
 // not depend on that order (nor on how the work is split into launches).
+#include <limits.h>
+
 #include "pct_internal.h"
 
 namespace pct {
@@ -229,6 +231,72 @@ __device__ void window_max4(const float* __restrict__ gk, const float* __restric
         }
     }
 }
+
+// window_max4 over c^init values already in `box` (rows of bw cells from
+// column bx0, row by0, covering every window): the same row-major walk,
+// products and first maxima; the maximising cells' c^init details (o[c].q)
+// are recomputed when `details` is set.
+__device__ void window_max4_box(const float* __restrict__ box, int bx0, int by0, int bw,
+                                const float* __restrict__ gk, const float* __restrict__ ck, const int (&cx)[4],
+                                const int (&cy)[4], const EvalParams& p, bool details, WinMax (&o)[4]) {
+    const int nx = p.nx, ny = p.ny, R = p.R;
+    int xlo = cx[0], xhi = cx[0], ylo = cy[0], yhi = cy[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        xlo = min(xlo, cx[c]);
+        xhi = max(xhi, cx[c]);
+        ylo = min(ylo, cy[c]);
+        yhi = max(yhi, cy[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        o[c] = WinMax{};
+        o[c].v = -INFINITY;
+    }
+    for (int qy = max(0, ylo - R); qy <= min(ny - 1, yhi + R); ++qy) {
+        const float* row = box + (qy - by0) * bw - bx0;
+        for (int qx = max(0, xlo - R); qx <= min(nx - 1, xhi + R); ++qx) {
+            const float ci = row[qx];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int m = abs(qx - cx[c]), n = abs(qy - cy[c]);
+                if (m > R || n > R) continue;
+                const float kw = p.K[m][n];
+                if (kw <= 0.0f) continue;
+                const float v = kw * ci;
+                if (v > o[c].v) {
+                    o[c].v = v;
+                    o[c].k = kw;
+                    o[c].qx = qx;
+                    o[c].qy = qy;
+                }
+            }
+        }
+    }
+    if (details) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c].q = cinit_at(gk, ck, o[c].qx, o[c].qy, p);
+    }
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_int(int v) {
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// LDS written by some lanes of a wavefront, then read by others.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// c^init cells a wavefront shares per round of 64 waypoints (8 KB each).
+constexpr int kTrajBox = 2048;
 
 // Eq. (1)-(5) adjoint at the maximising cell of a window, for gradient gq
 // of its c^init.
@@ -542,12 +610,54 @@ __global__ __launch_bounds__(kBlock) void k_traj_value_grad(const float* __restr
     const EvalParams& p = robots[prof];
     const int lane = threadIdx.x & 63;
     const float g = gf ? gf[wave] : 0.0f;
+    __shared__ float s_box[kBlock / 64][kTrajBox];
+    float* box = s_box[threadIdx.x / 64];
     float acc = 0.0f;
-    for (int w = lane; w < a.W; w += 64) {
-        const long long i = wave * a.W + w;
+    // rounds of 64 waypoints; a round whose waypoints share a slice and whose
+    // windows fit one box has the wavefront compute each c^init of the box
+    // once (consecutive waypoints of a trajectory are close, so their
+    // windows overlap) and every lane take its window maxima from it
+    for (int w0 = 0; w0 < a.W; w0 += 64) {
+        const int w = w0 + lane;
+        const bool act = w < a.W;
+        const long long i = wave * a.W + min(w, a.W - 1);
         const float x = wp[3 * i], y = wp[3 * i + 1], z = wp[3 * i + 2];
         const int k = slice[i];
-        const Bil b = bilinear(ground, a, x, y, z, k);
+        Bil b = bilinear(ground, a, x, y, z, k);
+        b.ok = b.ok && act;
+        int cx[4] = {0, 0, 0, 0}, cy[4] = {0, 0, 0, 0};
+        if (b.ok) {
+            const long long base = (long long)k * a.plane;
+            const long long cs[4] = {b.c00, b.c10, b.c01, b.c11};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const long long local = cs[c] - base;
+                cx[c] = (int)(local % a.nx);
+                cy[c] = (int)(local / a.nx);
+            }
+        }
+        const unsigned long long okm = __ballot(b.ok);
+        bool use_box = false;
+        int bx0 = 0, by0 = 0, bw = 0;
+        if (okm != 0ull) {   // uniform
+            const int kb = __shfl(k, (int)__builtin_ctzll(okm), 64);
+            const bool same_k = __ballot(b.ok && k != kb) == 0ull;
+            const int xlo = wave_min_int(b.ok ? min(min(cx[0], cx[1]), min(cx[2], cx[3])) : INT_MAX);
+            const int xhi = wave_max_int(b.ok ? max(max(cx[0], cx[1]), max(cx[2], cx[3])) : INT_MIN);
+            const int ylo = wave_min_int(b.ok ? min(min(cy[0], cy[1]), min(cy[2], cy[3])) : INT_MAX);
+            const int yhi = wave_max_int(b.ok ? max(max(cy[0], cy[1]), max(cy[2], cy[3])) : INT_MIN);
+            bx0 = max(0, xlo - p.R);
+            by0 = max(0, ylo - p.R);
+            bw = min(a.nx - 1, xhi + p.R) - bx0 + 1;
+            const int bh = min(a.ny - 1, yhi + p.R) - by0 + 1;
+            use_box = same_k && (long long)bw * bh <= kTrajBox;
+            if (use_box) {
+                const long long base = (long long)kb * a.plane;
+                for (int idx = lane; idx < bw * bh; idx += 64)
+                    box[idx] = cinit_at(ground + base, ceil + base, bx0 + idx % bw, by0 + idx / bw, p).ci;
+                wave_lds_sync();
+            }
+        }
         float gx = 0.0f, gy = 0.0f, gzw = 0.0f;
         if (b.ok) {
             const long long base = (long long)k * a.plane;
@@ -555,14 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_traj_value_grad(const float* __restr
             const float* ck = ceil + base;
             const long long cs[4] = {b.c00, b.c10, b.c01, b.c11};
             WinMax wm[4];
-            int cx[4], cy[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const long long local = cs[c] - base;
-                cx[c] = (int)(local % a.nx);
-                cy[c] = (int)(local / a.nx);
-            }
-            window_max4(gk, ck, cx, cy, p, wm);
+            if (use_box) window_max4_box(box, bx0, by0, bw, gk, ck, cx, cy, p, gf != nullptr, wm);
+            else window_max4(gk, ck, cx, cy, p, wm);
             const float w00 = (1.0f - b.fu) * (1.0f - b.fv), w10 = b.fu * (1.0f - b.fv);
             const float w01 = (1.0f - b.fu) * b.fv, w11 = b.fu * b.fv;
             const float ws[4] = {w00, w10, w01, w11};
@@ -598,11 +702,12 @@ __global__ __launch_bounds__(kBlock) void k_traj_value_grad(const float* __restr
                 }
             }
         }
-        if (gwp) {
+        if (gwp && act) {
             gwp[3 * i] = gx;
             gwp[3 * i + 1] = gy;
             gwp[3 * i + 2] = gzw;
         }
+        if (use_box) wave_lds_sync();   // the next round refills the box
     }
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
     if (lane == 0) f[wave] = acc;

@@ -123,6 +123,7 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
                         hipStream_t s, bool merge = false, int id_base = 0);
 
 size_t eval_ws_bytes(int N, int n_robots);
+size_t eval_ws_min_bytes(int N);   // the least scratch the slice test runs in (one copy of the run starts)
 // Strip shape of the evaluation: output rows per strip and wavefronts per
 // workgroup sharing one strip (1: each wavefront its own strip);
 // rows = 0: the tuned shape for the map if recorded, else the default.
@@ -169,7 +170,7 @@ struct Digest {
 void digest_params(Digest& d, const EvalParams& p);
 pct_status resident_tables(const void* region, int kind, uint64_t digest, bool upload);
 pct_status launch_simplify(const float* ground, const float* cost, const EvalParams& p, uint8_t* keep,
-                           void* ws, hipStream_t s);
+                           void* ws, size_t ws_bytes, hipStream_t s);
 
 pct_status launch_zero(float* p, long long n, hipStream_t s);
 

@@ -744,6 +744,33 @@ def case_traj_value_grad():
         qv, fv = qx.get(int(np.prod(shape)), np.int64), fl.get(int(np.prod(shape)), np.float32)
         np.testing.assert_allclose(qv * 2.0 ** -32, fv, rtol=1e-5, atol=2e-5 * max(1.0, float(np.abs(fv).max())))
     assert L.pct_fixed_to_float(P(gz2x), n, P(gz2x), None) == abi.PCT_ERR_ARG
+    # waypoints shuffled over each profile's trajectories and slices: rounds
+    # whose windows do not share one box take the per-lane path; f and dL/dwp
+    # still equal the per-profile path's
+    rng = np.random.default_rng(5)
+    wps_s = wp_all.reshape(len(profiles), -1, 3).copy()
+    sls_s = sl_all.reshape(len(profiles), -1).copy()
+    for i in range(len(profiles)):
+        perm = rng.permutation(wps_s.shape[1])
+        wps_s[i], sls_s[i] = wps_s[i][perm], sls_s[i][perm]
+    wps_s = np.ascontiguousarray(wps_s.reshape(wp_all.shape))
+    sls_s = np.ascontiguousarray(sls_s.reshape(sl_all.shape))
+    f1s, gwp1s = [], []
+    for i, r in enumerate(profiles):
+        cost, _ = evaluate(G, Cc, grid, e, [r], keep=False)
+        wpb1, slb1, gfb1 = Buf.of(wps_s[i]), Buf.of(sls_s[i]), Buf.of(gf_all[i])
+        f1s.append(sample_fwd(cost, G, grid, e, r, w_z, wpb1, slb1, T, W))
+        gz1s = Buf(8 * n)
+        gwp1s.append(traj_bwd(G, Cc, cost, aG, aC, grid, e, r, w_z, wpb1, slb1, T, W, gfb1, n, gz1s,
+                              abi.PCT_FIXED_POINT))
+    f2s, gwp2s, gz2s = Buf(4 * len(profiles) * T), Buf(12 * wp_all[..., 0].size), Buf(8 * n)
+    wpbs, slbs = Buf.of(wps_s), Buf.of(sls_s)   # named: a temporary would be freed before the call
+    check("multi shuffled", L.pct_trajectory_cost_multi(P(G), P(Cc), P(aG), P(aC), C.byref(g), C.byref(e), rs,
+                                                        len(profiles), w_z, P(wpbs), P(slbs), T, W, P(gfb), P(f2s),
+                                                        P(gwp2s), None, None, n, P(gz2s), abi.PCT_FIXED_POINT, P(ws),
+                                                        ws.nbytes, None))
+    np.testing.assert_array_equal(bits(f2s.get((len(profiles), T), np.float32)), bits(np.stack(f1s)))
+    np.testing.assert_array_equal(bits(gwp2s.get(wp_all.shape, np.float32)), bits(np.stack(gwp1s)))
     # values only: the same f, gradients untouched
     f3 = Buf(4 * len(profiles) * T)
     check("multi value", L.pct_trajectory_cost_multi(P(G), P(Cc), None, None, C.byref(g), C.byref(e), rs,
