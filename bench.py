@@ -734,9 +734,11 @@ def main():
                      "unit": "GB/s", "frac": eval_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": eval_bytes, "bytes_per_cell_slice": 12, "kernel_ms": ms_eval_kernel,
                      "valu_counted_ops": {"note": "the method's FP32 operations counted per cell-slice, over the "
-                                                  "non-packed FP32 issue rate of the chip; the kernel issues "
-                                                  "fewer instructions than counted (weights of exactly 1 and 0 "
-                                                  "skip their multiplies)",
+                                                  "non-packed FP32 issue rate of the chip; not a measure of the "
+                                                  "kernel: it issues fewer instructions than counted (weights of "
+                                                  "exactly 1 and 0 skip their multiplies, rows whose outputs are "
+                                                  "known to be c^B skip their inflation), so this can exceed 1; "
+                                                  "issued counts are in profiles/valu-config1-20M-map.txt",
                                           "ops_per_cell_slice": eval_ops_per_cell(R), "achieved_tops": eval_tops,
                                           "issue_peak_tops": VALU_PEAK_TOPS, "frac": eval_tops / VALU_PEAK_TOPS}},
         "wall_s_timed": c1["wall_s_timed"],
