@@ -706,13 +706,13 @@ pct_status make_items(const pct_item* h, int n_items, int64_t n_total, bool need
         if (n_total > (int64_t)INT32_MAX) return fail(PCT_ERR_ARG, "point count outside [0, 2^31)");
         BuildItemDev& d = (*out)[i];
         d.g = make_grid_dev(h[i].grid);
-        if (tuned) {
+        if (h[i].grid.nx <= 128) {
+            // narrow submap: 512-cell tiles as wide as the map
+            const int tw = h[i].grid.nx <= 64 ? 64 : 128;
+            d.g = tile_shape(d.g, tw, 512 / tw);
+        } else if (tuned) {
             const int th = batch_build_th(size_class(h[i].grid.nx), size_class(h[i].grid.ny));
-            if (th > d.g.th) {
-                d.g.th = th;
-                d.g.nty = (d.g.ny + th - 1) / th;
-                d.g.ntiles = d.g.ntx * d.g.nty;
-            }
+            if (th > d.g.th) d.g = tile_shape(d.g, d.g.tw, th);
         }
         d.xyz_off = h[i].xyz_offset;
         d.n = h[i].n_points;
@@ -912,8 +912,9 @@ pct_status pct_autotune_batched(const float* d_xyz, int64_t n_total, const pct_i
                                               ws_bytes, s);
         };
         const int n_before = (int)rep.size();
-        // construction tile height, once per (class x, class y)
-        if (!built[{cx, cy}]) {
+        // construction tile height, once per (class x, class y), for maps
+        // wider than 128 cells (narrower ones take tiles as wide as the map)
+        if (!built[{cx, cy}] && cx >= 8) {
             built[{cx, cy}] = true;
             int th_min = 2;
             for (const pct_item& t : sub) th_min = std::max(th_min, make_grid_dev(t.grid).th);

@@ -161,9 +161,9 @@ __device__ __forceinline__ bool bin_xyz(float x, float y, float zin, const GridD
     int ix, iy;
     if (!isfinite(z) || !rasterize(x, y, g, ix, iy)) return false;
     z = z + 0.0f;
-    int tx = ix / kBuildTileW, ty = iy / g.th;
+    int tx = ix / g.tw, ty = iy / g.th;
     tile = ty * g.ntx + tx;
-    cell = (unsigned)((iy - ty * g.th) * kBuildTileW + (ix - tx * kBuildTileW));
+    cell = (unsigned)((iy - ty * g.th) * g.tw + (ix - tx * g.tw));
     return true;
 }
 
@@ -174,9 +174,9 @@ __device__ __forceinline__ bool bin_point(const float* __restrict__ xyz, int64_t
     int ix, iy;
     if (!isfinite(z) || !rasterize(x, y, g, ix, iy)) return false;
     z = z + 0.0f;
-    int tx = ix / kBuildTileW, ty = iy / g.th;
+    int tx = ix / g.tw, ty = iy / g.th;
     tile = ty * g.ntx + tx;
-    cell = (unsigned)((iy - ty * g.th) * kBuildTileW + (ix - tx * kBuildTileW));
+    cell = (unsigned)((iy - ty * g.th) * g.tw + (ix - tx * g.tw));
     return true;
 }
 
@@ -240,7 +240,7 @@ struct BinPlan {
 
 BinPlan make_bin_plan(int64_t n, const GridDev& g) {
     BinPlan b{};
-    b.CT = kBuildTileW * g.th;
+    b.CT = g.tw * g.th;
     int64_t G = (g.ntiles + kSuperTarget - 1) / kSuperTarget;
     if (G < 1) G = 1;
     if (G > kMaxSuperG) G = kMaxSuperG;
@@ -785,7 +785,7 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
                             float zmin, float ds, int N, float* __restrict__ ground, float* __restrict__ ceil,
                             int* __restrict__ ag, int* __restrict__ ac, int CAP, int id_base = 0) {
     extern __shared__ unsigned s_mem[];
-    const int cells = kBuildTileW * g.th;
+    const int cells = g.tw * g.th;
     unsigned* s_cnt = s_mem;                 // cells
     unsigned* s_start = s_cnt + cells;       // cells + 1
     float* s_z = (float*)(s_start + cells + 1);
@@ -840,8 +840,8 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
         const int c_hi = hi;
         const unsigned g0 = s_start[c_lo];
         if (c_hi == c_lo + 1 && s_start[c_hi] - g0 > (unsigned)CAP) {
-            const int ix = tx * kBuildTileW + (c_lo % kBuildTileW);
-            const int iy = ty * g.th + c_lo / kBuildTileW;
+            const int ix = tx * g.tw + (c_lo % g.tw);
+            const int iy = ty * g.th + c_lo / g.tw;
             huge_cell<IDS, MERGE>((unsigned)c_lo, r0, r1, rz, rmeta, rid, ix, iy, g, zmin, ds, N, ground, ceil, ag, ac,
                                   id_base);
         } else {
@@ -856,8 +856,8 @@ __device__ void reduce_tile(int tg, int tl, const unsigned* __restrict__ off, co
             }
             __syncthreads();
             for (int c = c_lo + threadIdx.x; c < c_hi; c += kReduceBlock) {
-                const int ix = tx * kBuildTileW + (c % kBuildTileW);
-                const int iy = ty * g.th + c / kBuildTileW;
+                const int ix = tx * g.tw + (c % g.tw);
+                const int iy = ty * g.th + c / g.tw;
                 if (ix >= g.nx || iy >= g.ny) continue;
                 const unsigned s = s_start[c] - g0;
                 sweep_cell<IDS, MERGE>(s_z + s, s_id + s, (int)(s_start[c + 1] - s_start[c]), ix, iy, g, zmin, ds,
@@ -890,7 +890,7 @@ inline int reduce_cap(int64_t n, const GridDev& g, bool ids) {
 }
 
 inline size_t reduce_lds_bytes(const GridDev& g, bool ids, int cap) {
-    const int cells = kBuildTileW * g.th;
+    const int cells = g.tw * g.th;
     return sizeof(unsigned) * (2 * cells + 1) + (size_t)cap * (ids ? 8 : 4);
 }
 
@@ -1411,10 +1411,20 @@ GridDev make_grid_dev(const pct_grid& gr) {
     g.ny = gr.ny;
     g.fnx = (float)gr.nx;
     g.fny = (float)gr.ny;
+    g.tw = kBuildTileW;
     g.ntx = (gr.nx + kBuildTileW - 1) / kBuildTileW;
     g.th = 2;
     while (g.th < 8 && (int64_t)g.ntx * ((gr.ny + g.th - 1) / g.th) > kMaxLdsTiles) g.th *= 2;
     g.nty = (gr.ny + g.th - 1) / g.th;
+    g.ntiles = g.ntx * g.nty;
+    return g;
+}
+
+GridDev tile_shape(GridDev g, int tw, int th) {
+    g.tw = tw;
+    g.th = th;
+    g.ntx = (g.nx + tw - 1) / tw;
+    g.nty = (g.ny + th - 1) / th;
     g.ntiles = g.ntx * g.nty;
     return g;
 }
@@ -1468,7 +1478,7 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
     Digest dg;
     for (int i = 0; i < n_items; ++i) {
         const BuildItemDev& d = h_items[i];
-        dg.add(d.g.x0), dg.add(d.g.y0), dg.add(d.g.res), dg.add(d.g.nx), dg.add(d.g.ny), dg.add(d.g.th);
+        dg.add(d.g.x0), dg.add(d.g.y0), dg.add(d.g.res), dg.add(d.g.nx), dg.add(d.g.ny), dg.add(d.g.th), dg.add(d.g.tw);
         dg.add(d.g.ntiles), dg.add(d.xyz_off), dg.add(d.n), dg.add(d.zmin), dg.add(d.ds), dg.add(d.N);
         dg.add(d.out_off), dg.add(d.tile_base), dg.add(d.chunk_base), dg.add(d.echunk_base);
     }
@@ -1479,16 +1489,15 @@ pct_status launch_build_batched(const float* xyz, const BuildItemDev* h_items, i
         PCT_HIP(hipMemcpyAsync(w.items, h_items, sizeof(BuildItemDev) * n_items, hipMemcpyHostToDevice, s));
         PCT_HIP(hipStreamSynchronize(s));
     }
-    int max_tiles_lds = 0, max_th = 1, cap = 0;
+    int max_tiles_lds = 0, cap = 0;
     for (int i = 0; i < n_items; ++i) {
         if (h_items[i].g.ntiles <= kMaxLdsTiles) max_tiles_lds = std::max(max_tiles_lds, h_items[i].g.ntiles);
-        max_th = std::max(max_th, h_items[i].g.th);
         cap = std::max(cap, reduce_cap(h_items[i].n, h_items[i].g, ids));
     }
     cap = std::max(cap, ids ? kReduceCapIds : kReduceCap);
-    GridDev g_lds{};
-    g_lds.th = max_th;
-    const size_t max_reduce_lds = reduce_lds_bytes(g_lds, ids, cap);
+    // the largest tile (tw x th cells) of any item sizes the counters
+    size_t max_reduce_lds = 0;
+    for (int i = 0; i < n_items; ++i) max_reduce_lds = std::max(max_reduce_lds, reduce_lds_bytes(h_items[i].g, ids, cap));
     if (pct_status st = allow_lds(ids ? (const void*)k_breduce<true> : (const void*)k_breduce<false>, max_reduce_lds))
         return st;
     hipLaunchKernelGGL(k_fill_u32, dim3(std::min(1024, w.total_tiles / kBlock + 1)), dim3(kBlock), 0, s, w.count,

@@ -31,10 +31,12 @@ void clear_error();
 __host__ __device__ inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- grids
-// Construction tiles are 256 cells wide (each output row of a tile is one
-// contiguous 1 KB run per slice) and `th` cells tall; th grows with the grid
-// so that the tile count fits the LDS-privatised counters of the binning
-// kernels.
+// Construction tiles are `tw` cells wide, 256 by default (each output row
+// of a tile is one contiguous 1 KB run per slice), and `th` cells tall; th
+// grows with the grid so that the tile count fits the LDS-privatised
+// counters of the binning kernels.  Batched submaps narrower than 256 cells
+// take tiles of 64 or 128 cells by 8 or 4, so that most of a tile's 512
+// cells lie inside the map.
 constexpr int kBuildTileW = 256;
 constexpr int kMaxLdsTiles = 8192;
 
@@ -43,9 +45,11 @@ struct GridDev {
     int nx, ny;
     int th, ntx, nty;   // construction tiling
     int ntiles;
+    int tw;
 };
 
 GridDev make_grid_dev(const pct_grid& g);
+GridDev tile_shape(GridDev g, int tw, int th);
 
 // On-device rasterisation (Sec. III-A): one FP32 subtraction and one
 // correctly rounded FP32 division per axis, then the half-open range test.

@@ -554,8 +554,14 @@ def case_batch_tune():
     those before; resident tables of other shapes are refused; the tables
     survive a save and load, and a malformed file applies nothing."""
     import tempfile
-    # small items: the tuner runs every distinct candidate four times per class
+    # small items (the tuner runs every distinct candidate four times per
+    # class) and one wider than 128 cells, whose class tunes its tile height
     items_sc, pts, specs = make_batch(64, 2, side_hi=24, pts_hi=3_000, extra_empty=True)
+    wide = scenes.multistorey_scene(66, 14.0, 1.2, 4_000, n_floors=2)
+    assert wide.grid["nx"] > 128
+    specs.append(dict(xyz_offset=len(pts), n_points=len(wide.points), grid=wide.grid))
+    pts = np.ascontiguousarray(np.concatenate([pts, wide.points]))
+    items_sc.append(wide)
     rb = robot()
     L.pct_autotune_reset()
     _, before = batch_run(pts, specs, [rb], True)
@@ -569,9 +575,13 @@ def case_batch_tune():
                                                      None))
     es = list(ent[:cnt.value])
     classes = {(e.stage, e.class_x, e.class_y, e.radius) for e in es}
-    # three tile heights; strip shapes that launch the same strips are timed once
-    assert cnt.value >= 3 + 2 and len(classes) >= 2
-    assert len({(e.rows, e.waves) for e in es if e.stage == 1}) == sum(e.stage == 1 for e in es)
+    # three tile heights for the wide class only; strip shapes that launch
+    # the same strips are timed once
+    assert sum(e.stage == 0 for e in es) == 3 and all(e.class_x >= 8 for e in es if e.stage == 0)
+    assert len(classes) >= 3
+    for c in {(e.class_x, e.class_y, e.radius) for e in es if e.stage == 1}:
+        shapes = [(e.rows, e.waves) for e in es if e.stage == 1 and (e.class_x, e.class_y, e.radius) == c]
+        assert len(set(shapes)) == len(shapes), (c, shapes)
     for c in classes:
         assert sum(e.chosen for e in es if (e.stage, e.class_x, e.class_y, e.radius) == c) == 1, c
         assert all(e.ms > 0 for e in es if (e.stage, e.class_x, e.class_y, e.radius) == c)
@@ -589,19 +599,23 @@ def case_batch_tune():
         if st_ == 0:
             lines.append(f"cpu-emulator batch_build {cx} {cy} {4 if ch[0] == 8 else 8}")
         else:
-            lines.append(f"cpu-emulator batch_eval {cx} {cy} {R} {64 if ch == (32, 1) else 32} 1")
+            lines.append(f"cpu-emulator batch_eval {cx} {cy} {R} " + ("32 1" if ch == (64, 4) else "64 4"))
     lines.append("otherarch batch_build 1 1 4")
     with open(path, "w") as fp:
         fp.write("\n".join(lines) + "\n")
     ws = Buf(L.pct_batch_workspace_bytes(items, n_items, 1, 1))
     tc = sum(it.extent.n_slices * it.grid.nx * it.grid.ny for it in items)
     G, Cc, aG, aC = Buf(4 * tc), Buf(4 * tc), Buf(4 * tc), Buf(4 * tc)
+    cost1, kp1 = Buf(4 * tc), Buf(sum(it.extent.n_slices for it in items))
     build_args = lambda fl: (P(xb), len(pts), items, n_items, P(G), P(Cc), P(aG), P(aC), fl, P(ws), ws.nbytes, None)
+    eval_args = lambda fl: (P(G), P(Cc), items, n_items, rs, 1, P(cost1), P(kp1), fl, P(ws), ws.nbytes, None)
     check("build_batched", L.pct_build_tomogram_batched(*build_args(0)))
+    check("eval_batched", L.pct_eval_traversability_batched(*eval_args(0)))
     n_ap = C.c_int32()
     check("autotune_load", L.pct_autotune_load(path.encode(), C.byref(n_ap)))
     assert n_ap.value == len(classes)
     assert L.pct_build_tomogram_batched(*build_args(abi.PCT_DESCRIPTORS_RESIDENT)) == abi.PCT_ERR_ARG
+    assert L.pct_eval_traversability_batched(*eval_args(abi.PCT_DESCRIPTORS_RESIDENT)) == abi.PCT_ERR_ARG
     check("build_batched", L.pct_build_tomogram_batched(*build_args(0)))
     check("build_batched", L.pct_build_tomogram_batched(*build_args(abi.PCT_DESCRIPTORS_RESIDENT)))
     np.testing.assert_array_equal(bits(G.get(tc, np.float32)), bits(before["G"][:tc]))
