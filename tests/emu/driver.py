@@ -263,6 +263,35 @@ def case_slice_runs():
                 f"longest run over a traversable cell {longest}, {int(k1[i].sum())} kept; both slice tests agree")
 
 
+def case_static_many_slices():
+    """About a thousand slices on a small map: the static-scratch entry point
+    then holds one copy of the run starts (its array is nearly filled by the
+    N x N bit matrix) while a sized workspace holds sixteen; both give the
+    same costs and keep flags, admissible under the oracle's slice test."""
+    xs, ys = np.meshgrid((np.arange(16) + 0.5) * 0.1, (np.arange(12) + 0.5) * 0.1)
+    shelves = np.concatenate([np.column_stack([xs.ravel(), ys.ravel(), np.full(xs.size, z)])
+                              for z in (2.5, 5.0, 7.5)])
+    sc = scenes.dense_surface_scene(16, 12, 0.1, lambda x, y: 0.02 * x, per_cell=4, slice_dz=0.01,
+                                    extra=[shelves.astype(np.float32),
+                                           np.array([[0.05, 0.05, 9.9]], np.float32)])
+    e, tm, dev = tomogram_case(sc.points, sc.grid, ids=False, label="thousand slices")
+    assert e.n_slices > 960, e.n_slices
+    r = robot()
+    cost, kp = evaluate(dev[0], dev[1], sc.grid, e, [r])
+    cells = e.n_slices * sc.grid["nx"] * sc.grid["ny"]
+    g = grid_s(sc.grid)
+    rs = (abi.pct_robot * 1)(robot_s(r))
+    cost2, kp2 = Buf(4 * cells), Buf(e.n_slices)
+    check("eval static", L.pct_eval_traversability_static(P(dev[0]), P(dev[1]), C.byref(g), C.byref(e), rs, 1,
+                                                          P(cost2), P(kp2), None))
+    np.testing.assert_array_equal(bits(cost2.get(cells, np.float32)), bits(cost.get(cells, np.float32)))
+    k1 = kp.get(e.n_slices, np.uint8)
+    np.testing.assert_array_equal(kp2.get(e.n_slices, np.uint8), k1)
+    c = cost.get((e.n_slices, sc.grid["ny"], sc.grid["nx"]), np.float32).astype(np.float64)
+    assert oracle.simplify_check(tm["ground"], c, c, r["c_barrier"], 0.0, k1) == -1
+    say(f"static scratch at N={e.n_slices}: the same costs and {int(k1.sum())} kept slices as a sized workspace")
+
+
 def case_crowded_cells():
     """Four adjacent cells whose records fit in the tile reduce's LDS one by
     one but not together (1500 points each), beside ordinary cells, on a

@@ -59,7 +59,7 @@ def run_cases(cases, order="fwd", timeout=900):
 
 
 GROUPS = [
-    (("tiny", "edges", "config0", "multirobot", "fallback_eval"), "rev"),
+    (("tiny", "edges", "config0", "multirobot", "fallback_eval", "static_many_slices"), "rev"),
     (("slice_runs", "crowded_cells", "dense_tiles", "unaligned_points"), "rand"),
     (("crop", "dense", "multirobot_large"), "rand"),
     (("many_chunks", "two_level"), "fwd"),
