@@ -9,6 +9,7 @@
 //   c^T(x, y) = max_a max(V_a(x-a, y), V_a(x+a, y))             (row pass)
 // Each product K * c is the same FP32 multiply as in the direct 2-D window
 // and max is exact, so the result equals the direct FP32 window max.
+#include <limits.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -603,17 +604,29 @@ pct_status launch_eval_r(const float* ground, const float* ceil, const EvalParam
 // bit matrix of the in-run slices p with c_p > c_k.  A single thread then
 // runs the sequential chain over these N x N bits.
 
+// Reductions over a whole wavefront (every lane active) by DPP moves:
+// row_shr 1, 2, 4, 8 leave each row's result in its lane 15, row_bcast:15
+// into rows 1 and 3 and row_bcast:31 into rows 2 and 3 leave the
+// wavefront's in lane 63.  Lanes whose source is outside their row, and
+// rows outside the row mask, take the identity `id` instead.
+template <class Op>
+__device__ __forceinline__ int wave_reduce_dpp(int v, int id, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
 __device__ __forceinline__ int wave_max_i(int v) {
-    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
-    return v;
+    return wave_reduce_dpp(v, INT_MIN, [](int a, int b) { return max(a, b); });
 }
 __device__ __forceinline__ int wave_min_i(int v) {
-    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
-    return v;
+    return wave_reduce_dpp(v, INT_MAX, [](int a, int b) { return min(a, b); });
 }
 __device__ __forceinline__ unsigned wave_or(unsigned v) {
-    for (int m = 32; m >= 1; m >>= 1) v |= __shfl_xor(v, m, 64);
-    return v;
+    return (unsigned)wave_reduce_dpp((int)v, 0, [](int a, int b) { return a | b; });
 }
 
 __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, unsigned* __restrict__ urun,

@@ -163,9 +163,17 @@ bool try_wave(int w) {
             case OP_BALLOT: f.res = ballot; break;
             case OP_READFIRSTLANE: f.res = S.f[l0 + first].val; break;
             case OP_DPP: {
+                const int ctrl = f.arg & 0xfff, rmask = (f.arg >> 12) & 0xf, row = l / 16;
+                if (!((rmask >> row) & 1)) {   // row not written
+                    f.res = f.old;
+                    break;
+                }
                 int src;
-                if (f.arg == 0x138) src = l - 1;        // wave_shr:1
-                else if (f.arg == 0x130) src = l + 1;   // wave_shl:1
+                if (ctrl == 0x138) src = l - 1;                                   // wave_shr:1
+                else if (ctrl == 0x130) src = l + 1;                              // wave_shl:1
+                else if (ctrl > 0x110 && ctrl <= 0x11f) src = (l % 16 >= (ctrl & 0xf)) ? l - (ctrl & 0xf) : -1;  // row_shr
+                else if (ctrl == 0x142) src = row >= 1 ? 16 * row - 1 : -1;       // row_bcast:15
+                else if (ctrl == 0x143) src = row >= 2 ? 31 : -1;                 // row_bcast:31
                 else die("unsupported DPP control");
                 f.res = (src >= 0 && src < 64 && live(src)) ? S.f[l0 + src].val : f.old;
                 break;

@@ -162,9 +162,17 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
 inline unsigned long long __ballot(int pred) { return emu::wave_op(emu::OP_BALLOT, pred ? 1u : 0u, 0, 0); }
 // Lanes whose source lane is outside the wavefront or inactive get `old`,
 // or 0 with bound_ctrl.
+// DPP moves: wave_shr:1, wave_shl:1, row_shr:1..15, row_bcast:15 and
+// row_bcast:31; lanes of rows outside row_mask keep `old` (so a row mask
+// needs bound_ctrl off, where invalid sources give `old` too).
 inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
-    if (row_mask != 0xf || bank_mask != 0xf) __builtin_trap();
-    return emu::from_bits<int>(emu::wave_op(emu::OP_DPP, emu::to_bits(src), ctrl, emu::to_bits(bound_ctrl ? 0 : old)));
+    if (bank_mask != 0xf || (row_mask != 0xf && bound_ctrl)) __builtin_trap();
+    return emu::from_bits<int>(emu::wave_op(emu::OP_DPP, emu::to_bits(src), ctrl | (row_mask << 12),
+                                            emu::to_bits(bound_ctrl ? 0 : old)));
+}
+template <class T>
+inline T emu_readlane(T v, int lane) {
+    return emu::from_bits<T>(emu::wave_op(emu::OP_SHFL, emu::to_bits(v), lane, 0));
 }
 inline int emu_readfirstlane(int v) { return emu::from_bits<int>(emu::wave_op(emu::OP_READFIRSTLANE, emu::to_bits(v), 0, 0)); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
@@ -173,6 +181,7 @@ inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 #define __builtin_amdgcn_update_dpp emu_update_dpp
 #define __builtin_nontemporal_store(v, p) (void)(*(p) = (v))
 #define __builtin_amdgcn_readfirstlane emu_readfirstlane
+#define __builtin_amdgcn_readlane emu_readlane
 
 // Raw buffer access (stride 0): offset = voffset + soffset bytes from the
 // descriptor's base.  The hardware returns 0 for reads and drops writes
