@@ -185,30 +185,66 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(unsigned* __restrict__ p, i
         p[i] = v;
 }
 
+// Exclusive scan over a workgroup of one value per thread (every thread
+// calls it): the thread's prefix, and the workgroup's total in `total`.
+// Inclusive scans within each wavefront by shuffles, then the wavefront
+// totals through LDS (s_w: one word per wavefront).
+__device__ __forceinline__ unsigned block_scan_excl(unsigned v, unsigned* s_w, unsigned& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    unsigned incl = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned u = __shfl(incl, lane - d, 64);
+        if (lane >= d) incl += u;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    unsigned before = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        const unsigned t = s_w[i];
+        tot += t;
+        if (i < w) before += t;
+    }
+    __syncthreads();   // s_w is free again
+    total = tot;
+    return before + incl - v;
+}
+
+// Exclusive scan of len counts into out (which may be cnt itself) by one
+// workgroup of 1024 threads, in rounds of four consecutive counts per
+// thread (loaded together); returns the total.  cursor (nullable) receives
+// the offsets too.
+__device__ unsigned block_scan_counts(const unsigned* cnt, unsigned* out, unsigned* cursor, int len) {
+    __shared__ unsigned s_w[16];
+    unsigned carry = 0;
+    for (int base = 0; base < len; base += 4 * 1024) {
+        const int i0 = base + 4 * (int)threadIdx.x;
+        unsigned v[4], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = i0 + q < len ? cnt[i0 + q] : 0u;
+            sum += v[q];
+        }
+        unsigned total;
+        unsigned run = carry + block_scan_excl(sum, s_w, total);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (i0 + q < len) {
+                out[i0 + q] = run;
+                if (cursor) cursor[i0 + q] = run;
+            }
+            run += v[q];
+        }
+        carry += total;
+    }
+    return carry;
+}
+
 // Exclusive scan of the tile counts (one workgroup): off[0..ntiles], and
 // the scatter cursors start at the offsets.
 __global__ __launch_bounds__(1024) void k_scan_tiles(const unsigned* __restrict__ cnt, int ntiles,
                                                      unsigned* __restrict__ off, unsigned* __restrict__ cursor) {
-    __shared__ unsigned s_part[1024];
-    const int per = (ntiles + 1023) / 1024;
-    const int b = threadIdx.x * per, e = min(b + per, ntiles);
-    unsigned sum = 0;
-    for (int i = b; i < e; ++i) sum += cnt[i];
-    s_part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        unsigned v = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0u;
-        __syncthreads();
-        s_part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    unsigned run = s_part[threadIdx.x] - sum;
-    for (int i = b; i < e; ++i) {
-        off[i] = run;
-        cursor[i] = run;
-        run += cnt[i];
-    }
-    if (threadIdx.x == 1023) off[ntiles] = s_part[1023];
+    const unsigned total = block_scan_counts(cnt, off, cursor, ntiles);
+    if (threadIdx.x == 0) off[ntiles] = total;
 }
 
 // Two-level binning into construction tiles (a stable-free counting sort).
@@ -308,13 +344,12 @@ __device__ unsigned wave_scan_row(unsigned* __restrict__ row, int len) {
     return carry;
 }
 
-// Level-1 rows: bucket s scans its row of cnt1; the total goes to tot1[s].
-__global__ __launch_bounds__(kBlock) void k_bin1_rows(unsigned* __restrict__ cnt1, int nb1, int S1,
-                                                      unsigned* __restrict__ tot1) {
-    const int s = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x / 64);
-    if (s >= S1) return;
-    const unsigned t = wave_scan_row(cnt1 + (int64_t)s * nb1, nb1);
-    if ((threadIdx.x & 63) == 0) tot1[s] = t;
+// Level-1 rows: bucket s (one workgroup of 1024 per bucket) scans its row
+// of cnt1 in place; the total goes to tot1[s].
+__global__ __launch_bounds__(1024) void k_bin1_rows(unsigned* __restrict__ cnt1, int nb1, unsigned* __restrict__ tot1) {
+    unsigned* row = cnt1 + (int64_t)blockIdx.x * nb1;
+    const unsigned t = block_scan_counts(row, row, nullptr, nb1);
+    if (threadIdx.x == 0) tot1[blockIdx.x] = t;
 }
 
 // One workgroup: super-tile offsets off1[0..S1] and the level-2 workgroup
@@ -1252,7 +1287,7 @@ pct_status launch_build(const float* xyz, int64_t n, const GridDev& g, float zmi
         const size_t l1 = sizeof(unsigned) * (size_t)b.S1;
         hipLaunchKernelGGL(k_bin1_hist, dim3(b.nb1), dim3(kBinBlock), l1, s, xyz, n, g, b.G, b.S1, b.nb1, w.cnt1);
         PCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_bin1_rows, dim3((b.S1 + 3) / 4), dim3(kBlock), 0, s, w.cnt1, b.nb1, b.S1, w.tot1);
+        hipLaunchKernelGGL(k_bin1_rows, dim3(b.S1), dim3(1024), 0, s, w.cnt1, b.nb1, w.tot1);
         PCT_LAUNCH_CHECK();
         if (!b.two_level) {
             hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, w.tot1, g.ntiles, w.off, w.cursor);
