@@ -155,38 +155,13 @@ struct WinMax {
     Cinit q;
 };
 
-__device__ WinMax window_max(const float* __restrict__ gk, const float* __restrict__ ck, int x, int y,
-                             const EvalParams& p) {
-    WinMax o{};
-    o.v = -INFINITY;
-    const int nx = p.nx, ny = p.ny, R = p.R;
-    for (int n = -R; n <= R; ++n) {
-        const int qy = y + n;
-        if (qy < 0 || qy >= ny) continue;
-        for (int m = -R; m <= R; ++m) {
-            const int qx = x + m;
-            const float kw = p.K[abs(m)][abs(n)];
-            if (kw <= 0.0f || qx < 0 || qx >= nx) continue;
-            const Cinit c = cinit_at(gk, ck, qx, qy, p);
-            const float v = kw * c.ci;
-            if (v > o.v) {
-                o.v = v;
-                o.k = kw;
-                o.qx = qx;
-                o.qy = qy;
-                o.q = c;
-            }
-        }
-    }
-    return o;
-}
-
-// window_max for the four bilinear corners of a waypoint at once: corners
-// (cx[c], cy[c]) lie in a 2 x 2 block, so their windows share most cells.
-// The union of the windows is walked once in row-major order, computing
-// each cell's c^init once; every cell updates the corners whose window holds
-// it.  Row-major order over the union is row-major order over each corner's
-// window, so each corner gets the same first maximum as window_max.
+// The window maxima of the four bilinear corners of a waypoint at once:
+// corners (cx[c], cy[c]) lie in a 2 x 2 block, so their windows share most
+// cells.  The union of the windows is walked once in row-major order,
+// computing each cell's c^init once; every cell updates the corners whose
+// window holds it.  Row-major order over the union is row-major order over
+// each corner's window, so each corner gets the same first maximum as a walk
+// over its own window.
 __device__ void window_max4(const float* __restrict__ gk, const float* __restrict__ ck, const int (&cx)[4],
                             const int (&cy)[4], const EvalParams& p, WinMax (&o)[4]) {
     const int nx = p.nx, ny = p.ny, R = p.R;

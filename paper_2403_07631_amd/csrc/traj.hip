@@ -39,8 +39,6 @@ namespace pct {
 
 namespace {
 
-constexpr int kMaxM = PCT_MAX_PIECES;
-
 // On the unit interval, the quintic with end data x = (p0, v0, a0, p1, v1,
 // a1) has the monomial coefficients c0 = p0, c1 = v0, c2 = a0 / 2 and the
 // rows below for c3, c4, c5 (the inverse of the 6 x 6 end-condition
