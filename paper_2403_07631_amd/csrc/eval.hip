@@ -651,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_simp_init(int* __restrict__ maxp0, u
 // continues that run (ground is non-decreasing in k), any other starts a
 // run whose start is found, if a kept-slice test needs it, by reading the
 // ground below.
-constexpr int kSimpCells = 4;
+constexpr int kSimpCells = 2;
 
 template <int STRIDE>
 __device__ __forceinline__ void simp_flags_cells(const float* __restrict__ ground, const float* __restrict__ cost,
