@@ -440,7 +440,15 @@ __device__ __forceinline__ void eval_strip_item(const float* __restrict__ ground
             }
         }
     }
-    if (any_trav && lane == 0) atomicOr(&slice_bits[k >> 5], 1u << (k & 31));
+    if (any_trav && lane == 0) {
+        // the hundreds of strips of a slice with traversable cells end at
+        // about the same time, and atomics on one word queue behind each
+        // other: strips that find the bit set already leave it (a stale
+        // read only costs an atomic)
+        unsigned* word = &slice_bits[k >> 5];
+        const unsigned bit = 1u << (k & 31);
+        if ((*(volatile unsigned*)word & bit) == 0u) atomicOr(word, bit);
+    }
 }
 
 template <int R, int Q1, int Q0, int NW>
