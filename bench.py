@@ -69,9 +69,10 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, launch_bytes_alg):
+def load_traffic(kernel, strip_shape):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources."""
+    were taken on the current kernel sources and at the strip shape
+    (rows, waves) of the timed launch."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -79,6 +80,8 @@ def load_traffic(kernel, launch_bytes_alg):
         d = json.load(f)
     e = d.get(kernel)
     if not e or e.get("source_digest") != kernel_source_digest():
+        return None
+    if list(e.get("strip_shape", [])) != list(strip_shape):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -573,11 +576,12 @@ def bench_plan(P, torch, dev, steps, warmup, cpu=True):
     return out
 
 
-def bench_step(P, torch, dev, sc, rb, steps, warmup, label):
+def bench_step(P, torch, dev, sc, rb, steps, warmup, label, strip_shape=None):
     """The timed step on one map: extent (with its host read-back), tomogram
     construction, evaluation with inflation and the slice test, inputs
-    resident in HBM; the evaluation's strip shape is autotuned first.
-    Returns the timings and the last step's outputs."""
+    resident in HBM; the evaluation's strip shape is autotuned first, or set
+    to strip_shape = (rows, waves) when given.  Returns the timings and the
+    last step's outputs."""
     import ctypes
     grid = sc.grid
     xyz = torch.from_numpy(sc.points).to(dev)
@@ -588,8 +592,13 @@ def bench_step(P, torch, dev, sc, rb, steps, warmup, label):
     ws_e = torch.empty(P.lib().pct_eval_workspace_bytes(ctypes.byref(P.grid_struct(grid)), ctypes.byref(ext0), 1),
                        dtype=torch.uint8, device=dev)
     g0, c0, _, _ = P.pct_build_tomogram(xyz, grid, ext0, workspace=ws_b)
-    log(f"{label}: autotuning the evaluation's strip shape")
-    tuned, tune_ms = P.pct_autotune_traversability(g0, c0, grid, ext0, rb)
+    if strip_shape:
+        log(f"{label}: strip shape set to {strip_shape[0]} rows x {strip_shape[1]} wavefront(s)")
+        P.pct_autotune_set_traversability(grid, ext0, rb, strip_shape[0], strip_shape[1])
+        tuned, tune_ms = tuple(strip_shape), {}
+    else:
+        log(f"{label}: autotuning the evaluation's strip shape")
+        tuned, tune_ms = P.pct_autotune_traversability(g0, c0, grid, ext0, rb)
     del g0, c0
 
     def step():
@@ -648,7 +657,7 @@ def bench_step(P, torch, dev, sc, rb, steps, warmup, label):
                         "build": build_bytes / (ms_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "step": (eval_bytes + build_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
            "alg_bytes": {"eval": eval_bytes, "build": build_bytes},
-           "autotune": {"strip_rows": tuned[0], "strip_waves": tuned[1],
+           "autotune": {"strip_rows": tuned[0], "strip_waves": tuned[1], "set_not_tuned": bool(strip_shape),
                         "candidates_ms": {f"{r}x{w}": v for (r, w), v in tune_ms.items()}}}
     return res, xyz, (ext, g, c, cost, keep)
 
@@ -667,6 +676,10 @@ def main():
                          "and print them, for profiling; no benchmark line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--strip-shape", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
+                    metavar="ROWS,WAVES",
+                    help="set the 20M-point map's evaluation strip shape instead of autotuning it (for counter runs, "
+                         "whose instrumentation changes which shape the tuner picks)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
@@ -686,7 +699,8 @@ def main():
     sc = scenes.config1_scene()
     grid = sc.grid
     rb = P.robot_from_physical(sc.robot, grid["res"])
-    c1, xyz, (ext, g, c, cost, keep) = bench_step(P, torch, dev, sc, rb, args.steps, args.warmup, "20M-point map")
+    c1, xyz, (ext, g, c, cost, keep) = bench_step(P, torch, dev, sc, rb, args.steps, args.warmup, "20M-point map",
+                                                  strip_shape=args.strip_shape)
     n, N = c1["points"], c1["slices"]
     ms_eval_kernel = c1["stages_ms"]["eval_kernel"]
     eval_bytes = c1["alg_bytes"]["eval"]
@@ -695,7 +709,8 @@ def main():
     R = P.pct_kernel_radius(rb, grid["res"])
     eval_ops = eval_ops_per_cell(R) * cells
     eval_tops = eval_ops / (ms_eval_kernel * 1e-3) / 1e12
-    traffic = load_traffic("k_eval_strip", eval_bytes)
+    at = c1["autotune"]
+    traffic = load_traffic("k_eval_strip", (at["strip_rows"], at["strip_waves"]))
     if args.copy_calibration:
         log("copy calibration: 3 x 1 GiB device copy")
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
