@@ -478,6 +478,30 @@ struct EvalJob {
     int n_blocks;
 };
 
+// A job's slice-test scratch at ws + ws_off: the largest run starts (N
+// ints), the N x W bit matrix, then W words of slice marks (bit k: slice
+// k has a traversable cell), W = ceil(N / 32).
+struct JobScratch {
+    int* maxp0;
+    unsigned* urun;
+    unsigned* marks;
+};
+__host__ __device__ __forceinline__ size_t job_scratch_bytes(int N) {
+    const size_t W = (size_t)(N + 31) / 32;
+    return align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * W) +
+           align_up(sizeof(unsigned) * W);
+}
+__device__ __forceinline__ JobScratch job_scratch(char* ws, const EvalJob& jb) {
+    const int N = jb.p.N;
+    const size_t W = (size_t)(N + 31) / 32;
+    char* b = ws + jb.ws_off;
+    JobScratch js;
+    js.maxp0 = (int*)b;
+    js.urun = (unsigned*)(b + align_up(sizeof(int) * (size_t)N));
+    js.marks = (unsigned*)(b + align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * W));
+    return js;
+}
+
 __device__ __forceinline__ int find_job_block(const EvalJob* __restrict__ jobs, int n_jobs, int b) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -492,7 +516,7 @@ template <int R, int Q1, int Q0>
 __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restrict__ ground,
                                                             const float* __restrict__ ceil,
                                                             const EvalJob* __restrict__ jobs, int n_jobs, int n_blocks,
-                                                            float* __restrict__ cost) {
+                                                            float* __restrict__ cost, char* __restrict__ marks_ws) {
     static_assert(sizeof(WgLds<R, kDefaultWaves>) == (kBlock / 64) * sizeof(WgLds<R, 1>), "LDS of one-wave strips");
     __shared__ WgLds<R, kDefaultWaves> lds;
     const int per_xcd = gridDim.x / 8;
@@ -500,17 +524,19 @@ __global__ __launch_bounds__(kBlock) void k_eval_strip_jobs(const float* __restr
     if (b >= n_blocks) return;   // the whole workgroup
     const int j = __builtin_amdgcn_readfirstlane(find_job_block(jobs, n_jobs, b));
     const EvalJob& jb = jobs[j];
+    // slice marks for the slice test (marks_ws: the jobs' scratch, nullable)
+    unsigned* marks = marks_ws ? job_scratch(marks_ws, jb).marks : nullptr;
     if (jb.sg.nw > 1) {
         if (b - jb.block_base >= jb.n_blocks) return;
         eval_strip_item<R, Q1, Q0, kDefaultWaves>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off,
-                                                  jb.sg, b - jb.block_base, lds);
+                                                  jb.sg, b - jb.block_base, lds, marks);
     } else {
         const int wave = (int)(threadIdx.x >> 6);
         const int w = (b - jb.block_base) * (kBlock / 64) + wave;
         WgLds<R, 1>& mine = reinterpret_cast<WgLds<R, 1>*>(&lds)[wave];
         if (w < jb.sg.n_work)
             eval_strip_item<R, Q1, Q0, 1>(ground + jb.in_off, ceil + jb.in_off, jb.p, cost + jb.out_off, jb.sg, w,
-                                          mine);
+                                          mine, marks);
     }
 }
 
@@ -882,16 +908,16 @@ __device__ __forceinline__ int find_job_cell(const EvalJob* __restrict__ jobs, i
 __global__ __launch_bounds__(kBlock) void k_simp_init_jobs(const EvalJob* __restrict__ jobs, char* __restrict__ ws) {
     const EvalJob& jb = jobs[blockIdx.x];
     const int N = jb.p.N, W = (N + 31) / 32;
-    int* maxp0 = (int*)(ws + jb.ws_off);
-    unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    for (int i = threadIdx.x; i < N * W; i += kBlock) urun[i] = 0u;
-    for (int i = threadIdx.x; i < N; i += kBlock) maxp0[i] = -1;
+    const JobScratch js = job_scratch(ws, jb);
+    for (int i = threadIdx.x; i < N * W; i += kBlock) js.urun[i] = 0u;
+    for (int i = threadIdx.x; i < N; i += kBlock) js.maxp0[i] = -1;
+    for (int i = threadIdx.x; i < W; i += kBlock) js.marks[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restrict__ ground,
                                                             const float* __restrict__ cost,
                                                             const EvalJob* __restrict__ jobs, int n_jobs,
-                                                            char* __restrict__ ws) {
+                                                            char* __restrict__ ws, int marked) {
     // global padded cell of this lane's first cell; a wavefront's 64 x kSimpCells
     // cells never span two jobs (job ranges are padded to that)
     const long long wave0 = ((long long)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kSimpCells;
@@ -902,10 +928,10 @@ __global__ __launch_bounds__(kBlock) void k_simp_flags_jobs(const float* __restr
     const long long left = jb.p.plane - cell0;
     const int nact = (cell0 < 0 || left <= 0) ? 0 : (int)std::min<long long>(kSimpCells, (left + 63) / 64);
     const int N = jb.p.N, W = (N + 31) / 32;
-    int* maxp0 = (int*)(ws + jb.ws_off);
-    unsigned* urun = (unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    simp_flags_cells<64>(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, maxp0, urun,
-                         nact > 0 ? cell0 : 0, nact);
+    const JobScratch js = job_scratch(ws, jb);
+    // marked: the evaluation marked the slices with a traversable cell
+    simp_flags_cells<64>(ground + jb.in_off, cost + jb.out_off, jb.p.plane, N, jb.p.cB, W, js.maxp0, js.urun,
+                         nact > 0 ? cell0 : 0, nact, marked ? js.marks : nullptr);
 }
 
 __global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, const char* __restrict__ ws,
@@ -914,9 +940,8 @@ __global__ void k_keep_chain_jobs(const EvalJob* __restrict__ jobs, int n_jobs, 
     if (j >= n_jobs) return;
     const EvalJob& jb = jobs[j];
     const int N = jb.p.N, W = (N + 31) / 32;
-    const int* maxp0 = (const int*)(ws + jb.ws_off);
-    const unsigned* urun = (const unsigned*)(ws + jb.ws_off + align_up(sizeof(int) * (size_t)N));
-    keep_chain(maxp0, urun, N, W, keep + jb.keep_off);
+    const JobScratch js = job_scratch(const_cast<char*>(ws), jb);
+    keep_chain(js.maxp0, js.urun, N, W, keep + jb.keep_off);
 }
 
 }  // namespace
@@ -1308,7 +1333,7 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
             jb.block_base = jp->n_blocks;
             jb.n_blocks = jb.sg.nw > 1 ? jb.sg.n_work : (jb.sg.n_work + kBlock / 64 - 1) / (kBlock / 64);
             jp->cells += (jb.p.plane + 64 * kSimpCells - 1) / (64 * kSimpCells) * (64 * kSimpCells);
-            jp->scratch += align_up(sizeof(int) * (size_t)N) + align_up(sizeof(unsigned) * (size_t)N * ((N + 31) / 32));
+            jp->scratch += job_scratch_bytes(N);
             jp->n_blocks += jb.n_blocks;
             if (jp->R < 0) jp->R = jb.p.R;
             if (jb.p.R != jp->R || !strip_kernel_applies(jb.p)) jp->strip = false;
@@ -1320,10 +1345,10 @@ pct_status plan_jobs(const pct_item* items, int n_items, const pct_robot* robots
 
 template <int R, int Q1 = -1, int Q0 = kNoZeroTaps>
 pct_status launch_jobs_r(const float* ground, const float* ceil, const EvalJob* d_jobs, int n_jobs, int n_blocks,
-                         float* cost, hipStream_t s) {
+                         float* cost, char* marks_ws, hipStream_t s) {
     const int blocks = (n_blocks + 7) / 8 * 8;
     hipLaunchKernelGGL((k_eval_strip_jobs<R, Q1, Q0>), dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_jobs, n_jobs,
-                       n_blocks, cost);
+                       n_blocks, cost, marks_ws);
     PCT_LAUNCH_CHECK();
     return PCT_OK;
 }
@@ -1369,13 +1394,20 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
         PCT_HIP(hipMemcpyAsync(d_jobs, jp.jobs.data(), sizeof(EvalJob) * n_jobs, hipMemcpyHostToDevice, s));
         PCT_HIP(hipStreamSynchronize(s));
     }
+    // the slice test's scratch is cleared first: the strip kernels mark the
+    // slices with a traversable cell in it
+    if (keep) {
+        hipLaunchKernelGGL(k_simp_init_jobs, dim3(n_jobs), dim3(kBlock), 0, s, d_jobs, scratch);
+        PCT_LAUNCH_CHECK();
+    }
+    char* marks_ws = keep && jp.strip ? scratch : nullptr;
     if (jp.strip) {
         switch (jp.R) {
 #define PCT_J(r)                                                                                       \
     case r:                                                                                            \
         st = (jp.pattern && r >= 2)                                                                    \
-                 ? launch_jobs_r<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, d_jobs, n_jobs, jp.n_blocks, cost, s) \
-                 : launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_blocks, cost, s);                 \
+                 ? launch_jobs_r<r, (r - 2) * (r - 2), (r + 1) * (r + 1)>(ground, ceil, d_jobs, n_jobs, jp.n_blocks, cost, marks_ws, s) \
+                 : launch_jobs_r<r>(ground, ceil, d_jobs, n_jobs, jp.n_blocks, cost, marks_ws, s);                 \
         break;
             PCT_J(0) PCT_J(1) PCT_J(2) PCT_J(3) PCT_J(4) PCT_J(5) PCT_J(6) PCT_J(7) PCT_J(8)
 #undef PCT_J
@@ -1390,12 +1422,10 @@ pct_status launch_eval_batched(const float* ground, const float* ceil, const pct
         }
     }
     if (keep) {
-        hipLaunchKernelGGL(k_simp_init_jobs, dim3(n_jobs), dim3(kBlock), 0, s, d_jobs, scratch);
-        PCT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_simp_flags_jobs, dim3((unsigned)((jp.cells + (long long)kBlock * kSimpCells - 1) /
                                                              ((long long)kBlock * kSimpCells))),
                            dim3(kBlock), 0, s,
-                           ground, cost, d_jobs, n_jobs, scratch);
+                           ground, cost, d_jobs, n_jobs, scratch, marks_ws ? 1 : 0);
         PCT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_keep_chain_jobs, dim3((n_jobs + 63) / 64), dim3(64), 0, s, d_jobs, n_jobs, scratch, keep);
         PCT_LAUNCH_CHECK();
