@@ -878,18 +878,40 @@ __device__ void keep_chain(const int* __restrict__ maxp0, const unsigned* __rest
     }
 }
 
-// One workgroup of 64: the copies of the run starts merged per slice by
-// all lanes, then the chain on one lane.
+// One wavefront: the copies of the run starts merged per slice, then the
+// chain 64 slices at a time.  With p the last kept slice, the lanes test
+// the next 64 slices against p together; the first that passes is kept and
+// those before it are not (each would have been tested against the same
+// p), and the next step starts after it.  Steps: one per kept slice and
+// one per 64 slices, instead of one per slice.
 __global__ __launch_bounds__(64) void k_keep_chain(const int* __restrict__ maxp0, const unsigned* __restrict__ urun,
                                                    int N, int W, uint8_t* __restrict__ keep, int copies, int cstride) {
     __shared__ int s_m[PCT_MAX_SLICES];
-    for (int k = threadIdx.x; k < N; k += 64) {
+    const int lane = threadIdx.x;
+    for (int k = lane; k < N; k += 64) {
         int m = maxp0[k];
         for (int c = 1; c < copies; ++c) m = max(m, maxp0[c * cstride + k]);
         s_m[k] = m;
     }
     __syncthreads();
-    if (threadIdx.x == 0) keep_chain(s_m, urun, N, W, keep);
+    int p = -1, k0 = 0;   // uniform
+    while (k0 < N) {
+        const int k = k0 + lane;
+        bool u = false;
+        if (k < N) {
+            const int m = s_m[k];
+            u = p < 0 ? m >= 0 : (p < m || ((urun[(long long)k * W + p / 32] >> (p % 32)) & 1u) != 0u);
+        }
+        const unsigned long long b = __ballot(u);
+        const int f = b ? __ffsll((long long)b) - 1 : 64;   // the first kept lane, 64: none
+        if (k < N && lane <= f) keep[k] = lane == f ? 1 : 0;
+        if (f < 64) {
+            p = k0 + f;
+            k0 = p + 1;
+        } else {
+            k0 += 64;
+        }
+    }
 }
 
 // ---- batched slice test: one workgroup per job for the init and chain,
