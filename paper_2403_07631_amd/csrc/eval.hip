@@ -635,8 +635,9 @@ pct_status launch_eval_r(const float* ground, const float* ceil, const EvalParam
 // e^G_k (ground is non-decreasing in k), and inside that run only where
 // c_k < c_p.  The flags kernel therefore records, for every k, the largest
 // run start over the cells that are traversable and satisfy Eq. (9), and a
-// bit matrix of the in-run slices p with c_p > c_k.  A single thread then
-// runs the sequential chain over these N x N bits.
+// bit matrix of the in-run slices p with c_p > c_k.  The sequential chain
+// then runs over these N x N bits (one wavefront for a single map, one
+// thread per job in a batch).
 
 // Reductions over a whole wavefront (every lane active) by DPP moves:
 // row_shr 1, 2, 4, 8 leave each row's result in its lane 15, row_bcast:15
