@@ -81,9 +81,8 @@ def load_traffic(kernel, strip_shape):
     e = d.get(kernel)
     if not e or e.get("source_digest") != kernel_source_digest():
         return None
-    if list(e.get("strip_shape", [])) != list(strip_shape):
-        return None
-    return e.get("hbm_bytes_per_launch")
+    m = e.get("by_strip_shape", {}).get(f"{strip_shape[0]}x{strip_shape[1]}")
+    return m.get("hbm_bytes_per_launch") if m else None
 
 
 def _oracle_path(sc, window_cells):
