@@ -579,16 +579,9 @@ __global__ __launch_bounds__(kBlock) void k_traj_value_grad(const float* __restr
                                                             const int* __restrict__ slice,
                                                             const float* __restrict__ gf, float* __restrict__ f,
                                                             float* __restrict__ gwp, Sink s) {
-    // Wavefronts walk-major: the profiles of one trajectory are neighbours,
-    // and neighbouring workgroups share an XCD (workgroups go to the 8 XCDs
-    // in turn; the grid is a multiple of 8), so the profiles that sample the
-    // same cells read them through one L2.
-    const int per_xcd = gridDim.x / 8;
-    const long long lb = (long long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const long long lw = lb * (kBlock / 64) + threadIdx.x / 64;
-    if (lw >= (long long)n_profiles * a.T) return;
-    const int prof = __builtin_amdgcn_readfirstlane((int)(lw % n_profiles));
-    const long long wave = (long long)prof * a.T + lw / n_profiles;   // output slot (profile, trajectory)
+    const long long wave = (long long)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    if (wave >= (long long)n_profiles * a.T) return;
+    const int prof = __builtin_amdgcn_readfirstlane((int)(wave / a.T));
     const EvalParams& p = robots[prof];
     const int lane = threadIdx.x & 63;
     const float g = gf ? gf[wave] : 0.0f;
@@ -796,7 +789,7 @@ pct_status launch_traj_value_grad(const float* ground, const float* ceil, const 
     }
     const long long waves = (long long)n_profiles * T;
     if (waves == 0) return PCT_OK;
-    const unsigned blocks = (unsigned)(((waves + kBlock / 64 - 1) / (kBlock / 64) + 7) / 8 * 8);
+    const unsigned blocks = (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
     hipLaunchKernelGGL(k_traj_value_grad, dim3(blocks), dim3(kBlock), 0, s, ground, ceil, d_robots, a, n_profiles, wp,
                        slice, gf, f, gf ? gwp : nullptr, sk);
     PCT_LAUNCH_CHECK();
